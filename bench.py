@@ -1,0 +1,238 @@
+"""Benchmark: compressed (DIT) SpMV vs plain ELL on MI355X, plus CG time to 1e-10.
+
+Workload (default): the HPCG 27-point stencil matrix on a 104^3 grid
+(n = 1,124,864, nnz = 29,791,000, diagonal 26, neighbours -1), x ~ U[-1, 1]
+(seed 0).  One step = one y = A x over the DIT-compressed matrix (pattern ID +
+terminal indices per row, value table {-1, 26}).  Inputs are resident in HBM
+before the timed region.  The same matrix as FP64 ELL is timed beside it, and
+(unless --no-cg) unpreconditioned CG to 1e-10 on the 192^3 grid with b = A*1,
+FP64 and mixed precision.
+
+Prints one JSON line (see the repository's design notes for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "dit_spmv_stencil104_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1612_00530_amd", "csrc", "spmv.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(n_launch_bytes_alg):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it is current."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    txt = open(PROFILE_PMC).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    f = re.search(r"fetch_bytes_per_launch:\s*([\d.eE+]+)", txt)
+    w = re.search(r"write_bytes_per_launch:\s*([\d.eE+]+)", txt)
+    if not f or not w:
+        return None
+    return float(f.group(1)) + float(w.group(1))
+
+
+def time_launches(fn, reps, torch):
+    """Mean duration (ms) of one launch, from a HIP event pair around each launch on its stream."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(t.mean()), float(np.median(t)), float(t.min())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--grid", type=int, default=104)
+    ap.add_argument("--cg-grid", type=int, default=192)
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1612_00530_amd as P
+    from synthetic import stencil27, uniform_vector
+
+    P.load()  # fails loudly when the HIP library is missing
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    g = args.grid
+    log(f"[bench] generating 27-point stencil {g}^3")
+    A = stencil27(g, g, g)
+    n, nnz = A.n_rows, A.nnz
+    rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+    x = torch.from_numpy(uniform_vector(n, seed=0)).to(dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+
+    log("[bench] compressing (DIT, ELL)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    D = P.compress(rp, col, val, n_cols=n, fmt="DIT")
+    torch.cuda.synchronize()
+    t_compress = time.perf_counter() - t0
+    E = P.compress(rp, col, val, n_cols=n, fmt="ELL")
+    del rp, col, val
+    tuned = None
+    if not args.no_tune:
+        tuned = D.tune(torch.float64)
+        log(f"[bench] tuned DIT: {tuned}")
+    dinf, einf = D.info(), E.info()
+
+    # timed region: K back-to-back compressed SpMVs
+    for _ in range(args.warmup):
+        D.spmv(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        D.spmv(x, y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    gflops = 2.0 * nnz / (ms_per_step * 1e-3) / 1e9
+    log(f"[bench] DIT: {ms_per_step * 1000:.2f} us/step, {gflops:.1f} Gflops")
+
+    # dominant kernel: mean launch duration from HIP events on the launch stream
+    k_mean, k_med, k_min = time_launches(lambda: D.spmv(x, y), args.steps, torch)
+    alg_dit = dinf["bytes_stream"] + 8 * n + 8 * n
+    achieved = alg_dit / (k_mean * 1e-3) / 1e9
+    traffic = traffic_from_profile(alg_dit)
+
+    # ELL baseline, same matrix and vectors
+    for _ in range(args.warmup):
+        E.spmv(x, y)
+    e_mean, e_med, e_min = time_launches(lambda: E.spmv(x, y), max(20, args.steps // 2), torch)
+    alg_ell = einf["bytes_stream"] + 8 * n + 8 * n
+    ell_gflops = 2.0 * nnz / (e_mean * 1e-3) / 1e9
+    log(f"[bench] ELL: {e_mean * 1000:.2f} us/launch, {ell_gflops:.1f} Gflops, "
+        f"{alg_ell / (e_mean * 1e-3) / 1e9:.0f} GB/s")
+
+    # parity spot check of this very launch configuration against the oracle
+    out = {}
+    if not args.no_cpu:
+        import oracle
+
+        yref = oracle.spmv(A, x.cpu().numpy())
+        yg = D.spmv(x, y).cpu().numpy()
+        rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+        scale = np.bincount(rows, weights=np.abs(A.val) * np.abs(x.cpu().numpy()[A.col]), minlength=n)
+        out["parity_max_rel_err"] = float((np.abs(yg - yref) / scale).max())
+        # CPU baseline: the oracle as it stands, timed on the host cores
+        reps, t_cpu = 0, 0.0
+        xh = x.cpu().numpy()
+        t0 = time.perf_counter()
+        while reps < 3 or (time.perf_counter() - t0) < args.cpu_seconds:
+            oracle.spmv(A, xh)
+            reps += 1
+        t_cpu = (time.perf_counter() - t0) / reps
+        out["cpu_baseline"] = {"value": 2.0 * nnz / t_cpu / 1e9, "unit": "Gflops", "cores": oracle.threads(),
+                               "kind": "oracle",
+                               "sample": f"{reps} full CSR SpMVs of the {g}^3 stencil matrix (FP64, OpenMP rows)"}
+        log(f"[bench] CPU oracle: {out['cpu_baseline']['value']:.2f} Gflops on {oracle.threads()} threads")
+
+    cg = None
+    if not args.no_cg:
+        cg = run_cg(args.cg_grid, P, torch, dev)
+
+    res = {
+        "metric": "SpMV Gflops + effective HBM GB/s, compressed vs plain ELL; CG time to 1e-10",
+        "value": round(gflops, 2),
+        "unit": "Gflops",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"27-point stencil {g}^3 (HPCG matrix), DIT-compressed FP64 SpMV",
+                   "grid": [g, g, g], "n": n, "nnz": nnz, "format": "DIT",
+                   "rows_per_block": dinf["rows_per_block"], "lds_windows": dinf["lds_windows"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_dit_lds", "algorithmic_bytes_per_launch": alg_dit,
+                     "launch_us_mean": round(k_mean * 1000, 3), "launch_us_median": round(k_med * 1000, 3)},
+        "cpu_baseline": out.get("cpu_baseline"),
+        "effective_GBps_actual": round(alg_dit / (ms_per_step * 1e-3) / 1e9, 1),
+        "effective_GBps_equiv_uncompressed": round(alg_ell / (ms_per_step * 1e-3) / 1e9, 1),
+        "ell": {"gflops": round(ell_gflops, 2), "launch_us_mean": round(e_mean * 1000, 3),
+                "GBps": round(alg_ell / (e_mean * 1e-3) / 1e9, 1), "bytes_per_launch": alg_ell,
+                "hbm_frac": round(alg_ell / (e_mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "speedup_vs_ell": round(gflops / ell_gflops, 3),
+        "compress_seconds": round(t_compress, 3),
+        "bytes_per_row": {"DIT": round(dinf["bytes_stream"] / n, 3), "ELL": round(einf["bytes_stream"] / n, 3),
+                          "DIT_paper_widths": round(dinf["bytes_paper"] / n, 3)},
+        "parity_max_rel_err": out.get("parity_max_rel_err"),
+        "tuned": tuned,
+        "cg": cg,
+        "paper_context_gflops_per_chip": {"uncompressed": 11.6, "compressed": 32.4, "hardware": "PEZY-SC"},
+    }
+    print(json.dumps(res), flush=True)
+
+
+def run_cg(g, P, torch, dev):
+    """CG to 1e-10 on the g^3 stencil with b = A*1: FP64 DIT, mixed-precision DIT, FP64 ELL."""
+    from synthetic import stencil27
+
+    log(f"[bench] CG: generating {g}^3")
+    A = stencil27(g, g, g)
+    rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+    D = P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT")
+    E = P.compress(rp, col, val, n_cols=A.n_cols, fmt="ELL")
+    del rp, col, val
+    ones = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
+    b = D.spmv(ones)
+    res = {"grid": [g, g, g], "n": A.n_rows, "nnz": A.nnz, "rtol": 1e-10}
+    for name, M, mode in (("fp64_dit", D, 0), ("mixed_dit", D, 1), ("fp64_ell", E, 0)):
+        P.cg_solve(M, b, mode=mode, max_iter=20)  # warm-up of the code path
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, xs, stats = P.cg_solve(M, b, mode=mode, max_iter=5000)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        err = float((xs[0] - 1.0).abs().max().item())
+        res[name] = {"status": st, "seconds": round(t, 5), "iters": stats[0]["iters"],
+                     "outer_iters": stats[0]["outer_iters"], "relres_true_fp64": stats[0]["relres_true"],
+                     "max_abs_err_vs_ones": err}
+        log(f"[bench] CG {name}: {t * 1000:.2f} ms, {stats[0]['iters']} iters, relres {stats[0]['relres_true']:.2e}")
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * spmvc.h -- compressed sparse matrix-vector product and conjugate gradients
+ * on AMD Instinct MI355X (gfx950).  C ABI of libspmvc.so.
+ *
+ * The operation is y = A x (Eq. 1, Section I) over a matrix that is stored
+ * losslessly compressed with the schemes of Section V:
+ *
+ *   SPMVC_FMT_ELL  uncompressed ELL, one 4-byte column index and one 8-byte
+ *                  value per element (the baseline of Section IV-B and the
+ *                  "Original" row of Table II);
+ *   SPMVC_FMT_DT   "Data Table": the value table V (unique values, ascending),
+ *                  per row the column list S_i sorted by value and the
+ *                  terminal indices T_i (Section V, Fig. 1);
+ *   SPMVC_FMT_DIT  "Data+Index Table": columns replaced by displacements from
+ *                  the diagonal, each row's displacement sequence registered in
+ *                  a pattern table; a row stores only its pattern ID and T_i
+ *                  (Section V, index-compression paragraph and sample code).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless the comment says "host".
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is ordered
+ *     on that stream.  spmv / spmv_block are asynchronous; spmv_compress,
+ *     spmv_decompress and cg_solve synchronise `stream` before returning.
+ *   - Every call returns an spmvc_status; no C++ exception crosses the ABI.
+ *     After a failure spmvc_last_error() gives a thread-local message.
+ *   - Indices: rows and columns are 0-based, < 2^31; row_ptr is int64.
+ *   - The library never keeps a caller pointer beyond the call.
+ */
+#ifndef SPMVC_H
+#define SPMVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPMVC_OK = 0,
+    SPMVC_EINVAL = -1,       /* bad argument (null pointer, size, aliasing, option)    */
+    SPMVC_ENOMEM = -2,       /* device allocation failed                               */
+    SPMVC_EUNSORTED = -3,    /* CSR columns not strictly ascending within a row        */
+    SPMVC_ERANGE = -4,       /* row_ptr not monotone / column index out of range       */
+    SPMVC_EHIP = -5,         /* HIP runtime error                                      */
+    SPMVC_ENOTSPD = -6,      /* CG breakdown: p.Ap <= 0 or not finite                  */
+    SPMVC_ENOCONV = -7,      /* CG reached max_iter without meeting the tolerance      */
+    SPMVC_EUNSUPPORTED = -8  /* valid request this build does not handle (message says) */
+} spmvc_status;
+
+typedef enum { SPMVC_F64 = 0, SPMVC_F32 = 1 } spmvc_dtype;
+
+typedef enum {
+    SPMVC_FMT_ELL = 0,
+    SPMVC_FMT_DT = 1,
+    SPMVC_FMT_DIT = 2
+} spmvc_format;
+
+typedef struct spmvc_matrix_s *spmvc_matrix; /* opaque, owned by the library */
+
+/* Options of spmv_compress (host struct; NULL = defaults shown). */
+typedef struct {
+    int32_t fmt;              /* spmvc_format, default SPMVC_FMT_DIT                      */
+    int32_t k_max;            /* value-table capacity, 0..15, default 15                  */
+    int32_t p_max;            /* pattern-table capacity, 1..2^31-2, default 65535         */
+    int32_t min_pattern_rows; /* a pattern used by fewer rows is an escape, default 2     */
+    int32_t f32_shadow;       /* also keep FP32 copies of V / raw values (FP32 spmv), def 1 */
+} spmvc_compress_opts;
+
+/*
+ * Compress a CSR matrix.  Section V: "first the entire matrix is scanned and
+ * all unique values ... are listed and sorted in the ascending order" (V), the
+ * non-zeros of each row are sorted by value (S_i, ties by column), the run end
+ * of every value is recorded (T_i), and for DIT the displacements col - row
+ * are registered in a pattern table.
+ *
+ * Dictionary: a value enters V when 8*count > n_rows (it pays for its T byte
+ * per row); of those the k_max most frequent are kept; V is sorted by IEEE-754
+ * totalOrder on the bit pattern (-0.0 and +0.0 distinct, NaN payloads kept).
+ * Entries whose value is not in V are "raw": they follow the coded entries,
+ * by column, and keep their FP64 value.  T_i stores exclusive run ends.
+ * Pattern IDs follow first occurrence (lowest row).  Escape rows -- rows longer
+ * than 255, and for DIT rows whose pattern is used by fewer than
+ * min_pattern_rows rows or falls outside the p_max most frequent -- are kept
+ * as plain CSR.  The encoding is deterministic.
+ *
+ * row_ptr [n_rows+1] int64, col_idx [nnz] int32, vals [nnz] FP64: device
+ * arrays owned by the caller and read only during this call.  The CSR is
+ * validated on the device: row_ptr[0] == 0, monotone, row_ptr[n_rows] == nnz
+ * (else SPMVC_ERANGE); 0 <= col < n_cols (SPMVC_ERANGE); strictly ascending
+ * columns per row (SPMVC_EUNSORTED).  On success *out receives a handle that
+ * must be released with spmv_free.  n_rows == 0 or nnz == 0 is allowed.
+ */
+spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                           const int64_t *row_ptr, const int32_t *col_idx, const double *vals,
+                           const spmvc_compress_opts *opts, void *stream, spmvc_matrix *out);
+
+/*
+ * y = A x (Eq. 1).  x: [n_cols], y: [n_rows], both of dtype `dt` (FP64 or
+ * FP32), device, caller-owned; x and y must not overlap (SPMVC_EINVAL).
+ * FP64: products and sums in FP64 (fused multiply-add allowed).  FP32: the
+ * FP32 copies of V / raw values, FP32 x, FP32 accumulation.  Asynchronous.
+ */
+spmvc_status spmv(spmvc_matrix A, int32_t dt, const void *x, void *y, void *stream);
+
+/*
+ * Y = A X for nrhs right-hand sides, 1 <= nrhs <= 16.  Row-interleaved:
+ * element (j, r) of X is X[j*ldx + r] (ldx >= nrhs), element (i, r) of Y is
+ * Y[i*ldy + r] (ldy >= nrhs).  Each decoded matrix entry is applied to all
+ * nrhs vectors.  Same dtype / aliasing rules as spmv.  Asynchronous.
+ */
+spmvc_status spmv_block(spmvc_matrix A, int32_t dt, int32_t nrhs, const void *X, int64_t ldx,
+                        void *Y, int64_t ldy, void *stream);
+
+/* Options of cg_solve (host struct; NULL = defaults shown). */
+typedef struct {
+    double rtol;         /* stop when ||r|| <= rtol * ||b||, default 1e-10                 */
+    int32_t max_iter;    /* SpMV cap per (system, rhs) [FP64 mode; inner total in MIXED], 10000 */
+    int32_t mode;        /* 0 = FP64 CG, 1 = mixed precision with iterative refinement     */
+    double inner_rtol;   /* MIXED: inner FP32 solve tolerance relative to ||r||, 1e-5      */
+    int32_t max_outer;   /* MIXED: refinement steps cap, default 20                        */
+    int32_t check_every; /* iterations between host convergence checks, default 16         */
+} spmvc_cg_opts;
+
+/* Per (system, rhs) result (host struct). */
+typedef struct {
+    int32_t iters;           /* SpMVs inside the CG loop (MIXED: total FP32 inner iterations) */
+    int32_t outer_iters;     /* MIXED: refinement steps; FP64 mode: 0                      */
+    int32_t status;          /* spmvc_status of this solve                                 */
+    int32_t pad_;
+    double relres_true;      /* ||b - A x|| / ||b|| recomputed in FP64 at exit             */
+    double relres_recursive; /* last recursively updated residual norm / ||b||             */
+} spmvc_cg_stat;
+
+/*
+ * Solve A_s x = b for n_sys independent systems, each with nrhs right-hand
+ * sides, by unpreconditioned conjugate gradients from x0 = 0 (the CG part of
+ * Table I: DotProduct, Waxpby, SpMV).  A: host array [n_sys] of handles (square
+ * matrices).  b, x: host arrays [n_sys] of device pointers to row-interleaved
+ * [n_rows_s][nrhs] FP64 blocks (for nrhs == 1, plain vectors); x is
+ * overwritten with the solution (the last iterate on failure).  stat: host
+ * array [n_sys*nrhs], index s*nrhs + r.  Each (system, rhs) pair stops at its
+ * own tolerance.  Returns SPMVC_OK when every pair converged, else the first
+ * failing pair's status (SPMVC_ENOTSPD, SPMVC_ENOCONV).  Blocking.
+ * mode 1 (MIXED): outer FP64 residual r = b - A x, inner FP32 CG on A d = r
+ * with FP64 dot products, FP64 update x += d; requires nrhs == 1, n_sys == 1.
+ */
+spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs,
+                      const double *const *b, double *const *x, const spmvc_cg_opts *opts,
+                      spmvc_cg_stat *stat, void *stream);
+
+/*
+ * Rebuild the CSR matrix (columns ascending per row, values bit-identical)
+ * into caller-owned device arrays row_ptr [n_rows+1], col_idx [nnz],
+ * vals [nnz].  Blocking.  The lossless round trip of Section V.
+ */
+spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx, double *vals,
+                             void *stream);
+
+/* Description of a compressed matrix (host struct filled by spmv_info). */
+typedef struct {
+    int32_t fmt;           /* spmvc_format                                                */
+    int32_t K;             /* value-table entries                                         */
+    int32_t P;             /* pattern-table entries (DIT)                                 */
+    int32_t id_bytes;      /* width of a pattern ID (DIT): 1, 2 or 4                      */
+    int32_t width;         /* ELL/DT slots per row, DIT longest pattern                   */
+    int32_t max_raw;       /* most raw entries in one row                                 */
+    int64_t n_rows, n_cols, nnz;
+    int64_t n_escape_rows, n_escape_nnz, n_raw;
+    int64_t bytes_stream;  /* bytes one FP64 spmv must read for the matrix (all arrays)   */
+    int64_t bytes_ell;     /* the same matrix as FP64 ELL: 12 bytes per slot              */
+    int64_t bytes_paper;   /* at the paper's widths: ELL 12/slot, DT 4*(len+K), DIT 4*(1+K) per row */
+    int32_t lds_windows;   /* x windows staged in LDS by the DIT kernel (0 = direct gather) */
+    int32_t rows_per_block;
+    double V[15];          /* the value table (first K entries)                           */
+} spmvc_info;
+
+spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info /* host */);
+
+/*
+ * Internal arrays, for tests and tools: device pointer and byte size of one
+ * array of the encoding (which: see spmvc_array_id).  The pointer stays valid
+ * until spmv_free.  Layouts: ELL_VAL f64 / ELL_COL i32 / DT_S i32 are
+ * [width][n_pad] column-major (n_pad = n_rows rounded up to 64, padding
+ * column -1); IDS [n_pad] of id_bytes each (all-ones = escape row); T u8
+ * [K][n_pad]; PAT_OFF i32 [P][width] displacements, PAT_LEN u8 [P]; RAW f64 in
+ * slices of 64 rows, slice s at RAW_SLICE[s] (int64, elements), raw entry k
+ * of row 64s+l at RAW[RAW_SLICE[s] + 64k + l]; ESC_ROWS i64, ESC_PTR i64
+ * [n_esc+1], ESC_COL i32, ESC_VAL f64.
+ */
+typedef enum {
+    SPMVC_ARR_ELL_VAL = 0, SPMVC_ARR_ELL_COL = 1, SPMVC_ARR_DT_S = 2, SPMVC_ARR_IDS = 3,
+    SPMVC_ARR_T = 4, SPMVC_ARR_PAT_OFF = 5, SPMVC_ARR_PAT_LEN = 6, SPMVC_ARR_RAW = 7,
+    SPMVC_ARR_RAW_SLICE = 8, SPMVC_ARR_ESC_ROWS = 9, SPMVC_ARR_ESC_PTR = 10,
+    SPMVC_ARR_ESC_COL = 11, SPMVC_ARR_ESC_VAL = 12, SPMVC_ARR_V = 13
+} spmvc_array_id;
+
+spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, const void **dev_ptr, int64_t *bytes);
+
+/*
+ * Kernel configuration of a handle's spmv (rows per block, LDS staging).
+ * rows_per_block: 256..4096, a multiple of 256 (0 = keep).  lds: 1 = stage x
+ * windows in LDS when they fit, 0 = gather x directly, -1 = keep.  Used by the
+ * autotuner; any valid setting gives the same results.
+ */
+spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds);
+
+/*
+ * Autotuner: times each candidate kernel configuration of `A` for dtype `dt`
+ * and `nrhs` (spmv when nrhs == 1, else spmv_block) on scratch vectors, keeps
+ * the fastest in the handle and reports it (host outputs, may be NULL).
+ * Results are cached per (arch, format, n_rows, P, K, dtype, nrhs) in the JSON
+ * file named by $SPMVC_TUNE_CACHE when set.  Blocking.
+ */
+spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void *stream,
+                       int32_t *best_rows_per_block, int32_t *best_lds, double *best_us);
+
+void spmv_free(spmvc_matrix A);
+
+const char *spmvc_status_string(int32_t status);
+const char *spmvc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMVC_H */

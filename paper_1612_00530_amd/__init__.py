@@ -1,0 +1,283 @@
+"""Python binding of libspmvc: compressed SpMV and CG on MI355X (gfx950).
+
+Argument marshalling only: every step of compression, SpMV and CG runs in the
+HIP kernels of ``libspmvc.so`` behind the C ABI declared in
+``include/spmvc.h``.  Torch tensors supply device memory and the current HIP
+stream.  The library must be built (``paper_1612_00530_amd.build.build()``);
+there is no CPU fallback, and importing this module without the library
+raises at first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "load", "compress", "Matrix", "cg_solve", "SpmvcError",
+    "FMT_ELL", "FMT_DT", "FMT_DIT", "F64", "F32",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspmvc.so")
+
+FMT_ELL, FMT_DT, FMT_DIT = 0, 1, 2
+F64, F32 = 0, 1
+_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT}
+
+ARR = {
+    "ELL_VAL": 0, "ELL_COL": 1, "DT_S": 2, "IDS": 3, "T": 4, "PAT_OFF": 5, "PAT_LEN": 6,
+    "RAW": 7, "RAW_SLICE": 8, "ESC_ROWS": 9, "ESC_PTR": 10, "ESC_COL": 11, "ESC_VAL": 12, "V": 13,
+}
+
+EXPORTED = [
+    "spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
+    "spmv_get_array", "spmv_set_config", "spmv_tune", "spmv_free", "spmvc_status_string",
+    "spmvc_last_error",
+]
+
+
+class SpmvcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"spmvc status {status}: {msg}")
+        self.status = status
+
+
+class CompressOpts(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("k_max", ctypes.c_int32), ("p_max", ctypes.c_int32),
+                ("min_pattern_rows", ctypes.c_int32), ("f32_shadow", ctypes.c_int32)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class CgStat(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("relres_true", ctypes.c_double),
+                ("relres_recursive", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("K", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("id_bytes", ctypes.c_int32), ("width", ctypes.c_int32), ("max_raw", ctypes.c_int32),
+                ("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n_escape_rows", ctypes.c_int64), ("n_escape_nnz", ctypes.c_int64),
+                ("n_raw", ctypes.c_int64), ("bytes_stream", ctypes.c_int64),
+                ("bytes_ell", ctypes.c_int64), ("bytes_paper", ctypes.c_int64),
+                ("lds_windows", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
+                ("V", ctypes.c_double * 15)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libspmvc.so (raises ImportError if it has not been built)."""
+    global _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1612_00530_amd.build.build()")
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    lib = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.spmv_compress.argtypes = [i64, i64, i64, P, P, P, ctypes.POINTER(CompressOpts), P, ctypes.POINTER(P)]
+    lib.spmv.argtypes = [P, i32, P, P, P]
+    lib.spmv_block.argtypes = [P, i32, i32, P, i64, P, i64, P]
+    lib.cg_solve.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(P), ctypes.POINTER(P),
+                             ctypes.POINTER(CgOpts), ctypes.POINTER(CgStat), P]
+    lib.spmv_decompress.argtypes = [P, P, P, P, P]
+    lib.spmv_info.argtypes = [P, ctypes.POINTER(Info)]
+    lib.spmv_get_array.argtypes = [P, i32, ctypes.POINTER(P), ctypes.POINTER(i64)]
+    lib.spmv_set_config.argtypes = [P, i32, i32]
+    lib.spmv_tune.argtypes = [P, i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                              ctypes.POINTER(ctypes.c_double)]
+    lib.spmv_free.argtypes = [P]
+    lib.spmv_free.restype = None
+    lib.spmvc_status_string.argtypes = [i32]
+    lib.spmvc_status_string.restype = ctypes.c_char_p
+    lib.spmvc_last_error.restype = ctypes.c_char_p
+    for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
+                 "spmv_get_array", "spmv_set_config", "spmv_tune"]:
+        getattr(lib, name).restype = ctypes.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        msg = load().spmvc_last_error().decode() or load().spmvc_status_string(st).decode()
+        raise SpmvcError(st, msg)
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+class Matrix:
+    """A compressed matrix owned by libspmvc (released by ``free`` or garbage collection)."""
+
+    def __init__(self, handle, n_rows, n_cols, nnz):
+        self._h = handle
+        self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, nnz
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h:
+            load().spmv_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().spmv_info(self._h, ctypes.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in Info._fields_ if f != "V"}
+        d["V"] = [inf.V[i] for i in range(inf.K)]
+        d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT"}[inf.fmt]
+        return d
+
+    def spmv(self, x, y=None, dtype=None, stream=None):
+        """y = A x on the GPU (x, y: float64 or float32 CUDA tensors)."""
+        import torch
+
+        dtype = dtype or x.dtype
+        dt = F64 if dtype == torch.float64 else F32
+        if x.shape != (self.n_cols,):
+            raise ValueError("x has the wrong shape")
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=dtype, device=x.device)
+        elif y.shape != (self.n_rows,):
+            raise ValueError("y has the wrong shape")
+        _check(load().spmv(self._h, dt, _dev(x, dtype, "x"), _dev(y, dtype, "y"), _stream(stream)))
+        return y
+
+    def spmv_block(self, X, Y=None, stream=None):
+        """Y = A X for row-interleaved X of shape (n_cols, nrhs)."""
+        import torch
+
+        dt = F64 if X.dtype == torch.float64 else F32
+        if X.dim() != 2 or X.shape[0] != self.n_cols:
+            raise ValueError("X must be (n_cols, nrhs)")
+        nrhs = X.shape[1]
+        if Y is None:
+            Y = torch.empty((self.n_rows, nrhs), dtype=X.dtype, device=X.device)
+        _check(load().spmv_block(self._h, dt, nrhs, _dev(X, X.dtype, "X"), X.stride(0),
+                                 _dev(Y, X.dtype, "Y"), Y.stride(0), _stream(stream)))
+        return Y
+
+    def decompress(self):
+        import torch
+
+        dev = torch.device("cuda")
+        rp = torch.empty(self.n_rows + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=dev)
+        _check(load().spmv_decompress(self._h, _dev(rp, torch.int64, "rp"), ctypes.c_void_p(col.data_ptr()),
+                                      ctypes.c_void_p(val.data_ptr()), _stream()))
+        return rp, col[: self.nnz], val[: self.nnz]
+
+    def array(self, name: str):
+        """Copy of an internal array as a uint8 CUDA tensor (layout: see include/spmvc.h)."""
+        import torch
+
+        ptr = ctypes.c_void_p()
+        nb = ctypes.c_int64()
+        _check(load().spmv_get_array(self._h, ARR[name], ctypes.byref(ptr), ctypes.byref(nb)))
+        out = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        if nb.value:
+            _hip_copy(out.data_ptr(), ptr.value, nb.value)
+        return out
+
+    def set_config(self, rows_per_block=0, lds=-1):
+        _check(load().spmv_set_config(self._h, rows_per_block, lds))
+
+    def tune(self, dtype=None, nrhs=1):
+        import torch
+
+        dt = F32 if dtype == torch.float32 else F64
+        rows, lds, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(load().spmv_tune(self._h, dt, nrhs, _stream(), ctypes.byref(rows), ctypes.byref(lds),
+                                ctypes.byref(us)))
+        return {"rows_per_block": rows.value, "lds": lds.value, "us": us.value}
+
+
+_hip = None
+
+
+def _hip_copy(dst: int, src: int, nbytes: int):
+    """Device-to-device copy through the HIP runtime (synchronous)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipDeviceSynchronize.restype = ctypes.c_int
+    _hip.hipDeviceSynchronize()
+    st = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
+    if st != 0:
+        raise RuntimeError(f"hipMemcpy failed: {st}")
+
+
+def compress(row_ptr, col, val, n_cols=None, fmt="DIT", k_max=15, p_max=65535, min_pattern_rows=2,
+             f32_shadow=True, stream=None) -> Matrix:
+    """Compress a CSR matrix held in CUDA tensors (int64 row_ptr, int32 col, float64 val)."""
+    import torch
+
+    n_rows = row_ptr.numel() - 1
+    nnz = col.numel()
+    if n_cols is None:
+        raise ValueError("n_cols is required")
+    o = CompressOpts(_FMT_NAMES[fmt] if isinstance(fmt, str) else int(fmt), k_max, p_max, min_pattern_rows,
+                     1 if f32_shadow else 0)
+    h = ctypes.c_void_p()
+    _check(load().spmv_compress(n_rows, int(n_cols), nnz, _dev(row_ptr, torch.int64, "row_ptr"),
+                                _dev(col, torch.int32, "col"), _dev(val, torch.float64, "val"),
+                                ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+    return Matrix(h, n_rows, int(n_cols), nnz)
+
+
+def cg_solve(mats, bs, xs=None, rtol=1e-10, max_iter=10000, mode=0, inner_rtol=1e-5, max_outer=20,
+             check_every=16, nrhs=1, stream=None):
+    """CG on one or more systems; bs/xs: lists of CUDA float64 tensors (n,) or (n, nrhs)."""
+    import torch
+
+    if isinstance(mats, Matrix):
+        mats, bs = [mats], [bs]
+        xs = [xs] if xs is not None else None
+    n_sys = len(mats)
+    if xs is None:
+        xs = [torch.empty_like(b) for b in bs]
+    H = (ctypes.c_void_p * n_sys)(*[m.handle for m in mats])
+    B = (ctypes.c_void_p * n_sys)(*[_dev(b, torch.float64, "b").value for b in bs])
+    X = (ctypes.c_void_p * n_sys)(*[_dev(x, torch.float64, "x").value for x in xs])
+    o = CgOpts(rtol, max_iter, mode, inner_rtol, max_outer, check_every)
+    stats = (CgStat * (n_sys * nrhs))()
+    st = load().cg_solve(H, n_sys, nrhs, B, X, ctypes.byref(o), stats, _stream(stream))
+    out = [{"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status,
+            "relres_true": s.relres_true, "relres_recursive": s.relres_recursive} for s in stats]
+    return st, xs, out

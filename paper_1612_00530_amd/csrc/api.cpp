@@ -1,0 +1,266 @@
+// The C ABI of libspmvc: argument checks, error reporting, handle lifetime.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+
+#include "internal.h"
+
+namespace spmvc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+spmvc_status fail(spmvc_status st, const std::string &msg) {
+    set_error(msg);
+    return st;
+}
+
+namespace {
+
+template <class F> spmvc_status guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        return fail(e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(SPMVC_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SPMVC_EHIP, e.what());
+    } catch (...) {
+        return fail(SPMVC_EHIP, "unknown error");
+    }
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+bool f32_ready(const spmvc_matrix_s *M) {
+    return M->f32_shadow || (M->raw_elems == 0 && M->n_esc_nnz == 0);
+}
+
+void default_plan(spmvc_matrix_s *M) {
+    if (M->fmt != SPMVC_FMT_DIT) return;
+    for (int rows : {M->rows_per_block, 1024, 512, 256}) {
+        build_lds_plan(M, rows);
+        if (M->plan.n_win > 0) {
+            M->rows_per_block = rows;
+            return;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace spmvc
+
+using namespace spmvc;
+
+extern "C" {
+
+const char *spmvc_status_string(int32_t st) {
+    switch (st) {
+    case SPMVC_OK: return "ok";
+    case SPMVC_EINVAL: return "invalid argument";
+    case SPMVC_ENOMEM: return "out of device memory";
+    case SPMVC_EUNSORTED: return "CSR columns not strictly ascending within a row";
+    case SPMVC_ERANGE: return "CSR row pointer or column index out of range";
+    case SPMVC_EHIP: return "HIP runtime error";
+    case SPMVC_ENOTSPD: return "CG breakdown (matrix not SPD)";
+    case SPMVC_ENOCONV: return "CG did not converge";
+    case SPMVC_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *spmvc_last_error(void) { return g_last_error.c_str(); }
+
+spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col_idx, const double *vals, const spmvc_compress_opts *opts,
+                           void *stream, spmvc_matrix *out) {
+    return guarded([&]() -> spmvc_status {
+        if (!out) return fail(SPMVC_EINVAL, "out is null");
+        *out = nullptr;
+        if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(SPMVC_EINVAL, "negative size");
+        if (n_rows >= (1ll << 31) || n_cols >= (1ll << 31) || nnz >= (1ll << 31))
+            return fail(SPMVC_EINVAL, "n_rows, n_cols and nnz must be < 2^31");
+        if (!row_ptr) return fail(SPMVC_EINVAL, "row_ptr is null");
+        if (nnz > 0 && (!col_idx || !vals)) return fail(SPMVC_EINVAL, "col_idx / vals is null");
+        if (nnz > 0 && n_cols == 0) return fail(SPMVC_ERANGE, "entries in a matrix with no columns");
+        spmvc_compress_opts o{SPMVC_FMT_DIT, 15, 65535, 2, 1};
+        if (opts) o = *opts;
+        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_DIT) return fail(SPMVC_EINVAL, "unknown format");
+        if (o.k_max < 0 || o.k_max > kMaxK) return fail(SPMVC_EINVAL, "k_max must be in 0..15");
+        if (o.p_max < 1 || o.p_max > 0x7FFFFFFE) return fail(SPMVC_EINVAL, "p_max must be in 1..2^31-2");
+        if (o.min_pattern_rows < 1) return fail(SPMVC_EINVAL, "min_pattern_rows must be >= 1");
+        auto *M = new spmvc_matrix_s();
+        M->n_rows = n_rows;
+        M->n_cols = n_cols;
+        M->nnz = nnz;
+        try {
+            compress(M, row_ptr, col_idx, vals, o, static_cast<hipStream_t>(stream));
+            default_plan(M);
+        } catch (...) {
+            delete M;
+            throw;
+        }
+        *out = M;
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv(spmvc_matrix A, int32_t dt, const void *x, void *y, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
+        if (dt != SPMVC_F64 && dt != SPMVC_F32) return fail(SPMVC_EINVAL, "dtype must be F64 or F32");
+        if ((A->n_cols > 0 && !x) || (A->n_rows > 0 && !y)) return fail(SPMVC_EINVAL, "x / y is null");
+        const size_t es = dt == SPMVC_F64 ? 8 : 4;
+        if (overlap(x, es * A->n_cols, y, es * A->n_rows)) return fail(SPMVC_EINVAL, "x and y overlap");
+        if (dt == SPMVC_F32 && !f32_ready(A)) return fail(SPMVC_EUNSUPPORTED, "FP32 spmv needs f32_shadow at compress time");
+        launch_spmv(A, dt, x, y, static_cast<hipStream_t>(stream));
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_block(spmvc_matrix A, int32_t dt, int32_t nrhs, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                        void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
+        if (dt != SPMVC_F64 && dt != SPMVC_F32) return fail(SPMVC_EINVAL, "dtype must be F64 or F32");
+        if (nrhs < 1 || nrhs > 16) return fail(SPMVC_EINVAL, "nrhs must be in 1..16");
+        if (ldx < nrhs || ldy < nrhs) return fail(SPMVC_EINVAL, "ldx and ldy must be >= nrhs");
+        if ((A->n_cols > 0 && !X) || (A->n_rows > 0 && !Y)) return fail(SPMVC_EINVAL, "X / Y is null");
+        const size_t es = dt == SPMVC_F64 ? 8 : 4;
+        if (overlap(X, es * A->n_cols * ldx, Y, es * A->n_rows * ldy)) return fail(SPMVC_EINVAL, "X and Y overlap");
+        if (dt == SPMVC_F32 && !f32_ready(A)) return fail(SPMVC_EUNSUPPORTED, "FP32 spmv needs f32_shadow at compress time");
+        launch_spmv_block(A, dt, nrhs, X, ldx, Y, ldy, static_cast<hipStream_t>(stream));
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs, const double *const *b, double *const *x,
+                      const spmvc_cg_opts *opts, spmvc_cg_stat *stat, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !b || !x || !stat) return fail(SPMVC_EINVAL, "null argument");
+        if (n_sys < 1) return fail(SPMVC_EINVAL, "n_sys must be >= 1");
+        if (nrhs < 1 || nrhs > 16) return fail(SPMVC_EINVAL, "nrhs must be in 1..16");
+        spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16};
+        if (opts) o = *opts;
+        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || (o.mode != 0 && o.mode != 1))
+            return fail(SPMVC_EINVAL, "invalid cg options");
+        if (o.mode == 1 && (n_sys != 1 || nrhs != 1))
+            return fail(SPMVC_EUNSUPPORTED, "mixed-precision mode takes one system with one right-hand side");
+        if (o.mode == 1 && (!(o.inner_rtol > 0.0) || o.max_outer < 0)) return fail(SPMVC_EINVAL, "invalid inner options");
+        for (int s = 0; s < n_sys; ++s) {
+            if (!A[s]) return fail(SPMVC_EINVAL, "matrix handle is null");
+            if (A[s]->n_rows != A[s]->n_cols) return fail(SPMVC_EINVAL, "CG needs square matrices");
+            if (A[s]->n_rows > 0 && (!b[s] || !x[s])) return fail(SPMVC_EINVAL, "b / x is null");
+            if (overlap(b[s], 8 * A[s]->n_rows * nrhs, x[s], 8 * A[s]->n_rows * nrhs))
+                return fail(SPMVC_EINVAL, "b and x overlap");
+            if (o.mode == 1 && !f32_ready(A[s])) return fail(SPMVC_EUNSUPPORTED, "mixed mode needs f32_shadow");
+        }
+        for (int i = 0; i < n_sys * nrhs; ++i) stat[i] = spmvc_cg_stat{};
+        const spmvc_status st = cg_solve_impl(A, n_sys, nrhs, b, x, o, stat, static_cast<hipStream_t>(stream));
+        if (st != SPMVC_OK) set_error(spmvc_status_string(st));
+        return st;
+    });
+}
+
+spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx, double *vals, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !row_ptr) return fail(SPMVC_EINVAL, "null argument");
+        if (A->nnz > 0 && (!col_idx || !vals)) return fail(SPMVC_EINVAL, "col_idx / vals is null");
+        decompress(A, row_ptr, col_idx, vals, static_cast<hipStream_t>(stream));
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !info) return fail(SPMVC_EINVAL, "null argument");
+        spmvc_info r{};
+        r.fmt = A->fmt;
+        r.K = A->K;
+        r.P = A->P;
+        r.id_bytes = A->id_bytes;
+        r.width = A->width;
+        r.max_raw = A->max_raw;
+        r.n_rows = A->n_rows;
+        r.n_cols = A->n_cols;
+        r.nnz = A->nnz;
+        r.n_escape_rows = A->n_esc;
+        r.n_escape_nnz = A->n_esc_nnz;
+        r.n_raw = A->n_raw;
+        r.bytes_stream = stream_bytes(A, SPMVC_F64);
+        // ELL of the same matrix: width = longest row, 12 bytes per slot over padded rows
+        int64_t maxlen = A->width;
+        if (A->fmt == SPMVC_FMT_DIT) {
+            maxlen = 0;
+            for (int q = 0; q < A->P; ++q) maxlen = std::max<int64_t>(maxlen, A->h_pat_len[q]);
+        }
+        r.bytes_ell = 12 * maxlen * A->n_pad + 12 * A->n_esc_nnz + 16 * A->n_esc;
+        const int64_t k4 = 4 * static_cast<int64_t>(A->K);
+        if (A->fmt == SPMVC_FMT_ELL)
+            r.bytes_paper = 12 * A->nnz;
+        else if (A->fmt == SPMVC_FMT_DT)
+            r.bytes_paper = 4 * (A->nnz - A->n_esc_nnz) + k4 * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz +
+                            8 * A->n_raw;
+        else
+            r.bytes_paper = (4 + k4) * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
+        r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode == 1) ? A->plan.n_win : 0;
+        r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan.rows : kBlock;
+        for (int c = 0; c < A->K; ++c) r.V[c] = A->V[c];
+        *info = r;
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, const void **dev_ptr, int64_t *bytes) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !dev_ptr || !bytes) return fail(SPMVC_EINVAL, "null argument");
+        const DevBuf *b = nullptr;
+        switch (which) {
+        case SPMVC_ARR_ELL_VAL: b = &A->ell_val; break;
+        case SPMVC_ARR_ELL_COL: b = &A->ell_col; break;
+        case SPMVC_ARR_DT_S: b = &A->dt_S; break;
+        case SPMVC_ARR_IDS: b = &A->ids; break;
+        case SPMVC_ARR_T: b = &A->T; break;
+        case SPMVC_ARR_PAT_OFF: b = &A->pat_off; break;
+        case SPMVC_ARR_PAT_LEN: b = &A->pat_len; break;
+        case SPMVC_ARR_RAW: b = &A->raw; break;
+        case SPMVC_ARR_RAW_SLICE: b = &A->raw_slice; break;
+        case SPMVC_ARR_ESC_ROWS: b = &A->esc_rows; break;
+        case SPMVC_ARR_ESC_PTR: b = &A->esc_ptr; break;
+        case SPMVC_ARR_ESC_COL: b = &A->esc_col; break;
+        case SPMVC_ARR_ESC_VAL: b = &A->esc_val; break;
+        case SPMVC_ARR_V: b = &A->V_dev; break;
+        default: return fail(SPMVC_EINVAL, "unknown array id");
+        }
+        *dev_ptr = b->p;
+        *bytes = static_cast<int64_t>(b->bytes);
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds) {
+    return guarded([&]() -> spmvc_status {
+        if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
+        if (rows_per_block != 0 && (rows_per_block < 256 || rows_per_block > 4096 || rows_per_block % 256))
+            return fail(SPMVC_EINVAL, "rows_per_block must be a multiple of 256 in 256..4096");
+        if (lds < -1 || lds > 1) return fail(SPMVC_EINVAL, "lds must be -1, 0 or 1");
+        if (lds >= 0) A->lds_mode = lds;
+        if (rows_per_block) {
+            A->rows_per_block = rows_per_block;
+            build_lds_plan(A, rows_per_block);
+        }
+        return SPMVC_OK;
+    });
+}
+
+void spmv_free(spmvc_matrix A) { delete A; }
+
+}  // extern "C"

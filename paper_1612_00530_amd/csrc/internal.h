@@ -1,0 +1,132 @@
+// Internal declarations of libspmvc (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/spmvc.h"
+
+namespace spmvc {
+
+constexpr int kMaxK = 15;           // value-table capacity
+constexpr int kMaxPatternLen = 255; // T and positions are one byte
+constexpr int kSlice = 64;          // rows per raw-value slice (one wavefront)
+constexpr int kMaxWindows = 8;      // x windows staged in LDS per block
+constexpr int kLdsBudgetBytes = 64 * 1024;
+constexpr int kBlock = 256;         // threads per block of the SpMV kernels
+constexpr int32_t kEscapeColumn = -2; // ELL/DT slot-0 marker of an escape row (padding is -1)
+
+// ---- errors -------------------------------------------------------------------------
+void set_error(const std::string &msg);
+spmvc_status fail(spmvc_status st, const std::string &msg);
+
+struct Error {
+    spmvc_status st;
+    std::string msg;
+};
+
+#define SPMVC_HIP(call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw ::spmvc::Error{e_ == hipErrorOutOfMemory ? SPMVC_ENOMEM : SPMVC_EHIP,     \
+                                 std::string(#call) + ": " + hipGetErrorString(e_)};        \
+    } while (0)
+
+#define SPMVC_CHECK_LAUNCH() SPMVC_HIP(hipGetLastError())
+
+// ---- device buffers ------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void alloc(size_t n) {
+        release();
+        if (n == 0) return;
+        SPMVC_HIP(hipMalloc(&p, n));
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+};
+
+// ---- LDS staging plan of the DIT kernel for one rows-per-block value ------------------
+struct LdsPlan {
+    int rows = 0;                 // rows per block this plan was built for
+    int n_win = 0;                // 0 = plan not usable (direct gather)
+    int64_t lo[kMaxWindows] = {}; // window w holds x[r0+lo[w] .. r0+rows-1+hi[w]]
+    int32_t len[kMaxWindows] = {};
+    int32_t base[kMaxWindows] = {}; // element offset of window w in LDS
+    int32_t total = 0;            // LDS elements
+    bool tab_in_lds = false;      // table small enough to copy into LDS per block
+    DevBuf tab;                   // uint16 [P][width]: LDS element index of each displacement
+};
+
+}  // namespace spmvc
+
+// The opaque handle.
+struct spmvc_matrix_s {
+    int64_t n_rows = 0, n_cols = 0, nnz = 0, n_pad = 0;
+    int32_t fmt = SPMVC_FMT_DIT;
+    int32_t K = 0, P = 0, id_bytes = 1, width = 0, max_raw = 0;
+    int32_t f32_shadow = 1;
+    double V[spmvc::kMaxK] = {};
+    float V32[spmvc::kMaxK] = {};
+    int64_t n_esc = 0, n_esc_nnz = 0, n_raw = 0, raw_elems = 0;
+    // device arrays
+    spmvc::DevBuf ell_val, ell_col, dt_S, ids, T, pat_off, pat_len, raw, raw32, raw_slice,
+        esc_rows, esc_ptr, esc_col, esc_val, esc_val32, V_dev;
+    // host copies of the (small) pattern table, for LDS plans
+    std::vector<int32_t> h_pat_off; // [P][width]
+    std::vector<uint8_t> h_pat_len; // [P]
+    // kernel configuration
+    int32_t rows_per_block = 1024;
+    int32_t lds_mode = 1; // 1 = stage in LDS when a plan fits
+    spmvc::LdsPlan plan;
+    int32_t block_rows = 256;   // spmv_block: rows per block
+};
+
+namespace spmvc {
+
+// compress.hip
+void compress(spmvc_matrix_s *M, const int64_t *row_ptr, const int32_t *col, const double *val,
+              const spmvc_compress_opts &o, hipStream_t s);
+void decompress(const spmvc_matrix_s *M, int64_t *row_ptr, int32_t *col, double *val,
+                hipStream_t s);
+
+// spmv.hip
+void build_lds_plan(spmvc_matrix_s *M, int rows);
+// `skip` (device int, may be null): when *skip != 0 the kernels return at once.
+void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s,
+                 const int *skip = nullptr);
+void launch_spmv_block(const spmvc_matrix_s *M, int dt, int nrhs, const void *X, int64_t ldx,
+                       void *Y, int64_t ldy, hipStream_t s, const int *skip = nullptr);
+int64_t stream_bytes(const spmvc_matrix_s *M, int dt);
+
+// cg.hip
+spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
+                           double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,
+                           hipStream_t s);
+
+// scan.hip: exclusive prefix sum of n int64 values (in may equal out); returns the total.
+int64_t exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+inline unsigned grid_for(int64_t work, int block, unsigned cap = 1u << 20) {
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<unsigned>(g);
+}
+
+}  // namespace spmvc

@@ -1,0 +1,162 @@
+// Autotuner: time each kernel configuration of a handle and keep the fastest.
+//
+// Candidates (single right-hand side, DIT): rows per block in {256 .. 4096}
+// with the x windows staged in LDS, and the direct-gather kernel (x read
+// through the L1/L2 caches).  Every candidate gives the same result; only the
+// time differs.  Winners are cached per (arch, format, rows, P, K, dtype, nrhs)
+// in the JSON object stored in the file named by $SPMVC_TUNE_CACHE.
+#include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "internal.h"
+
+namespace spmvc {
+namespace {
+
+struct Cand {
+    int rows, lds;
+};
+
+std::string cache_key(const spmvc_matrix_s *M, int dt, int nrhs) {
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::ostringstream k;
+    k << prop.gcnArchName << "|fmt" << M->fmt << "|n" << M->n_rows << "|P" << M->P << "|K" << M->K << "|dt" << dt
+      << "|nrhs" << nrhs;
+    return k.str();
+}
+
+// The cache file holds one JSON object: {"key": [rows, lds, microseconds], ...}
+std::map<std::string, std::vector<double>> read_cache(const char *path) {
+    std::map<std::string, std::vector<double>> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"');
+        const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+        const size_t b0 = line.find('[');
+        const size_t b1 = line.find(']');
+        if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos) continue;
+        std::vector<double> v;
+        std::stringstream ss(line.substr(b0 + 1, b1 - b0 - 1));
+        std::string tok;
+        while (std::getline(ss, tok, ',')) v.push_back(std::atof(tok.c_str()));
+        if (v.size() == 3) m[line.substr(q0 + 1, q1 - q0 - 1)] = v;
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, std::vector<double>> &m) {
+    std::ofstream f(path, std::ios::trunc);
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (const auto &kv : m) {
+        f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << "]"
+          << (++i < m.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+}
+
+}  // namespace
+}  // namespace spmvc
+
+using namespace spmvc;
+
+extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void *stream, int32_t *best_rows,
+                                  int32_t *best_lds, double *best_us) {
+    try {
+        if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
+        if (dt != SPMVC_F64 && dt != SPMVC_F32) return fail(SPMVC_EINVAL, "dtype must be F64 or F32");
+        if (nrhs < 1 || nrhs > 16) return fail(SPMVC_EINVAL, "nrhs must be in 1..16");
+        if (dt == SPMVC_F32 && !(A->f32_shadow || (A->raw_elems == 0 && A->n_esc_nnz == 0)))
+            return fail(SPMVC_EUNSUPPORTED, "FP32 spmv needs f32_shadow at compress time");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const char *cpath = std::getenv("SPMVC_TUNE_CACHE");
+        const std::string key = cache_key(A, dt, nrhs);
+        if (cpath) {
+            auto m = read_cache(cpath);
+            auto it = m.find(key);
+            if (it != m.end()) {
+                const int rows = static_cast<int>(it->second[0]), lds = static_cast<int>(it->second[1]);
+                A->lds_mode = lds;
+                A->rows_per_block = rows;
+                build_lds_plan(A, rows);
+                if (best_rows) *best_rows = rows;
+                if (best_lds) *best_lds = lds;
+                if (best_us) *best_us = it->second[2];
+                return SPMVC_OK;
+            }
+        }
+        std::vector<Cand> cands;
+        if (A->fmt == SPMVC_FMT_DIT && nrhs == 1) {
+            for (int rows : {256, 512, 1024, 2048, 4096}) cands.push_back({rows, 1});
+            cands.push_back({A->rows_per_block, 0});
+        } else {
+            cands.push_back({A->rows_per_block, A->lds_mode});
+        }
+        const size_t es = dt == SPMVC_F64 ? 8 : 4;
+        DevBuf x, y;
+        x.alloc(es * std::max<int64_t>(A->n_cols, 1) * nrhs);
+        y.alloc(es * std::max<int64_t>(A->n_rows, 1) * nrhs);
+        SPMVC_HIP(hipMemsetAsync(x.p, 0x3F, x.bytes, s));
+        hipEvent_t e0, e1;
+        SPMVC_HIP(hipEventCreate(&e0));
+        SPMVC_HIP(hipEventCreate(&e1));
+        double best = 1e300;
+        Cand win = cands.front();
+        for (const Cand &c : cands) {
+            A->lds_mode = c.lds;
+            A->rows_per_block = c.rows;
+            build_lds_plan(A, c.rows);
+            if (c.lds == 1 && A->fmt == SPMVC_FMT_DIT && A->plan.n_win == 0) continue;  // does not fit
+            auto run = [&]() {
+                if (nrhs == 1)
+                    launch_spmv(A, dt, x.p, y.p, s);
+                else
+                    launch_spmv_block(A, dt, nrhs, x.p, nrhs, y.p, nrhs, s);
+            };
+            for (int w = 0; w < 3; ++w) run();
+            std::vector<float> ts;
+            for (int r = 0; r < 15; ++r) {
+                SPMVC_HIP(hipEventRecord(e0, s));
+                run();
+                SPMVC_HIP(hipEventRecord(e1, s));
+                SPMVC_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                SPMVC_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ts.push_back(ms);
+            }
+            std::sort(ts.begin(), ts.end());
+            const double us = 1000.0 * ts[ts.size() / 2];
+            if (us < best) {
+                best = us;
+                win = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        A->lds_mode = win.lds;
+        A->rows_per_block = win.rows;
+        build_lds_plan(A, win.rows);
+        if (cpath) {
+            auto m = read_cache(cpath);
+            m[key] = {static_cast<double>(win.rows), static_cast<double>(win.lds), best};
+            write_cache(cpath, m);
+        }
+        if (best_rows) *best_rows = win.rows;
+        if (best_lds) *best_lds = win.lds;
+        if (best_us) *best_us = best;
+        return SPMVC_OK;
+    } catch (const Error &e) {
+        return fail(e.st, e.msg);
+    } catch (...) {
+        return fail(SPMVC_EHIP, "autotuner failed");
+    }
+}

@@ -1,0 +1,70 @@
+"""The C-ABI library: it loads and exports every entry point include/spmvc.h declares.
+
+Runs without a GPU (no compute calls).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spmvc.h")
+LIB = os.path.join(ROOT, "paper_1612_00530_amd", "libspmvc.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:spmvc_status|void|const char\s*\*|char\s*\*)\s*\*?\s*(\w+)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["spmv_compress", "spmv", "spmv_block", "cg_solve"]:
+        assert required in names
+    assert len(names) >= 12
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libspmvc.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libspmvc.so not built")
+def test_status_strings_without_gpu():
+    lib = ctypes.CDLL(LIB)
+    lib.spmvc_status_string.restype = ctypes.c_char_p
+    lib.spmvc_status_string.argtypes = [ctypes.c_int32]
+    assert lib.spmvc_status_string(0) == b"ok"
+    assert b"SPD" in lib.spmvc_status_string(-6)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libspmvc.so not built")
+def test_null_arguments_rejected_on_host():
+    """Host-side validation: no device work is issued for these calls."""
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    lib.spmv.argtypes = [P, ctypes.c_int32, P, P, P]
+    lib.spmv_compress.argtypes = [ctypes.c_int64] * 3 + [P] * 6
+    assert lib.spmv(None, 0, None, None, None) == -1
+    assert lib.spmv_compress(4, 4, 0, None, None, None, None, None, None) == -1
+    out = P()
+    assert lib.spmv_compress(-1, 4, 0, None, None, None, None, None, ctypes.byref(out)) == -1
+    lib.spmvc_last_error.restype = ctypes.c_char_p
+    assert b"negative" in lib.spmvc_last_error()
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import paper_1612_00530_amd as P
+
+    with pytest.raises(ImportError):
+        P.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,112 @@
+"""GPU conjugate gradients against the CPU oracle.
+
+The result of every solve is checked with the oracle's FP64 SpMV: the true
+relative residual ||b - A x|| / ||b|| must be <= 1e-10 (plus a little slack
+for the final rounding), and for b = A*1 the solution must approach 1.
+Iteration counts of the FP64 solver must match the oracle's within 2 (the
+two sum in different orders).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import stencil27, stencil27_irregular, uniform_vector
+
+from gpu_util import compress, lib, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def solve(A, b, fmt="DIT", **kw):
+    torch = torch_mod()
+    P = lib()
+    M = compress(A, fmt=fmt)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    st, xs, stats = P.cg_solve(M, bt, **kw)
+    torch.cuda.synchronize()
+    return st, xs[0].cpu().numpy(), stats
+
+
+@pytest.mark.parametrize("fmt", ["ELL", "DT", "DIT"])
+@pytest.mark.parametrize("grid", [(16, 16, 16), (32, 32, 32)])
+def test_fp64_cg_ones(fmt, grid):
+    say("case: cg ones", fmt, grid)
+    A = stencil27(*grid)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    st, x, stats = solve(A, b, fmt=fmt)
+    _, _, it_ref, _ = oracle.cg(A, b)
+    assert st == 0 and stats[0]["status"] == 0
+    assert abs(stats[0]["iters"] - it_ref) <= 2
+    assert oracle.relres(A, b, x) <= 1.5e-10
+    assert abs(stats[0]["relres_true"] - oracle.relres(A, b, x)) <= 1e-12
+    assert np.abs(x - 1).max() < 1e-7
+
+
+def test_fp64_cg_random_rhs_irregular():
+    say("case: cg irregular")
+    A = stencil27_irregular(30, 28, 26, seed=0)
+    b = uniform_vector(A.n_rows, seed=0)
+    st, x, stats = solve(A, b)
+    _, _, it_ref, _ = oracle.cg(A, b)
+    assert st == 0 and abs(stats[0]["iters"] - it_ref) <= 2
+    assert oracle.relres(A, b, x) <= 1.5e-10
+
+
+@pytest.mark.parametrize("grid", [(16, 16, 16), (64, 64, 64)])
+def test_mixed_precision_reaches_fp64_tolerance(grid):
+    say("case: mixed", grid)
+    A = stencil27(*grid)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    st, x, stats = solve(A, b, mode=1)
+    assert st == 0
+    assert stats[0]["outer_iters"] >= 1
+    assert oracle.relres(A, b, x) <= 1.5e-10
+    assert np.abs(x - 1).max() < 1e-7
+
+
+def test_multi_rhs_and_systems():
+    say("case: multi rhs")
+    torch = torch_mod()
+    P = lib()
+    grids = [(10, 12, 9), (16, 11, 13)]
+    mats, As, bs = [], [], []
+    for g in grids:
+        A = stencil27(*g)
+        As.append(A)
+        mats.append(compress(A))
+        B = np.stack([uniform_vector(A.n_rows, seed=s) for s in range(3)], axis=1)
+        bs.append(torch.from_numpy(B).cuda())
+    st, xs, stats = P.cg_solve(mats, bs, nrhs=3)
+    torch.cuda.synchronize()
+    assert st == 0
+    for s, A in enumerate(As):
+        X = xs[s].cpu().numpy()
+        B = bs[s].cpu().numpy()
+        for r in range(3):
+            assert oracle.relres(A, B[:, r], X[:, r]) <= 1.5e-10
+            assert stats[s * 3 + r]["status"] == 0
+
+
+def test_breakdown_and_max_iter():
+    say("case: cg failures")
+    A = stencil27(8, 8, 8)
+    A.val[:] = -A.val  # negative definite: p.Ap < 0 at the first step
+    st, x, stats = solve(A, np.ones(A.n_rows))
+    assert st == -6 and stats[0]["iters"] == 1
+    B = stencil27(16, 16, 16)
+    st, x, stats = solve(B, uniform_vector(B.n_rows, seed=0), max_iter=5)
+    assert st == -7 and stats[0]["iters"] == 5
+
+
+def test_zero_rhs():
+    say("case: zero rhs")
+    A = stencil27(8, 8, 8)
+    st, x, stats = solve(A, np.zeros(A.n_rows))
+    assert st == 0 and stats[0]["iters"] == 0 and np.all(x == 0)

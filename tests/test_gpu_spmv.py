@@ -1,0 +1,285 @@
+"""GPU parity of compression and SpMV against the CPU oracle (called through the C ABI).
+
+* compression is lossless: decompress(compress(A)) == A bit for bit;
+* the encoded arrays equal the reference codec's (deterministic IDs, exact V/T);
+* FP64 SpMV within 1e-14 of the oracle, per row relative to sum |a_ij||x_j|;
+* FP32 SpMV within (len + 2) * 2^-24 of the same normaliser;
+* block SpMV equals the oracle's per-column products.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import codec
+from synthetic import CSR, stencil27, stencil27_irregular, uniform_vector
+
+from gpu_util import compress, lib, max_rel_err, row_scale, same_bits, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["ELL", "DT", "DIT"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_spmv(M, x, dtype="f64"):
+    torch = torch_mod()
+    t = torch.from_numpy(x).cuda()
+    if dtype == "f32":
+        t = t.float()
+    y = M.spmv(t)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def roundtrip_ok(M, A):
+    rp, col, val = M.decompress()
+    return (np.array_equal(rp.cpu().numpy(), A.row_ptr) and np.array_equal(col.cpu().numpy(), A.col)
+            and same_bits(val.cpu().numpy(), A.val))
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_stencil16_parity_and_roundtrip(fmt):
+    say("case: stencil 16^3", fmt)
+    A = stencil27(16, 16, 16)
+    x = uniform_vector(A.n_cols, seed=0)
+    M = compress(A, fmt=fmt)
+    y = gpu_spmv(M, x)
+    assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
+    assert roundtrip_ok(M, A)
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_stencil104_full_size_parity(fmt):
+    say("case: stencil 104^3", fmt)
+    A = stencil27(104, 104, 104)
+    x = uniform_vector(A.n_cols, seed=0)
+    M = compress(A, fmt=fmt)
+    y = gpu_spmv(M, x)
+    assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
+    inf = M.info()
+    if fmt == "DIT":
+        assert inf["K"] == 2 and inf["P"] == 19 and inf["n_escape_rows"] == 8
+        assert inf["id_bytes"] == 1 and inf["lds_windows"] == 3
+    # closed form: A*1 = 26 - #neighbours, exact in any summation order
+    y1 = gpu_spmv(M, np.ones(A.n_cols))
+    assert np.array_equal(y1, oracle.spmv(A, np.ones(A.n_cols)))
+
+
+@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (2048, 1), (4096, 1), (1024, 0)])
+def test_dit_kernel_configs_agree(rows, lds):
+    say("case: DIT config", rows, lds)
+    A = stencil27(40, 37, 23)
+    x = uniform_vector(A.n_cols, seed=3)
+    M = compress(A, fmt="DIT")
+    M.set_config(rows, lds)
+    y = gpu_spmv(M, x)
+    assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_irregular128_parity_and_roundtrip(fmt):
+    say("case: irregular 128^3", fmt)
+    A = stencil27_irregular(128, 128, 128, seed=0)
+    x = uniform_vector(A.n_cols, seed=0)
+    M = compress(A, fmt=fmt)
+    y = gpu_spmv(M, x)
+    assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
+    assert roundtrip_ok(M, A)
+    if fmt == "DIT":
+        inf = M.info()
+        assert inf["K"] == 0 and inf["id_bytes"] == 2
+        assert inf["n_escape_rows"] < 0.02 * A.n_rows
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_fp32_within_bound(fmt):
+    say("case: fp32", fmt)
+    for A in (stencil27(33, 20, 17), stencil27_irregular(24, 22, 20, seed=2)):
+        x = uniform_vector(A.n_cols, seed=1).astype(np.float32)
+        M = compress(A, fmt=fmt)
+        y = gpu_spmv(M, x.astype(np.float64), dtype="f32")
+        yref = oracle.spmv(A, x.astype(np.float64))
+        lens = np.diff(A.row_ptr)
+        s = row_scale(A, x.astype(np.float64))
+        assert np.all(np.abs(y - yref) <= (lens + 2) * 2.0 ** -24 * s + 1e-300)
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("nrhs", [1, 3, 8, 16])
+def test_block_spmv(fmt, nrhs):
+    say("case: block", fmt, nrhs)
+    torch = torch_mod()
+    A = stencil27_irregular(20, 18, 15, seed=4) if fmt == "DT" else stencil27(21, 18, 15)
+    X = np.stack([uniform_vector(A.n_cols, seed=10 + r) for r in range(nrhs)], axis=1)
+    M = compress(A, fmt=fmt)
+    Y = M.spmv_block(torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    Y = Y.cpu().numpy()
+    Yref = oracle.spmv_block(A, X)
+    for r in range(nrhs):
+        assert max_rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14
+
+
+# ---- encoded arrays equal the reference codec's -----------------------------------------
+
+def _np(t, dtype):
+    return t.cpu().numpy().view(dtype)
+
+
+@pytest.mark.parametrize("make", [lambda: stencil27(16, 16, 16), lambda: stencil27_irregular(20, 17, 13, seed=1),
+                                  lambda: stencil27(5, 3, 4)])
+def test_dit_arrays_equal_reference_codec(make):
+    say("case: DIT arrays")
+    A = make()
+    enc = codec.encode_dit(A)
+    M = compress(A, fmt="DIT")
+    inf = M.info()
+    n, n_pad, K, W = A.n_rows, ((A.n_rows + 63) // 64) * 64, enc.K, inf["width"]
+    assert inf["K"] == K and inf["P"] == enc.P
+    assert same_bits(np.array(inf["V"]), enc.V)
+    idt = {1: np.uint8, 2: np.uint16, 4: np.uint32}[inf["id_bytes"]]
+    ids = _np(M.array("IDS"), idt)[:n].astype(np.int64)
+    ids[ids == np.iinfo(idt).max] = -1
+    assert np.array_equal(ids, enc.ids)
+    if K:
+        T = _np(M.array("T"), np.uint8).reshape(K, n_pad)[:, :n].T
+        assert np.array_equal(T, enc.T)
+    pl = _np(M.array("PAT_LEN"), np.uint8).astype(np.int64)
+    assert np.array_equal(pl, np.diff(enc.pat_ptr))
+    po = _np(M.array("PAT_OFF"), np.int32).reshape(enc.P, W)
+    for p in range(enc.P):
+        assert np.array_equal(po[p, :pl[p]], enc.pat_off[enc.pat_ptr[p]:enc.pat_ptr[p + 1]])
+    assert np.array_equal(_np(M.array("ESC_ROWS"), np.int64), enc.esc_rows)
+    if enc.esc_rows.size:
+        assert np.array_equal(_np(M.array("ESC_PTR"), np.int64), enc.esc_ptr)
+        assert np.array_equal(_np(M.array("ESC_COL"), np.int32)[:enc.esc_col.size], enc.esc_col)
+    # raw values: slices of 64 rows, column-major inside a slice
+    if enc.raw.size:
+        raw = _np(M.array("RAW"), np.float64)
+        sl = _np(M.array("RAW_SLICE"), np.int64)
+        for i in range(0, n, max(1, n // 501)):
+            k = enc.raw_ptr[i + 1] - enc.raw_ptr[i]
+            got = raw[sl[i // 64] + (i % 64) + 64 * np.arange(k)]
+            assert same_bits(got, enc.raw[enc.raw_ptr[i]:enc.raw_ptr[i + 1]])
+
+
+def test_dt_arrays_equal_reference_codec():
+    say("case: DT arrays")
+    A = stencil27(12, 10, 9)
+    enc = codec.encode_dt(A)
+    M = compress(A, fmt="DT")
+    inf = M.info()
+    n, n_pad, W = A.n_rows, ((A.n_rows + 63) // 64) * 64, inf["width"]
+    S = _np(M.array("DT_S"), np.int32).reshape(W, n_pad)[:, :n].T
+    for i in range(n):
+        L = enc.S_ptr[i + 1] - enc.S_ptr[i]
+        assert np.array_equal(S[i, :L], enc.S[enc.S_ptr[i]:enc.S_ptr[i + 1]])
+        assert np.all(S[i, L:] == -1)
+
+
+# ---- edge cases ---------------------------------------------------------------------
+
+SPECIAL = np.array([0.0, -0.0, 1.0, -1.0, np.inf, -np.inf, np.nan, 26.0, 5e-324], dtype=np.float64)
+
+
+def random_csr(rng, n_rows, n_cols, max_len, pool):
+    lens = rng.integers(0, max_len + 1, n_rows)
+    lens = np.minimum(lens, n_cols)
+    cols = [np.sort(rng.choice(n_cols, size=L, replace=False)) for L in lens]
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(lens, out=rp[1:])
+    col = np.concatenate(cols).astype(np.int32) if n_rows else np.zeros(0, np.int32)
+    val = rng.choice(pool, size=int(rp[-1]))
+    return CSR(n_rows, n_cols, rp, col, val)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_random_special_values_roundtrip_and_spmv(seed, fmt):
+    say("case: random special", seed, fmt)
+    rng = np.random.default_rng(seed)
+    nan_payload = np.frombuffer(np.uint64(0x7FF0000000000777).tobytes(), dtype=np.float64)[0]
+    pool = np.concatenate([SPECIAL, [nan_payload], rng.uniform(-5, 5, 4)])
+    A = random_csr(rng, int(rng.integers(1, 700)), int(rng.integers(1, 900)), 40, pool)
+    M = compress(A, fmt=fmt, min_pattern_rows=1 + seed % 2)
+    assert roundtrip_ok(M, A)
+    x = rng.uniform(-1, 1, A.n_cols)
+    y = gpu_spmv(M, x)
+    yref = oracle.spmv(A, x)
+    # special values: NaN where the oracle has NaN, otherwise the 1e-14 bound
+    nan = np.isnan(yref)
+    assert np.array_equal(np.isnan(y), nan)
+    fin = ~nan & np.isfinite(yref)
+    s = row_scale(A, x)[fin]
+    assert np.all(np.abs(y[fin] - yref[fin]) <= 1e-14 * s + 0.0)
+    inf = ~nan & ~np.isfinite(yref)
+    assert np.array_equal(y[inf], yref[inf])
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_long_rows_escape_and_empty_rows(fmt):
+    say("case: long rows", fmt)
+    rng = np.random.default_rng(9)
+    n_rows, n_cols = 300, 1000
+    lens = np.zeros(n_rows, dtype=np.int64)
+    lens[5] = 600  # longer than 255: escape row
+    lens[100:200] = 7
+    cols = [np.sort(rng.choice(n_cols, size=L, replace=False)) for L in lens]
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(lens, out=rp[1:])
+    A = CSR(n_rows, n_cols, rp, np.concatenate(cols).astype(np.int32), rng.choice([-1.0, 2.0, 0.5], int(rp[-1])))
+    M = compress(A, fmt=fmt)
+    assert roundtrip_ok(M, A)
+    x = rng.uniform(-1, 1, n_cols)
+    assert max_rel_err(A, x, gpu_spmv(M, x), oracle.spmv(A, x)) <= 1e-14
+    assert M.info()["n_escape_rows"] >= 1
+
+
+def test_empty_matrix_and_single_row():
+    say("case: empty / single row")
+    torch = torch_mod()
+    P = lib()
+    A = CSR(3, 5, np.zeros(4, dtype=np.int64), np.zeros(0, np.int32), np.zeros(0))
+    M = P.compress(torch.zeros(4, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
+                   torch.zeros(0, dtype=torch.float64, device="cuda"), n_cols=5)
+    y = M.spmv(torch.ones(5, dtype=torch.float64, device="cuda"))
+    assert torch.all(y == 0)
+    B = CSR(1, 66, [0, 5], [45, 49, 50, 51, 65], [-1.0, -1.0, 26.0, -1.0, -1.0])
+    for fmt in FORMATS:
+        M = compress(B, fmt=fmt, min_pattern_rows=1)
+        assert roundtrip_ok(M, B)
+        x = uniform_vector(66, seed=2)
+        assert max_rel_err(B, x, gpu_spmv(M, x), oracle.spmv(B, x)) <= 1e-14
+
+
+def test_invalid_csr_is_rejected():
+    say("case: invalid CSR")
+    torch = torch_mod()
+    P = lib()
+    dev = "cuda"
+    rp = torch.tensor([0, 2, 3], dtype=torch.int64, device=dev)
+    with pytest.raises(P.SpmvcError) as e:  # unsorted columns
+        P.compress(rp, torch.tensor([3, 1, 0], dtype=torch.int32, device=dev),
+                   torch.ones(3, dtype=torch.float64, device=dev), n_cols=4)
+    assert e.value.status == -3
+    with pytest.raises(P.SpmvcError) as e:  # column out of range
+        P.compress(rp, torch.tensor([1, 9, 0], dtype=torch.int32, device=dev),
+                   torch.ones(3, dtype=torch.float64, device=dev), n_cols=4)
+    assert e.value.status == -4
+    with pytest.raises(P.SpmvcError) as e:  # row_ptr not ending at nnz
+        P.compress(torch.tensor([0, 2, 5], dtype=torch.int64, device=dev),
+                   torch.tensor([0, 1, 2], dtype=torch.int32, device=dev),
+                   torch.ones(3, dtype=torch.float64, device=dev), n_cols=4)
+    assert e.value.status == -4
+    A = stencil27(4, 4, 4)
+    M = compress(A)
+    x = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
+    with pytest.raises(P.SpmvcError) as e:  # x and y alias
+        M.spmv(x, x)
+    assert e.value.status == -1
