@@ -68,11 +68,11 @@ typedef struct {
 } spmvc_compress_opts;
 
 /*
- * Compress a CSR matrix.  Section V: "first the entire matrix is scanned and
- * all unique values ... are listed and sorted in the ascending order" (V), the
- * non-zeros of each row are sorted by value (S_i, ties by column), the run end
- * of every value is recorded (T_i), and for DIT the displacements col - row
- * are registered in a pattern table.
+ * Compress a CSR matrix with the steps of Section V: one pass over all
+ * entries collects the distinct values into the ascending value table V; each
+ * row's entries are ordered by value (S_i, ties by column); the end of every
+ * value's run in that order is kept (T_i); for DIT the column indices become
+ * displacements col - row whose per-row sequences go into a pattern table.
  *
  * Dictionary: a value enters V when 8*count > n_rows (it pays for its T byte
  * per row); of those the k_max most frequent are kept; V is sorted by IEEE-754
@@ -178,9 +178,10 @@ typedef struct {
 spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info /* host */);
 
 /*
- * Internal arrays, for tests and tools: device pointer and byte size of one
- * array of the encoding (which: see spmvc_array_id).  The pointer stays valid
- * until spmv_free.  Layouts: ELL_VAL f64 / ELL_COL i32 / DT_S i32 are
+ * Internal arrays, for tests and tools: byte size of one array of the
+ * encoding (which: see spmvc_array_id) in *bytes, and when dst is not NULL a
+ * copy of it into the caller's device buffer dst (at least *bytes long;
+ * blocking).  Layouts: ELL_VAL f64 / ELL_COL i32 / DT_S i32 are
  * [width][n_pad] column-major (n_pad = n_rows rounded up to 64, padding
  * column -1); IDS [n_pad] of id_bytes each (all-ones = escape row); T u8
  * [K][n_pad]; PAT_OFF i32 [P][width] displacements, PAT_LEN u8 [P]; RAW f64 in
@@ -195,7 +196,7 @@ typedef enum {
     SPMVC_ARR_ESC_COL = 11, SPMVC_ARR_ESC_VAL = 12, SPMVC_ARR_V = 13
 } spmvc_array_id;
 
-spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, const void **dev_ptr, int64_t *bytes);
+spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *bytes, void *stream);
 
 /*
  * Kernel configuration of a handle's spmv (rows per block, LDS staging).

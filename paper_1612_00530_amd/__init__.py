@@ -80,6 +80,10 @@ def load(path: str = LIB_PATH):
         raise ImportError(f"{path} is missing: build it with paper_1612_00530_amd.build.build()")
     if _lib is not None and path == LIB_PATH:
         return _lib
+    # torch first: its HIP runtime (soname libamdhip64.so.7) then also serves this
+    # library, so the process holds one HIP runtime, not two.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.spmv_compress.argtypes = [i64, i64, i64, P, P, P, ctypes.POINTER(CompressOpts), P, ctypes.POINTER(P)]
@@ -89,7 +93,7 @@ def load(path: str = LIB_PATH):
                              ctypes.POINTER(CgOpts), ctypes.POINTER(CgStat), P]
     lib.spmv_decompress.argtypes = [P, P, P, P, P]
     lib.spmv_info.argtypes = [P, ctypes.POINTER(Info)]
-    lib.spmv_get_array.argtypes = [P, i32, ctypes.POINTER(P), ctypes.POINTER(i64)]
+    lib.spmv_get_array.argtypes = [P, i32, P, ctypes.POINTER(i64), P]
     lib.spmv_set_config.argtypes = [P, i32, i32]
     lib.spmv_tune.argtypes = [P, i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                               ctypes.POINTER(ctypes.c_double)]
@@ -205,12 +209,12 @@ class Matrix:
         """Copy of an internal array as a uint8 CUDA tensor (layout: see include/spmvc.h)."""
         import torch
 
-        ptr = ctypes.c_void_p()
         nb = ctypes.c_int64()
-        _check(load().spmv_get_array(self._h, ARR[name], ctypes.byref(ptr), ctypes.byref(nb)))
+        _check(load().spmv_get_array(self._h, ARR[name], None, ctypes.byref(nb), _stream()))
         out = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
         if nb.value:
-            _hip_copy(out.data_ptr(), ptr.value, nb.value)
+            _check(load().spmv_get_array(self._h, ARR[name], ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.byref(nb), _stream()))
         return out
 
     def set_config(self, rows_per_block=0, lds=-1):
@@ -224,23 +228,6 @@ class Matrix:
         _check(load().spmv_tune(self._h, dt, nrhs, _stream(), ctypes.byref(rows), ctypes.byref(lds),
                                 ctypes.byref(us)))
         return {"rows_per_block": rows.value, "lds": lds.value, "us": us.value}
-
-
-_hip = None
-
-
-def _hip_copy(dst: int, src: int, nbytes: int):
-    """Device-to-device copy through the HIP runtime (synchronous)."""
-    global _hip
-    if _hip is None:
-        _hip = ctypes.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-        _hip.hipMemcpy.restype = ctypes.c_int
-        _hip.hipDeviceSynchronize.restype = ctypes.c_int
-    _hip.hipDeviceSynchronize()
-    st = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
-    if st != 0:
-        raise RuntimeError(f"hipMemcpy failed: {st}")
 
 
 def compress(row_ptr, col, val, n_cols=None, fmt="DIT", k_max=15, p_max=65535, min_pattern_rows=2,

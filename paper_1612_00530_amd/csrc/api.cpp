@@ -219,9 +219,9 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
     });
 }
 
-spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, const void **dev_ptr, int64_t *bytes) {
+spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *bytes, void *stream) {
     return guarded([&]() -> spmvc_status {
-        if (!A || !dev_ptr || !bytes) return fail(SPMVC_EINVAL, "null argument");
+        if (!A || !bytes) return fail(SPMVC_EINVAL, "null argument");
         const DevBuf *b = nullptr;
         switch (which) {
         case SPMVC_ARR_ELL_VAL: b = &A->ell_val; break;
@@ -240,8 +240,12 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, const void **dev_ptr,
         case SPMVC_ARR_V: b = &A->V_dev; break;
         default: return fail(SPMVC_EINVAL, "unknown array id");
         }
-        *dev_ptr = b->p;
         *bytes = static_cast<int64_t>(b->bytes);
+        if (dst && b->bytes) {
+            hipStream_t s = static_cast<hipStream_t>(stream);
+            SPMVC_HIP(hipMemcpyAsync(dst, b->p, b->bytes, hipMemcpyDeviceToDevice, s));
+            SPMVC_HIP(hipStreamSynchronize(s));
+        }
         return SPMVC_OK;
     });
 }
