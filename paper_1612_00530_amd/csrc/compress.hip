@@ -94,11 +94,21 @@ struct GTable {
     int *flags;
 };
 
+// Bounded insert: a key that finds no slot within kMaxProbe steps, or would
+// push the fill past fill_limit, raises kFlagOverflow instead (the host then
+// recounts with more partitions), so no insert can run long.
+constexpr uint64_t kMaxProbe = 1024;
+
 __device__ void g_insert(const GTable &t, uint64_t key, uint32_t c, int64_t idx) {
     uint64_t s = mix64(key) & t.mask;
-    for (uint64_t probe = 0; probe <= t.mask; ++probe) {
+    const uint64_t limit = t.mask < kMaxProbe ? t.mask + 1 : kMaxProbe;
+    for (uint64_t probe = 0; probe < limit; ++probe) {
         uint64_t k = load_relaxed(&t.keys[s]);
         if (k == kEmpty) {
+            if (__hip_atomic_load(t.fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= t.fill_limit) {
+                atomicOr(t.flags, kFlagOverflow);
+                return;
+            }
             const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long *>(&t.keys[s]),
                                            static_cast<unsigned long long>(kEmpty),
                                            static_cast<unsigned long long>(key));

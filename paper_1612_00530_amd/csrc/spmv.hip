@@ -362,10 +362,11 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
     for (int q = 0; q < M->P; ++q)
         for (int k = 0; k < M->h_pat_len[q]; ++k) ds.insert(M->h_pat_off[static_cast<size_t>(q) * W + k]);
     if (ds.empty()) return;
+    // Two windows merge when the gap between them is below `rows`: a separate
+    // window costs `rows` more LDS elements than the gap it skips.
     std::vector<std::pair<int64_t, int64_t>> win;
-    constexpr int64_t kMergeGap = 64;
     for (int64_t d : ds) {
-        if (!win.empty() && d - win.back().second <= kMergeGap)
+        if (!win.empty() && d - win.back().second <= rows)
             win.back().second = d;
         else
             win.push_back({d, d});
