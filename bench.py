@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 512 MiB read+write elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -91,6 +93,13 @@ def main():
     P.load()  # fails loudly when the HIP library is missing
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     g = args.grid
     log(f"[bench] generating 27-point stencil {g}^3")
     A = stencil27(g, g, g)

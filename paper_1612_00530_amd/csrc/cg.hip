@@ -11,10 +11,17 @@
 // the batch returns at entry (the `done` flag), so surplus launches cost only
 // their launch overhead.
 //
-// Reductions: every block reduces its elements in a fixed order (wavefront
-// butterfly through lane permutes, then the waves in index order), writes one
-// partial, and the last block to finish -- found with an acquire-release
-// ticket -- adds the partials in index order.  The result does not depend on
+// Reductions without device-wide fences: every block reduces its elements in a
+// fixed order (wavefront butterfly through lane permutes, then the waves in
+// index order) and writes one partial; the *next* kernel reads all partials
+// and every one of its blocks adds them in the same fixed order, so all blocks
+// hold the identical scalar and no block waits for another.  (An agent-scope
+// release per block -- the usual last-block-done pattern -- writes back the
+// whole L2 of an XCD on this chip and costs more than the streaming itself.)
+// The SpMV of the iteration writes the p.q partials itself.  Scalars that
+// persist across iterations are written by block 0 only, into slots other
+// blocks of the same kernel do not read (rho is double-buffered by iteration
+// parity; the iteration index comes from the host).  Results do not depend on
 // block scheduling, so iteration counts repeat exactly from run to run.
 #include <algorithm>
 #include <cmath>
@@ -24,14 +31,14 @@
 namespace spmvc {
 namespace {
 
-constexpr int kRT = 256;         // threads per reduction block
-constexpr unsigned kRMaxBlocks = 2048;
+constexpr int kRT = 512;                // threads per BLAS-1 block (8 waves)
+constexpr unsigned kRMaxBlocks = 1024;  // partials per reduction
 
 struct CgScal {
-    double rho, rho0, sigma, alpha, beta, rel, rtol, pad0;
+    double rho[2];    // r.r of the current iterate, by iteration parity
+    double rho0, rtol, rel, sigma;
     int32_t iters, max_iter, done, status;
-    uint32_t ticket[4];
-    double aux[4]; // aux[0]: result of standalone reductions
+    double aux[4];
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -40,174 +47,200 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum over the block; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double *sh) {
+// Sum over a block of NT threads; the result is returned to every thread.
+template <int NT> __device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[NT / 64];
     v = wave_sum(v);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
     if (l == 0) sh[w] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kRT / 64; ++i) s += sh[i];
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += sh[i];
     return s;
 }
 
-__device__ __forceinline__ double load_agent(const double *p) {
-    const uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double(static_cast<long long>(b));
-}
-
-// Grid reduction; returns true in thread 0 of the last block, with *out = the sum.
-__device__ bool grid_sum(double v, double *partials, uint32_t *ticket, double *out) {
-    __shared__ double sh[kRT / 64];
-    __shared__ int last;
-    const double b = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = b;
-        __threadfence();
-        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+// Sum of partials[0..np) in a fixed order; identical in every block.
+template <int NT> __device__ __forceinline__ double sum_partials(const double *partials, int np) {
     double s = 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += kRT) s += load_agent(&partials[i]);
-    const double tot = block_sum(s, sh);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        *out = tot;
-        return true;
-    }
-    return false;
+    for (int i = threadIdx.x; i < np; i += NT) s += partials[i];
+    return block_sum<NT>(s);
 }
 
 template <class Real> __device__ __forceinline__ double dd(Real v) { return static_cast<double>(v); }
 
-// x = 0, r = rhs, p = rhs, rho = rho0 = r.r
+// Grid-stride loop over [0, n) that handles four elements per step, each a
+// stride apart, so every thread has four independent loads of each stream in
+// flight; the tail is handled one element at a time.
+#define SPMVC_STREAM4(BODY4, BODY1)                                                              \
+    {                                                                                            \
+        const int64_t stride_ = static_cast<int64_t>(gridDim.x) * kRT;                           \
+        int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x;                        \
+        for (; i + 3 * stride_ < n; i += 4 * stride_) {                                          \
+            BODY4                                                                                \
+        }                                                                                        \
+        for (; i < n; i += stride_) {                                                            \
+            BODY1                                                                                \
+        }                                                                                        \
+    }
+
+// x = 0, r = rhs, p = rhs; partials of r.r
 template <class Real, class RhsT>
 __global__ __launch_bounds__(kRT) void k_cg_start(int64_t n, const RhsT *__restrict__ rhs, Real *__restrict__ x,
-                                                  Real *__restrict__ r, Real *__restrict__ p, double *partials,
-                                                  CgScal *st, double rtol, int max_iter) {
+                                                  Real *__restrict__ r, Real *__restrict__ p, double *partials) {
     double acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRT;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x; i < n; i += stride) {
+    SPMVC_STREAM4(
+        Real v[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) v[u] = static_cast<Real>(rhs[i + u * stride_]);
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            x[i + u * stride_] = Real(0); r[i + u * stride_] = v[u]; p[i + u * stride_] = v[u];
+            acc += dd(v[u]) * dd(v[u]);
+        }
+        ,
         const Real v = static_cast<Real>(rhs[i]);
-        x[i] = Real(0);
-        r[i] = v;
-        p[i] = v;
+        x[i] = Real(0); r[i] = v; p[i] = v;
         acc += dd(v) * dd(v);
-    }
-    double tot;
-    if (grid_sum(acc, partials, &st->ticket[0], &tot)) {
-        st->rho = tot;
-        st->rho0 = tot;
-        st->rtol = rtol;
-        st->iters = 0;
-        st->max_iter = max_iter;
-        st->rel = tot > 0.0 ? 1.0 : 0.0;
-        st->done = (tot == 0.0) ? 1 : 0;
-        st->status = SPMVC_OK;
-        if (tot == 0.0) st->rel = 0.0;
-        if (!(tot == tot) || tot > 1.7e308) {
-            st->done = 1;
-            st->status = SPMVC_EINVAL;
-        }
+    )
+    const double b = block_sum<kRT>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+// rho0 = rho[0] = sum of the partials; state reset (one block)
+__global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, int np, CgScal *st, double rtol,
+                                                      int max_iter) {
+    const double tot = sum_partials<kRT>(partials, np);
+    if (threadIdx.x != 0) return;
+    st->rho[0] = tot;
+    st->rho[1] = 0.0;
+    st->rho0 = tot;
+    st->rtol = rtol;
+    st->iters = 0;
+    st->max_iter = max_iter;
+    st->rel = tot > 0.0 ? 1.0 : 0.0;
+    st->done = (tot == 0.0) ? 1 : 0;
+    st->status = SPMVC_OK;
+    if (!(tot == tot) || tot > 1.7e308) {
+        st->done = 1;
+        st->status = SPMVC_EINVAL;
     }
 }
 
-// sigma = p.q, alpha = rho / sigma (breakdown when sigma <= 0 or not finite)
-template <class Real>
-__global__ __launch_bounds__(kRT) void k_cg_alpha(int64_t n, const Real *__restrict__ p, const Real *__restrict__ q,
-                                                  double *partials, CgScal *st) {
-    if (st->done) return;
-    double acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRT;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x; i < n; i += stride)
-        acc += dd(p[i]) * dd(q[i]);
-    double sigma;
-    if (grid_sum(acc, partials, &st->ticket[1], &sigma)) {
-        st->sigma = sigma;
-        if (!(sigma > 0.0) || !isfinite(sigma)) {
-            st->done = 1;
-            st->status = SPMVC_ENOTSPD;
-            st->iters += 1;
-        } else {
-            st->alpha = st->rho / sigma;
-        }
-    }
-}
-
-// x += alpha p; r -= alpha q; rho' = r.r; convergence test; beta
+// sigma = sum of the p.q partials of the SpMV; alpha = rho / sigma;
+// x += alpha p; r -= alpha q; partials of r.r.  A breakdown (sigma <= 0 or not
+// finite) stops the solve.
 template <class Real>
 __global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__ x, Real *__restrict__ r,
                                                    const Real *__restrict__ p, const Real *__restrict__ q,
-                                                   double *partials, CgScal *st) {
+                                                   const double *sig_part, int n_sig, double *rr_part, CgScal *st,
+                                                   int par, int it) {
     if (st->done) return;
-    const Real alpha = static_cast<Real>(st->alpha);
+    const double sigma = sum_partials<kRT>(sig_part, n_sig);
+    if (!(sigma > 0.0) || !isfinite(sigma)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->sigma = sigma;
+            st->done = 1;
+            st->status = SPMVC_ENOTSPD;
+            st->iters = it + 1;
+        }
+        return;
+    }
+    const Real alpha = static_cast<Real>(st->rho[par] / sigma);
     double acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRT;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x; i < n; i += stride) {
+    SPMVC_STREAM4(
+        Real xv[4]; Real rv[4]; Real pv[4]; Real qv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            xv[u] = x[i + u * stride_]; rv[u] = r[i + u * stride_];
+            pv[u] = p[i + u * stride_]; qv[u] = q[i + u * stride_];
+        }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            x[i + u * stride_] = xv[u] + alpha * pv[u];
+            const Real ri = rv[u] - alpha * qv[u];
+            r[i + u * stride_] = ri;
+            acc += dd(ri) * dd(ri);
+        }
+        ,
         x[i] = x[i] + alpha * p[i];
         const Real ri = r[i] - alpha * q[i];
         r[i] = ri;
         acc += dd(ri) * dd(ri);
-    }
-    double rho_new;
-    if (grid_sum(acc, partials, &st->ticket[2], &rho_new)) {
-        st->iters += 1;
+    )
+    const double b = block_sum<kRT>(acc);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = b;
+}
+
+// rho' = sum of the r.r partials; convergence test; beta = rho'/rho; p = r + beta p.
+template <class Real>
+__global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, const Real *__restrict__ r, Real *__restrict__ p,
+                                                    const double *rr_part, int n_rr, CgScal *st, int par, int it) {
+    if (st->done) return;
+    const double rho_new = sum_partials<kRT>(rr_part, n_rr);
+    const double rho = st->rho[par];
+    const bool conv = sqrt(rho_new) <= st->rtol * sqrt(st->rho0);
+    const bool stop = conv || (it + 1 >= st->max_iter) || !isfinite(rho_new);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iters = it + 1;
         st->rel = sqrt(rho_new) / sqrt(st->rho0);
-        if (sqrt(rho_new) <= st->rtol * sqrt(st->rho0)) {
+        st->rho[par ^ 1] = rho_new;
+        if (conv) {
             st->done = 1;
             st->status = SPMVC_OK;
-        } else if (st->iters >= st->max_iter) {
-            st->done = 1;
-            st->status = SPMVC_ENOCONV;
         } else if (!isfinite(rho_new)) {
             st->done = 1;
             st->status = SPMVC_ENOTSPD;
+        } else if (it + 1 >= st->max_iter) {
+            st->done = 1;
+            st->status = SPMVC_ENOCONV;
         }
-        st->beta = rho_new / st->rho;
-        st->rho = rho_new;
     }
-}
-
-// p = r + beta p
-template <class Real>
-__global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, const Real *__restrict__ r, Real *__restrict__ p,
-                                                    const CgScal *st) {
-    if (st->done) return;
-    const Real beta = static_cast<Real>(st->beta);
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRT;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x; i < n; i += stride)
+    if (stop) return;
+    const Real beta = static_cast<Real>(rho_new / rho);
+    SPMVC_STREAM4(
+        Real rv[4]; Real pv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = r[i + u * stride_]; pv[u] = p[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) p[i + u * stride_] = rv[u] + beta * pv[u];
+        ,
         p[i] = r[i] + beta * p[i];
+    )
 }
 
-// r = b - Ax (FP64) and aux[0] = r.r
+// partials of (b - ax).(b - ax), optionally storing r = b - ax; partials of b.b
 __global__ __launch_bounds__(kRT) void k_residual(int64_t n, const double *__restrict__ b,
                                                   const double *__restrict__ ax, double *__restrict__ r,
-                                                  double *partials, CgScal *st) {
-    double acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRT;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x; i < n; i += stride) {
+                                                  double *rr_part, double *bb_part) {
+    double acc = 0.0, accb = 0.0;
+    SPMVC_STREAM4(
+        double bv[4]; double av[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { bv[u] = b[i + u * stride_]; av[u] = ax[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            const double v = bv[u] - av[u];
+            if (r) r[i + u * stride_] = v;
+            acc += v * v;
+            accb += bv[u] * bv[u];
+        }
+        ,
         const double v = b[i] - ax[i];
         if (r) r[i] = v;
         acc += v * v;
+        accb += b[i] * b[i];
+    )
+    const double s1 = block_sum<kRT>(acc);
+    const double s2 = block_sum<kRT>(accb);
+    if (threadIdx.x == 0) {
+        rr_part[blockIdx.x] = s1;
+        bb_part[blockIdx.x] = s2;
     }
-    double tot;
-    if (grid_sum(acc, partials, &st->ticket[3], &tot)) st->aux[0] = tot;
 }
 
-// aux[1] = b.b
-__global__ __launch_bounds__(kRT) void k_norm2(int64_t n, const double *__restrict__ b, double *partials,
-                                               CgScal *st) {
-    double acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kRT;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x; i < n; i += stride) acc += b[i] * b[i];
-    double tot;
-    if (grid_sum(acc, partials, &st->ticket[3], &tot)) st->aux[1] = tot;
+// aux[0] = sum of rr partials, aux[1] = sum of bb partials (one block)
+__global__ __launch_bounds__(kRT) void k_residual_fin(const double *rr_part, const double *bb_part, int np,
+                                                      CgScal *st) {
+    const double a = sum_partials<kRT>(rr_part, np);
+    const double b = sum_partials<kRT>(bb_part, np);
+    if (threadIdx.x == 0) {
+        st->aux[0] = a;
+        st->aux[1] = b;
+    }
 }
 
 // x += (double) d
@@ -231,7 +264,7 @@ __global__ void k_scatter_col(int64_t n, const double *__restrict__ v, double *_
 }
 
 unsigned rgrid(int64_t n) {
-    int64_t g = (n + kRT * 4 - 1) / (kRT * 4);
+    int64_t g = (n + kRT * 8 - 1) / (kRT * 8);
     return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(g, kRMaxBlocks)));
 }
 
@@ -245,12 +278,14 @@ struct Pinned {
 
 struct Solver {
     hipStream_t s;
-    DevBuf scal, partials;
+    DevBuf scal, part_a, part_b, part_sig;
     Pinned pin;
-    explicit Solver(hipStream_t st) : s(st) {
+    Solver(hipStream_t st, int64_t sig_blocks) : s(st) {
         scal.alloc(sizeof(CgScal));
         SPMVC_HIP(hipMemsetAsync(scal.p, 0, sizeof(CgScal), s));
-        partials.alloc(sizeof(double) * kRMaxBlocks);
+        part_a.alloc(sizeof(double) * kRMaxBlocks);
+        part_b.alloc(sizeof(double) * kRMaxBlocks);
+        part_sig.alloc(sizeof(double) * std::max<int64_t>(sig_blocks, 1));
     }
     CgScal *st() { return scal.as<CgScal>(); }
     const CgScal &read() {
@@ -267,17 +302,20 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Rea
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     const int dt = std::is_same<Real, double>::value ? SPMVC_F64 : SPMVC_F32;
-    k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, z, r, p, sv.partials.as<double>(), sv.st(), rtol, max_iter);
+    k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, z, r, p, sv.part_a.as<double>());
+    k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), rtol, max_iter);
     SPMVC_CHECK_LAUNCH();
     const int chunk = std::max(1, check_every);
-    const int64_t max_chunks = static_cast<int64_t>(max_iter) / chunk + 2;
-    for (int64_t c = 0; c < max_chunks; ++c) {
+    int it = 0;
+    while (it < max_iter) {
         if (sv.read().done) break;
-        for (int j = 0; j < chunk; ++j) {
-            launch_spmv(M, dt, p, q, sv.s, &sv.st()->done);
-            k_cg_alpha<Real><<<g, kRT, 0, sv.s>>>(n, p, q, sv.partials.as<double>(), sv.st());
-            k_cg_update<Real><<<g, kRT, 0, sv.s>>>(n, z, r, p, q, sv.partials.as<double>(), sv.st());
-            k_cg_pupdate<Real><<<g, kRT, 0, sv.s>>>(n, r, p, sv.st());
+        for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
+            const int par = it & 1;
+            const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.part_sig.as<double>());
+            k_cg_update<Real><<<g, kRT, 0, sv.s>>>(n, z, r, p, q, sv.part_sig.as<double>(), static_cast<int>(ns),
+                                                   sv.part_b.as<double>(), sv.st(), par, it);
+            k_cg_pupdate<Real><<<g, kRT, 0, sv.s>>>(n, r, p, sv.part_b.as<double>(), static_cast<int>(g), sv.st(),
+                                                    par, it);
         }
         SPMVC_CHECK_LAUNCH();
     }
@@ -289,22 +327,30 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Rea
     return out;
 }
 
-// ||b - A x|| / ||b|| in FP64 (tmp: n doubles)
-double true_relres(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp) {
+// ||b - A x||^2 and ||b||^2 in FP64 (tmp: n doubles; r receives b - Ax when not null)
+void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp, double *r,
+              double &rr, double &bb) {
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     launch_spmv(M, SPMVC_F64, x, tmp, sv.s);
-    k_residual<<<g, kRT, 0, sv.s>>>(n, b, tmp, nullptr, sv.partials.as<double>(), sv.st());
-    k_norm2<<<g, kRT, 0, sv.s>>>(n, b, sv.partials.as<double>(), sv.st());
+    k_residual<<<g, kRT, 0, sv.s>>>(n, b, tmp, r, sv.part_a.as<double>(), sv.part_b.as<double>());
+    k_residual_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), sv.part_b.as<double>(), static_cast<int>(g), sv.st());
     SPMVC_CHECK_LAUNCH();
     const CgScal &h = sv.read();
-    return h.aux[1] > 0.0 ? std::sqrt(h.aux[0]) / std::sqrt(h.aux[1]) : std::sqrt(h.aux[0]);
+    rr = h.aux[0];
+    bb = h.aux[1];
+}
+
+double true_relres(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp) {
+    double rr, bb;
+    residual(M, sv, b, x, tmp, nullptr, rr, bb);
+    return bb > 0.0 ? std::sqrt(rr) / std::sqrt(bb) : std::sqrt(rr);
 }
 
 spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
                         spmvc_cg_stat &stat, hipStream_t s) {
     const int64_t n = M->n_rows;
-    Solver sv(s);
+    Solver sv(s, spmv_dot_blocks(M));
     DevBuf r, p, q;
     r.alloc(sizeof(double) * std::max<int64_t>(n, 1));
     p.alloc(sizeof(double) * std::max<int64_t>(n, 1));
@@ -319,12 +365,14 @@ spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, con
     return static_cast<spmvc_status>(h.status);
 }
 
-// Mixed precision: FP64 residual / update outside, FP32-SpMV CG inside.
+// Mixed precision: FP64 residual / update outside, FP32-SpMV CG inside.  The
+// inner tolerance is inner_rtol, loosened for the last step to what the outer
+// tolerance still needs (0.9 rtol ||b|| / ||r||), so no step over-solves.
 spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
                          spmvc_cg_stat &stat, hipStream_t s) {
     const int64_t n = M->n_rows;
     const int64_t nn = std::max<int64_t>(n, 1);
-    Solver sv(s);
+    Solver sv(s, spmv_dot_blocks(M));
     DevBuf r64, q64, r32, p32, q32, d32;
     r64.alloc(sizeof(double) * nn);
     q64.alloc(sizeof(double) * nn);
@@ -332,28 +380,29 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
     p32.alloc(sizeof(float) * nn);
     q32.alloc(sizeof(float) * nn);
     d32.alloc(sizeof(float) * nn);
-    const unsigned g = rgrid(n);
     SPMVC_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn, s));
-    k_norm2<<<g, kRT, 0, s>>>(n, b, sv.partials.as<double>(), sv.st());
-    SPMVC_CHECK_LAUNCH();
-    const double bnorm = std::sqrt(sv.read().aux[1]);
     int inner_total = 0, outer = 0;
     spmvc_status st = SPMVC_ENOCONV;
-    double rel = bnorm > 0 ? 1.0 : 0.0;
-    if (bnorm == 0.0) st = SPMVC_OK;
-    while (st != SPMVC_OK && outer <= o.max_outer) {
-        launch_spmv(M, SPMVC_F64, x, q64.p, s);
-        k_residual<<<g, kRT, 0, s>>>(n, b, q64.as<double>(), r64.as<double>(), sv.partials.as<double>(), sv.st());
-        SPMVC_CHECK_LAUNCH();
-        rel = std::sqrt(sv.read().aux[0]) / bnorm;
+    double rel = 1.0;
+    while (outer <= o.max_outer) {
+        double rr, bb;
+        residual(M, sv, b, x, q64.as<double>(), r64.as<double>(), rr, bb);
+        const double bnorm = std::sqrt(bb);
+        if (bnorm == 0.0) {
+            rel = 0.0;
+            st = SPMVC_OK;
+            break;
+        }
+        rel = std::sqrt(rr) / bnorm;
         if (rel <= o.rtol) {
             st = SPMVC_OK;
             break;
         }
         if (outer == o.max_outer || inner_total >= o.max_iter) break;
         ++outer;
+        const double inner_tol = std::max(o.inner_rtol, 0.9 * o.rtol / rel);
         const CgScal h = run_cg<float, double>(M, sv, r64.as<double>(), d32.as<float>(), r32.as<float>(),
-                                               p32.as<float>(), q32.as<float>(), o.inner_rtol,
+                                               p32.as<float>(), q32.as<float>(), std::min(inner_tol, 0.5),
                                                std::max(1, o.max_iter - inner_total), o.check_every);
         inner_total += h.iters;
         if (h.status == SPMVC_ENOTSPD || h.status == SPMVC_EINVAL) {

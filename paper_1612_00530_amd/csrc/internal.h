@@ -68,10 +68,22 @@ struct LdsPlan {
     int64_t lo[kMaxWindows] = {}; // window w holds x[r0+lo[w] .. r0+rows-1+hi[w]]
     int32_t len[kMaxWindows] = {};
     int32_t base[kMaxWindows] = {}; // element offset of window w in LDS
-    int32_t total = 0;            // LDS elements
+    int32_t total = 0;            // LDS elements of the x windows
     bool tab_in_lds = false;      // table small enough to copy into LDS per block
-    DevBuf tab;                   // uint16 [P][width]: LDS element index of each displacement
+    DevBuf tab;                   // uint16 [P][width+1]: length, then LDS element index per entry
+    // register kernel (patterns of at most kRegW entries): rows of kRegTw uint16 =
+    // length, then the LDS *byte* offset of each entry; entries past the length
+    // point at a window of `rows` zeros, so every row runs the same kRegW steps.
+    bool reg = false;
+    int32_t zero_base = 0;        // element offset of the zero window (after the x windows)
+    bool reg_tab_in_lds = false;
+    DevBuf reg_tab64, reg_tab32;  // byte offsets for FP64 and FP32 elements
+    bool v_finite = false;        // every value-table entry finite (v * 0 == 0)
+    bool v_same_lo = false;       // value-table entries share their low 32 bits
 };
+
+constexpr int kRegW = 32;   // longest pattern the register kernel takes
+constexpr int kRegTw = 40;  // uint16 per register-table row (80 bytes, 16-byte aligned)
 
 }  // namespace spmvc
 
@@ -113,6 +125,11 @@ void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStr
 void launch_spmv_block(const spmvc_matrix_s *M, int dt, int nrhs, const void *X, int64_t ldx,
                        void *Y, int64_t ldy, hipStream_t s, const int *skip = nullptr);
 int64_t stream_bytes(const spmvc_matrix_s *M, int dt);
+// y = A x that also writes one partial of x.y per block into dot (FP64); returns
+// the number of partials (= spmv_dot_blocks(M)).  Used by CG for p.Ap.
+unsigned launch_spmv_dot(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s,
+                         const int *skip, double *dot);
+int64_t spmv_dot_blocks(const spmvc_matrix_s *M);
 
 // cg.hip
 spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,

@@ -7,20 +7,28 @@
 //   DIT  ID [n_pad], T u8 [K][n_pad]        (pattern ID + terminal indices)
 // One lane owns one row.  A row's entries are consumed in the canonical order
 // of Section V: first all entries of V[0] (positions < T[0]), then V[1], ...,
-// then the raw FP64 entries; the value of a run is a wave-uniform scalar, so
-// the decode costs one compare per entry.
+// then the raw FP64 entries.
 //
 // DIT with LDS staging: for a block of R consecutive rows [r0, r0+R) every
 // displacement d of the pattern table reads x[r0+d .. r0+R-1+d].  The sorted
 // set of displacements is cut into a few dense windows (for the 27-point stencil:
 // one per z-plane), each window is loaded into LDS once with coalesced loads,
-// and the pattern table is re-expressed as LDS element indices (uint16).  The
-// gather x[row + d] -- the indirect access the paper names as its bottleneck --
+// and the pattern table is re-expressed as LDS offsets (uint16).  The gather
+// x[row + d] -- the indirect access the paper names as its bottleneck --
 // becomes an LDS read.
+//
+// The register kernel (k_dit_reg) holds a row's whole pattern (at most 32
+// entries, 80 bytes) in registers, so its 32 LDS reads are independent and
+// issue back to back.  Per entry it costs one add (offset + row), one LDS read,
+// one compare against T and one select of the value, and one FMA.  Rows shorter
+// than 32 read a zero window in LDS for the missing entries (exact when every
+// table value is finite); patterns with raw values use a per-entry predicate.
 //
 // Escape rows (plain CSR) are served by extra blocks appended to the same grid;
 // the main blocks skip them (ID == all-ones, or column -2 in slot 0).
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <set>
 
 #include "internal.h"
@@ -30,7 +38,7 @@ namespace {
 
 struct SpmvArgs {
     int64_t n_rows, n_cols, n_pad;
-    int32_t K, width, P, raw_present;
+    int32_t K, width, P, raw_present, id_bytes;
     const void *ids;
     const uint8_t *T;
     const int32_t *pat_off;
@@ -45,6 +53,7 @@ struct SpmvArgs {
     int64_t n_esc;
     unsigned n_main_blocks;
     const int *skip; // optional: when *skip != 0 the launch does nothing (solver done)
+    double *dot;     // optional: per-block partial of x.y (x at the row, y the result), FP64
     double V[kMaxK];
     float V32[kMaxK];
     // LDS plan (DIT)
@@ -52,8 +61,11 @@ struct SpmvArgs {
     int64_t win_lo[kMaxWindows];
     int32_t win_len[kMaxWindows];
     int32_t win_base[kMaxWindows];
-    const uint16_t *tab; // [P][width+1]: len, then LDS indices
+    const uint16_t *tab; // [P][width+1]: len, then LDS element indices
     int32_t tab_elems;
+    int32_t zero_base, zero_len;   // register kernel: zero window
+    const uint16_t *reg_tab;       // [P][kRegTw]: len, then LDS byte offsets
+    int32_t lds_x_bytes;           // bytes of windows + zero window (16-byte multiple)
 };
 
 template <class Real> __device__ __forceinline__ Real vtab(const SpmvArgs &a, int c);
@@ -64,11 +76,33 @@ template <class T> __device__ __forceinline__ T ldg_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
-// One escape row per thread: plain CSR, columns ascending.
+// Sum over the kBlock threads of a block, in a fixed order; valid in every thread.
+__device__ __forceinline__ double block_sum_256(double v) {
+    __shared__ double sh[kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
+    return s;
+}
+
+// Writes the block's partial of x.y when the launch asks for it (all threads call).
+__device__ __forceinline__ void emit_dot(const SpmvArgs &a, double part) {
+    if (!a.dot) return;
+    const double b = block_sum_256(part);
+    if (threadIdx.x == 0) a.dot[blockIdx.x] = b;
+}
+
+// One escape row per thread: plain CSR, columns ascending.  Returns x_row * y_row
+// (first right-hand side) for the optional dot product.
 template <class Real, int NR>
-__device__ __forceinline__ void escape_row(const SpmvArgs &a, int64_t e, int nrhs, const Real *__restrict__ x,
-                                           int64_t ldx, Real *__restrict__ y, int64_t ldy) {
-    if (e >= a.n_esc) return;
+__device__ __forceinline__ double escape_row(const SpmvArgs &a, int64_t e, int nrhs, const Real *__restrict__ x,
+                                             int64_t ldx, Real *__restrict__ y, int64_t ldy) {
+    if (e >= a.n_esc) return 0.0;
     const int64_t row = a.esc_rows[e];
     const Real *ev = static_cast<const Real *>(a.esc_val);
     Real acc[NR];
@@ -84,9 +118,14 @@ __device__ __forceinline__ void escape_row(const SpmvArgs &a, int64_t e, int nrh
 #pragma unroll
     for (int r = 0; r < NR; ++r)
         if (NR == 1 || r < nrhs) y[row * ldy + r] = acc[r];
+    return a.dot ? static_cast<double>(x[row * ldx]) * static_cast<double>(acc[0]) : 0.0;
 }
 
 template <class IdT> __device__ __forceinline__ constexpr IdT esc_id() { return static_cast<IdT>(~static_cast<IdT>(0)); }
+
+template <int FMT, class Real, class IdT, bool RAW, int NR>
+__device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int nrhs, const Real *__restrict__ x,
+                                             int64_t ldx, Real *__restrict__ y, int64_t ldy);
 
 // ---- direct-gather kernel: every format, 1..16 right-hand sides --------------------
 // FMT: SPMVC_FMT_ELL / DT / DIT.  NR: compile-time RHS capacity (runtime nrhs <= NR).
@@ -95,12 +134,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_direct(SpmvArgs a, int nrhs, co
                                                          int64_t ldx, Real *__restrict__ y, int64_t ldy) {
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
-        escape_row<Real, NR>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, nrhs, x,
-                             ldx, y, ldy);
+        emit_dot(a, escape_row<Real, NR>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
+                                         nrhs, x, ldx, y, ldy));
         return;
     }
     const int64_t row = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (row >= a.n_rows) return;
+    double dotc = 0.0;
+    if (row < a.n_rows) dotc = direct_row<FMT, Real, IdT, RAW, NR>(a, row, nrhs, x, ldx, y, ldy);
+    emit_dot(a, dotc);
+}
+
+// One row of the direct kernel; returns x_row * y_row (first right-hand side).
+template <int FMT, class Real, class IdT, bool RAW, int NR>
+__device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int nrhs, const Real *__restrict__ x,
+                                             int64_t ldx, Real *__restrict__ y, int64_t ldy) {
     Real acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = Real(0);
@@ -113,23 +160,38 @@ __global__ __launch_bounds__(kBlock) void k_spmv_direct(SpmvArgs a, int nrhs, co
     };
 
     if constexpr (FMT == SPMVC_FMT_ELL) {
-        if (a.cols[row] == kEscapeColumn) return;
-        for (int k = 0; k < a.width; ++k) {
+        if (a.cols[row] == kEscapeColumn) return 0.0;
+        // Slots are read four at a time with no data-dependent exit, so the
+        // column and value loads of a group are all in flight together.
+        int k = 0;
+        for (; k + 4 <= a.width; k += 4) {
+            int32_t c[4];
+            double v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t o = static_cast<int64_t>(k + j) * a.n_pad + row;
+                c[j] = ldg_stream(a.cols + o);
+                v[j] = ldg_stream(a.ell_val + o);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c[j] >= 0) apply(static_cast<Real>(v[j]), c[j]);
+        }
+        for (; k < a.width; ++k) {
             const int64_t o = static_cast<int64_t>(k) * a.n_pad + row;
             const int32_t c = ldg_stream(a.cols + o);
-            if (c < 0) break;
-            apply(static_cast<Real>(ldg_stream(a.ell_val + o)), c);
+            if (c >= 0) apply(static_cast<Real>(ldg_stream(a.ell_val + o)), c);
         }
     } else {
         const int32_t *pat = nullptr;
         int len = 0;
         if constexpr (FMT == SPMVC_FMT_DIT) {
             const IdT id = static_cast<const IdT *>(a.ids)[row];
-            if (id == esc_id<IdT>()) return;
+            if (id == esc_id<IdT>()) return 0.0;
             pat = a.pat_off + static_cast<int64_t>(id) * a.width;
             len = a.pat_len[id];
         } else {
-            if (a.cols[row] == kEscapeColumn) return;
+            if (a.cols[row] == kEscapeColumn) return 0.0;
             len = a.width;
         }
         auto column = [&](int k) -> int64_t {
@@ -157,35 +219,59 @@ __global__ __launch_bounds__(kBlock) void k_spmv_direct(SpmvArgs a, int nrhs, co
 #pragma unroll
     for (int r = 0; r < NR; ++r)
         if (NR == 1 || r < nrhs) y[row * ldy + r] = acc[r];
+    return a.dot ? static_cast<double>(x[row * ldx]) * static_cast<double>(acc[0]) : 0.0;
 }
 
-// ---- DIT with x windows staged in LDS (single right-hand side) ----------------------
+// Load the block's x windows (and the zero window) into LDS.  The windows are
+// contiguous in LDS, so element f of the flat LDS range maps to global index
+// f + (r0 + lo[w] - base[w]) of its window w.  Loads are issued eight at a
+// time with clamped addresses (a window slot outside [0, n_cols) is never read
+// by a stored entry), so they are all in flight together.
+template <class Real>
+__device__ __forceinline__ void stage_windows(const SpmvArgs &a, const Real *__restrict__ x, Real *xs, int64_t r0) {
+    const int total = a.lds_total;
+    const int64_t last = a.n_cols - 1;
+    auto gidx = [&](int f) -> int64_t {
+        int64_t d = r0 + a.win_lo[0] - a.win_base[0];
+        for (int w = 1; w < a.n_win; ++w)
+            if (f >= a.win_base[w]) d = r0 + a.win_lo[w] - a.win_base[w];
+        const int64_t g = f + d;
+        return g < 0 ? 0 : (g > last ? last : g);
+    };
+    constexpr int B = 8;
+    int f = threadIdx.x;
+    for (; f + (B - 1) * kBlock < total; f += B * kBlock) {
+        Real v[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) v[j] = x[gidx(f + j * kBlock)];
+#pragma unroll
+        for (int j = 0; j < B; ++j) xs[f + j * kBlock] = v[j];
+    }
+    for (; f < total; f += kBlock) xs[f] = x[gidx(f)];
+    for (int e = threadIdx.x; e < a.zero_len; e += kBlock) xs[a.zero_base + e] = Real(0);
+}
+
+// ---- DIT, LDS windows, generic walk (any K, raw values, any pattern length) --------
 template <class Real, class IdT, bool RAW, bool TAB_LDS>
 __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
-        escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, 1, x, 1, y, 1);
+        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
+                                        1, x, 1, y, 1));
         return;
     }
     extern __shared__ __align__(16) unsigned char smem[];
     Real *xs = reinterpret_cast<Real *>(smem);
     uint16_t *tab_s = reinterpret_cast<uint16_t *>(smem + sizeof(Real) * a.lds_total);
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * a.rows;
-    for (int w = 0; w < a.n_win; ++w) {
-        const int64_t g0 = r0 + a.win_lo[w];
-        Real *dst = xs + a.win_base[w];
-        const int n = a.win_len[w];
-        for (int e = threadIdx.x; e < n; e += kBlock) {
-            const int64_t g = g0 + e;
-            dst[e] = (g >= 0 && g < a.n_cols) ? x[g] : Real(0);
-        }
-    }
+    stage_windows<Real>(a, x, xs, r0);
     if constexpr (TAB_LDS) {
         for (int e = threadIdx.x; e < a.tab_elems; e += kBlock) tab_s[e] = a.tab[e];
     }
     __syncthreads();
     const uint16_t *tab = TAB_LDS ? tab_s : a.tab;
     const int tw = a.width + 1;
+    double dotc = 0.0;
     for (int rel = threadIdx.x; rel < a.rows; rel += kBlock) {
         const int64_t row = r0 + rel;
         if (row >= a.n_rows) break;
@@ -207,12 +293,120 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
             for (; k < len; ++k) acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xr[t[k]], acc);
         }
         y[row] = acc;
+        if (a.dot) dotc += static_cast<double>(x[row]) * static_cast<double>(acc);
     }
+    emit_dot(a, dotc);
 }
 
-template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *skip) {
+// ---- DIT, LDS windows, pattern held in registers (patterns of <= 32 entries) -------
+// KK = 1 or 2: value table of KK entries, no raw values, short rows padded with
+// zero-window entries.  KK = 0: no value table, every value raw, entries past
+// the row length masked.  SAME_LO: the table's values share their low 32 bits,
+// so a value is picked by selecting only its high word.  RPT rows per thread
+// (rows per block = 256 * RPT); each thread's row IDs and T are loaded before
+// the windows are staged, so their latency overlaps the staging.
+__device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
+    if (id_bytes == 1) return static_cast<const uint8_t *>(ids)[row];
+    if (id_bytes == 2) return static_cast<const uint16_t *>(ids)[row];
+    return static_cast<const uint32_t *>(ids)[row];
+}
+
+template <class Real, int KK, bool TAB_LDS, bool SAME_LO, int RPT>
+__global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
+    if (a.skip && *a.skip) return;
+    if (blockIdx.x >= a.n_main_blocks) {
+        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
+                                        1, x, 1, y, 1));
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    Real *xs = reinterpret_cast<Real *>(smem);
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * (kBlock * RPT);
+    double dotc = 0.0;
+    const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+
+    uint32_t idv[RPT];
+    int t0v[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int64_t row = r0 + threadIdx.x + j * kBlock;
+        const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
+        idv[j] = load_id(a.ids, a.id_bytes, rc);
+        t0v[j] = KK >= 1 ? static_cast<int>(a.T[rc]) : 0;
+    }
+    stage_windows<Real>(a, x, xs, r0);
+    uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
+    if constexpr (TAB_LDS) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.reg_tab);
+        const int n16 = a.P * (kRegTw * 2 / 16);
+        for (int e = threadIdx.x; e < n16; e += kBlock) tab_s[e] = src[e];
+    }
+    __syncthreads();
+    const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
+
+    const double v0 = a.V[0], v1 = a.V[KK >= 2 ? 1 : 0];
+    const float f0 = a.V32[0], f1 = a.V32[KK >= 2 ? 1 : 0];
+    const uint32_t lo = static_cast<uint32_t>(__double_as_longlong(v0));
+    const uint32_t hi0 = static_cast<uint32_t>(__double_as_longlong(v0) >> 32);
+    const uint32_t hi1 = static_cast<uint32_t>(__double_as_longlong(v1) >> 32);
+
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rel = threadIdx.x + j * kBlock;
+        const int64_t row = r0 + rel;
+        if (row >= a.n_rows || idv[j] == esc) continue;
+        const uint4 *tp = tab + static_cast<int64_t>(idv[j]) * (kRegTw * 2 / 16);
+        uint32_t w[20];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const uint4 u = tp[q];
+            w[4 * q + 0] = u.x;
+            w[4 * q + 1] = u.y;
+            w[4 * q + 2] = u.z;
+            w[4 * q + 3] = u.w;
+        }
+        const int len = static_cast<int>(w[0] & 0xFFFFu);
+        const uint32_t relb = static_cast<uint32_t>(rel) * sizeof(Real);
+        const int t0 = t0v[j];
+        const Real *raw = static_cast<const Real *>(a.raw);
+        const int64_t rb = KK == 0 ? a.raw_slice[row / kSlice] + (row % kSlice) : 0;
+        Real acc = Real(0);
+#pragma unroll
+        for (int k = 0; k < kRegW; ++k) {
+            const uint32_t word = w[(k + 1) >> 1];
+            const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
+            if constexpr (KK == 0) {
+                if (k < len) {
+                    const Real xv = *reinterpret_cast<const Real *>(smem + relb + off);
+                    acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xv, acc);
+                }
+            } else {
+                const Real xv = *reinterpret_cast<const Real *>(smem + relb + off);
+                Real v;
+                if constexpr (KK == 1) {
+                    if constexpr (sizeof(Real) == 8) v = v0; else v = f0;
+                } else if constexpr (sizeof(Real) == 8) {
+                    if constexpr (SAME_LO)
+                        v = __hiloint2double(static_cast<int>(k < t0 ? hi0 : hi1), static_cast<int>(lo));
+                    else
+                        v = k < t0 ? v0 : v1;
+                } else {
+                    v = k < t0 ? f0 : f1;
+                }
+                acc = fma(v, xv, acc);
+            }
+        }
+        (void)len;
+        y[row] = acc;
+        if (a.dot) dotc += static_cast<double>(x[row]) * static_cast<double>(acc);
+    }
+    emit_dot(a, dotc);
+}
+
+template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *skip, double *dot) {
     SpmvArgs a{};
     a.skip = skip;
+    a.dot = dot;
     a.n_rows = M->n_rows;
     a.n_cols = M->n_cols;
     a.n_pad = M->n_pad;
@@ -220,6 +414,7 @@ template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *ski
     a.width = M->width;
     a.P = M->P;
     a.raw_present = M->raw_elems > 0;
+    a.id_bytes = M->id_bytes;
     a.ids = M->ids.p;
     a.T = M->T.as<uint8_t>();
     a.pat_off = M->pat_off.as<int32_t>();
@@ -279,6 +474,15 @@ void launch_direct_nr(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     SPMVC_CHECK_LAUNCH();
 }
 
+// Which register-kernel variant fits the matrix: 0 = none, else KK + 1.
+int reg_variant(const spmvc_matrix_s *M) {
+    const LdsPlan &p = M->plan;
+    if (!p.reg) return 0;
+    if (M->K == 0 && M->raw_elems > 0) return 1;                       // KK = 0
+    if ((M->K == 1 || M->K == 2) && M->raw_elems == 0 && p.v_finite) return M->K + 1;
+    return 0;
+}
+
 template <class Real>
 void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hipStream_t s) {
     const LdsPlan &p = M->plan;
@@ -290,14 +494,56 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
         a.win_len[w] = p.len[w];
         a.win_base[w] = p.base[w];
     }
-    a.tab = p.tab.as<uint16_t>();
-    a.tab_elems = M->P * (M->width + 1);
     a.n_main_blocks = static_cast<unsigned>((M->n_rows + p.rows - 1) / p.rows);
     const unsigned grid = a.n_main_blocks + escape_blocks(M);
-    size_t shmem = sizeof(Real) * static_cast<size_t>(p.total);
-    if (p.tab_in_lds) shmem += sizeof(uint16_t) * static_cast<size_t>(a.tab_elems) + 16;
     const Real *xp = static_cast<const Real *>(x);
     Real *yp = static_cast<Real *>(y);
+    const int rv = reg_variant(M);
+    if (rv > 0) {
+        const bool f64 = sizeof(Real) == 8;
+        a.zero_base = p.zero_base;
+        a.zero_len = p.rows;
+        a.reg_tab = f64 ? p.reg_tab64.as<uint16_t>() : p.reg_tab32.as<uint16_t>();
+        const int x_bytes = static_cast<int>(sizeof(Real)) * (p.zero_base + p.rows);
+        a.lds_x_bytes = (x_bytes + 15) & ~15;
+        size_t shmem = a.lds_x_bytes;
+        if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
+        const bool same_lo = p.v_same_lo;
+        const int rpt = p.rows / kBlock;
+#define SPMVC_REG_R(KK, TL, SL)                                                                                 \
+    if (rpt == 1)                                                                                               \
+        k_dit_reg<Real, KK, TL, SL, 1><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
+    else if (rpt == 2)                                                                                          \
+        k_dit_reg<Real, KK, TL, SL, 2><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
+    else if (rpt == 4)                                                                                          \
+        k_dit_reg<Real, KK, TL, SL, 4><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
+    else                                                                                                        \
+        k_dit_reg<Real, KK, TL, SL, 8><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+#define SPMVC_REG_T(KK, SL)          \
+    if (p.reg_tab_in_lds) {          \
+        SPMVC_REG_R(KK, true, SL)    \
+    } else {                         \
+        SPMVC_REG_R(KK, false, SL)   \
+    }
+        if (rv == 1) {
+            SPMVC_REG_T(0, false)
+        } else if (rv == 2) {
+            SPMVC_REG_T(1, false)
+        } else if (same_lo && sizeof(Real) == 8) {
+            SPMVC_REG_T(2, true)
+        } else {
+            SPMVC_REG_T(2, false)
+        }
+#undef SPMVC_REG_T
+#undef SPMVC_REG_R
+        SPMVC_CHECK_LAUNCH();
+        return;
+    }
+    a.zero_len = 0;
+    a.tab = p.tab.as<uint16_t>();
+    a.tab_elems = M->P * (M->width + 1);
+    size_t shmem = sizeof(Real) * static_cast<size_t>(p.total);
+    if (p.tab_in_lds) shmem += sizeof(uint16_t) * static_cast<size_t>(a.tab_elems) + 16;
     const bool raw = M->raw_elems > 0;
 #define SPMVC_LDS(IDT)                                                                                \
     if (raw) {                                                                                        \
@@ -324,8 +570,8 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
 
 template <class Real>
 void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                    hipStream_t s, const int *skip) {
-    SpmvArgs a = make_args<Real>(M, skip);
+                    hipStream_t s, const int *skip, double *dot = nullptr) {
+    SpmvArgs a = make_args<Real>(M, skip, dot);
     if (nrhs == 1)
         launch_direct_nr<Real, 1>(M, a, 1, X, ldx, Y, ldy, s);
     else if (nrhs <= 4)
@@ -336,26 +582,37 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
         launch_direct_nr<Real, 16>(M, a, nrhs, X, ldx, Y, ldy, s);
 }
 
+bool uses_lds(const spmvc_matrix_s *M) {
+    return M->fmt == SPMVC_FMT_DIT && M->lds_mode == 1 && M->plan.n_win > 0 && M->P > 0;
+}
+
 template <class Real>
-void launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStream_t s, const int *skip) {
+void launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStream_t s, const int *skip,
+                   double *dot = nullptr) {
     if (M->n_rows == 0) return;
-    if (M->fmt == SPMVC_FMT_DIT && M->lds_mode == 1 && M->plan.n_win > 0 && M->P > 0) {
-        launch_lds<Real>(M, make_args<Real>(M, skip), x, y, s);
+    if (uses_lds(M)) {
+        launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
         return;
     }
-    launch_block_t<Real>(M, 1, x, 1, y, 1, s, skip);
+    launch_block_t<Real>(M, 1, x, 1, y, 1, s, skip, dot);
 }
 
 }  // namespace
 
-// Cut the displacement set into dense windows for `rows` rows per block.
+// Cut the displacement set into dense windows for `rows` rows per block and
+// express the pattern table in LDS offsets.  All LDS use stays within
+// kLdsBudgetBytes for FP64 elements (FP32 uses half of the x part).
 void build_lds_plan(spmvc_matrix_s *M, int rows) {
     LdsPlan &p = M->plan;
     p.tab.release();
+    p.reg_tab64.release();
+    p.reg_tab32.release();
     p.rows = rows;
     p.n_win = 0;
     p.total = 0;
     p.tab_in_lds = false;
+    p.reg = false;
+    p.reg_tab_in_lds = false;
     if (M->fmt != SPMVC_FMT_DIT || M->P == 0 || M->width == 0) return;
     const int W = M->width;
     std::set<int64_t> ds;
@@ -381,17 +638,20 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
         total += len[w];
     }
     if (total * static_cast<int64_t>(sizeof(double)) > kLdsBudgetBytes || total > 65535) return;
+    auto lds_index = [&](int64_t d) -> int64_t {
+        size_t w = 0;
+        while (!(d >= win[w].first && d <= win[w].second)) ++w;
+        return base[w] + d - lo[w];
+    };
+    // walk-kernel table: [len, element index...]
     const int64_t tab_bytes = static_cast<int64_t>(M->P) * (W + 1) * static_cast<int64_t>(sizeof(uint16_t));
     std::vector<uint16_t> tab(static_cast<size_t>(M->P) * (W + 1), 0);
     for (int q = 0; q < M->P; ++q) {
         const int L = M->h_pat_len[q];
         tab[static_cast<size_t>(q) * (W + 1)] = static_cast<uint16_t>(L);
-        for (int k = 0; k < L; ++k) {
-            const int64_t d = M->h_pat_off[static_cast<size_t>(q) * W + k];
-            size_t w = 0;
-            while (!(d >= win[w].first && d <= win[w].second)) ++w;
-            tab[static_cast<size_t>(q) * (W + 1) + 1 + k] = static_cast<uint16_t>(base[w] + d - lo[w]);
-        }
+        for (int k = 0; k < L; ++k)
+            tab[static_cast<size_t>(q) * (W + 1) + 1 + k] =
+                static_cast<uint16_t>(lds_index(M->h_pat_off[static_cast<size_t>(q) * W + k]));
     }
     p.tab.alloc(sizeof(uint16_t) * tab.size());
     SPMVC_HIP(hipMemcpy(p.tab.p, tab.data(), p.tab.bytes, hipMemcpyHostToDevice));
@@ -403,6 +663,41 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
     }
     p.total = static_cast<int32_t>(total);
     p.n_win = static_cast<int>(win.size());
+
+    // register-kernel table: [len, byte offset...] with a zero window after the x windows
+    p.v_finite = true;
+    for (int c = 0; c < M->K; ++c) p.v_finite = p.v_finite && std::isfinite(M->V[c]);
+    p.v_same_lo = true;
+    for (int c = 0; c < M->K; ++c) {
+        uint64_t b0, bc;
+        std::memcpy(&b0, &M->V[0], 8);
+        std::memcpy(&bc, &M->V[c], 8);
+        p.v_same_lo = p.v_same_lo && (static_cast<uint32_t>(b0) == static_cast<uint32_t>(bc));
+    }
+    const int64_t x_elems = total + rows;  // windows + zero window
+    const int64_t x_bytes64 = ((x_elems * 8) + 15) & ~int64_t(15);
+    const bool rows_ok = rows == 256 || rows == 512 || rows == 1024 || rows == 2048;
+    if (rows_ok && W <= kRegW && x_bytes64 <= kLdsBudgetBytes && x_elems * 8 <= 65535) {
+        const int64_t reg_tab_bytes = static_cast<int64_t>(M->P) * kRegTw * 2;
+        p.zero_base = static_cast<int32_t>(total);
+        for (int es : {8, 4}) {
+            std::vector<uint16_t> rt(static_cast<size_t>(M->P) * kRegTw, 0);
+            for (int q = 0; q < M->P; ++q) {
+                const int L = M->h_pat_len[q];
+                uint16_t *r = rt.data() + static_cast<size_t>(q) * kRegTw;
+                r[0] = static_cast<uint16_t>(L);
+                for (int k = 0; k < kRegW; ++k) {
+                    const int64_t e = k < L ? lds_index(M->h_pat_off[static_cast<size_t>(q) * W + k]) : total;
+                    r[1 + k] = static_cast<uint16_t>(e * es);
+                }
+            }
+            DevBuf &dst = es == 8 ? p.reg_tab64 : p.reg_tab32;
+            dst.alloc(sizeof(uint16_t) * rt.size());
+            SPMVC_HIP(hipMemcpy(dst.p, rt.data(), dst.bytes, hipMemcpyHostToDevice));
+        }
+        p.reg_tab_in_lds = reg_tab_bytes <= 16 * 1024 && x_bytes64 + reg_tab_bytes <= kLdsBudgetBytes;
+        p.reg = true;
+    }
 }
 
 void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s, const int *skip) {
@@ -410,6 +705,24 @@ void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStr
         launch_spmv_t<double>(M, x, y, s, skip);
     else
         launch_spmv_t<float>(M, x, y, s, skip);
+}
+
+// Blocks of the single-vector launch (main + escape): one dot partial each.
+int64_t spmv_dot_blocks(const spmvc_matrix_s *M) {
+    if (M->n_rows == 0) return 0;
+    const int64_t main = uses_lds(M) ? (M->n_rows + M->plan.rows - 1) / M->plan.rows
+                                     : (M->n_pad + kBlock - 1) / kBlock;
+    return main + escape_blocks(M);
+}
+
+unsigned launch_spmv_dot(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s, const int *skip,
+                         double *dot) {
+    if (M->n_rows == 0) return 0;
+    if (dt == SPMVC_F64)
+        launch_spmv_t<double>(M, x, y, s, skip, dot);
+    else
+        launch_spmv_t<float>(M, x, y, s, skip, dot);
+    return static_cast<unsigned>(spmv_dot_blocks(M));
 }
 
 void launch_spmv_block(const spmvc_matrix_s *M, int dt, int nrhs, const void *X, int64_t ldx, void *Y,
