@@ -44,7 +44,17 @@ bool f32_ready(const spmvc_matrix_s *M) {
     return M->f32_shadow || (M->raw_elems == 0 && M->n_esc_nnz == 0);
 }
 
+// XCDs the hardware spreads consecutive blocks over (gfx94x / gfx95x: eight).
+int xcd_count() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1;
+    const std::string arch = prop.gcnArchName;
+    return (arch.rfind("gfx94", 0) == 0 || arch.rfind("gfx95", 0) == 0) ? 8 : 1;
+}
+
 void default_plan(spmvc_matrix_s *M) {
+    M->n_xcd = xcd_count();
     if (M->fmt != SPMVC_FMT_DIT) return;
     for (int rows : {M->rows_per_block, 1024, 512, 256}) {
         build_lds_plan(M, rows);

@@ -82,8 +82,8 @@ struct LdsPlan {
     bool v_same_lo = false;       // value-table entries share their low 32 bits
 };
 
-constexpr int kRegW = 32;   // longest pattern the register kernel takes
-constexpr int kRegTw = 40;  // uint16 per register-table row (80 bytes, 16-byte aligned)
+constexpr int kRegW = 31;   // longest pattern the register kernel takes
+constexpr int kRegTw = 32;  // uint16 per register-table row (64 bytes, 16-byte aligned)
 
 }  // namespace spmvc
 
@@ -107,6 +107,7 @@ struct spmvc_matrix_s {
     int32_t lds_mode = 1; // 1 = stage in LDS when a plan fits
     spmvc::LdsPlan plan;
     int32_t block_rows = 256;   // spmv_block: rows per block
+    int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
 };
 
 namespace spmvc {

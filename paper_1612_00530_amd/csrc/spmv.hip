@@ -66,6 +66,8 @@ struct SpmvArgs {
     int32_t zero_base, zero_len;   // register kernel: zero window
     const uint16_t *reg_tab;       // [P][kRegTw]: len, then LDS byte offsets
     int32_t lds_x_bytes;           // bytes of windows + zero window (16-byte multiple)
+    int32_t n_xcd;                 // XCDs the blocks are spread over (tile mapping)
+    int32_t async_lds;             // x is 16-byte aligned: stage windows with direct LDS loads
 };
 
 template <class Real> __device__ __forceinline__ Real vtab(const SpmvArgs &a, int c);
@@ -123,6 +125,16 @@ __device__ __forceinline__ double escape_row(const SpmvArgs &a, int64_t e, int n
 
 template <class IdT> __device__ __forceinline__ constexpr IdT esc_id() { return static_cast<IdT>(~static_cast<IdT>(0)); }
 
+// Row tile of block `bid` among `nb` tiles.  Blocks are dispatched round-robin
+// over the XCDs (bid % n_xcd); each XCD is given a contiguous run of tiles so
+// that neighbouring tiles, whose x windows overlap, share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_tile(unsigned bid, unsigned nb, int n_xcd) {
+    if (n_xcd <= 1 || nb < static_cast<unsigned>(n_xcd)) return bid;
+    const unsigned q = nb / n_xcd, r = nb % n_xcd;
+    const unsigned xcd = bid % n_xcd, j = bid / n_xcd;
+    return static_cast<int64_t>(xcd) * q + min(xcd, r) + j;
+}
+
 template <int FMT, class Real, class IdT, bool RAW, int NR>
 __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int nrhs, const Real *__restrict__ x,
                                              int64_t ldx, Real *__restrict__ y, int64_t ldy);
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_direct(SpmvArgs a, int nrhs, co
                                          nrhs, x, ldx, y, ldy));
         return;
     }
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t row = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * kBlock + threadIdx.x;
     double dotc = 0.0;
     if (row < a.n_rows) dotc = direct_row<FMT, Real, IdT, RAW, NR>(a, row, nrhs, x, ldx, y, ldy);
     emit_dot(a, dotc);
@@ -222,33 +234,54 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
     return a.dot ? static_cast<double>(x[row * ldx]) * static_cast<double>(acc[0]) : 0.0;
 }
 
-// Load the block's x windows (and the zero window) into LDS.  The windows are
-// contiguous in LDS, so element f of the flat LDS range maps to global index
-// f + (r0 + lo[w] - base[w]) of its window w.  Loads are issued eight at a
-// time with clamped addresses (a window slot outside [0, n_cols) is never read
-// by a stored entry), so they are all in flight together.
+// Load the block's x windows (and the zero window) into LDS.  Each window is a
+// contiguous range of x.  Interior windows are copied with direct
+// global-to-LDS loads (16 bytes per lane, no register round trip), so every
+// load of the block is in flight at once; windows that reach past either end
+// of x (first and last blocks), or an x that is not 16-byte aligned, take the
+// register path with clamped indices (a window slot outside [0, n_cols) is
+// never read by a stored entry).  Window starts and lengths are multiples of
+// four elements, so each 16-byte chunk lies wholly inside its window.
+// One 16-byte direct global-to-LDS load per lane: the wavefront's 64 chunks
+// land contiguously at lds (a wavefront-uniform address).  The builtin exists
+// only for the GPU target; the host compilation pass sees an empty body.
+__device__ __forceinline__ void lds_load16(const void *g, void *lds) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+#else
+    (void)g;
+    (void)lds;
+#endif
+}
+
 template <class Real>
 __device__ __forceinline__ void stage_windows(const SpmvArgs &a, const Real *__restrict__ x, Real *xs, int64_t r0) {
-    const int total = a.lds_total;
-    const int64_t last = a.n_cols - 1;
-    auto gidx = [&](int f) -> int64_t {
-        int64_t d = r0 + a.win_lo[0] - a.win_base[0];
-        for (int w = 1; w < a.n_win; ++w)
-            if (f >= a.win_base[w]) d = r0 + a.win_lo[w] - a.win_base[w];
-        const int64_t g = f + d;
-        return g < 0 ? 0 : (g > last ? last : g);
-    };
-    constexpr int B = 8;
-    int f = threadIdx.x;
-    for (; f + (B - 1) * kBlock < total; f += B * kBlock) {
-        Real v[B];
-#pragma unroll
-        for (int j = 0; j < B; ++j) v[j] = x[gidx(f + j * kBlock)];
-#pragma unroll
-        for (int j = 0; j < B; ++j) xs[f + j * kBlock] = v[j];
+    constexpr int PER = 16 / sizeof(Real);  // elements per lane per direct load
+    constexpr int CH = 64 * PER;            // elements per wavefront per direct load
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool direct = false;
+    for (int w = 0; w < a.n_win; ++w) {
+        const int64_t g0 = r0 + a.win_lo[w];
+        const int n = a.win_len[w];
+        Real *dst = xs + a.win_base[w];
+        if (a.async_lds && g0 >= 0 && g0 + n <= a.n_cols) {
+            const int nch = (n + CH - 1) / CH;
+            for (int c = wave; c < nch; c += kBlock / 64) {
+                const int e = c * CH + lane * PER;
+                if (e < n) lds_load16(x + g0 + e, dst + c * CH);
+            }
+            direct = true;
+        } else {
+            const int64_t last = a.n_cols - 1;
+            for (int e = threadIdx.x; e < n; e += kBlock) {
+                int64_t g = g0 + e;
+                g = g < 0 ? 0 : (g > last ? last : g);
+                dst[e] = x[g];
+            }
+        }
     }
-    for (; f < total; f += kBlock) xs[f] = x[gidx(f)];
     for (int e = threadIdx.x; e < a.zero_len; e += kBlock) xs[a.zero_base + e] = Real(0);
+    if (direct) __builtin_amdgcn_s_waitcnt(0);  // direct loads have landed in LDS
 }
 
 // ---- DIT, LDS windows, generic walk (any K, raw values, any pattern length) --------
@@ -263,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
     extern __shared__ __align__(16) unsigned char smem[];
     Real *xs = reinterpret_cast<Real *>(smem);
     uint16_t *tab_s = reinterpret_cast<uint16_t *>(smem + sizeof(Real) * a.lds_total);
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * a.rows;
+    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * a.rows;
     stage_windows<Real>(a, x, xs, r0);
     if constexpr (TAB_LDS) {
         for (int e = threadIdx.x; e < a.tab_elems; e += kBlock) tab_s[e] = a.tab[e];
@@ -300,18 +333,47 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
 
 // ---- DIT, LDS windows, pattern held in registers (patterns of <= 32 entries) -------
 // KK = 1 or 2: value table of KK entries, no raw values, short rows padded with
-// zero-window entries.  KK = 0: no value table, every value raw, entries past
-// the row length masked.  SAME_LO: the table's values share their low 32 bits,
-// so a value is picked by selecting only its high word.  RPT rows per thread
-// (rows per block = 256 * RPT); each thread's row IDs and T are loaded before
-// the windows are staged, so their latency overlaps the staging.
+// zero-window entries.  The table lists each pattern's entries in *reverse*
+// canonical order, so a row's V[1] entries (positions >= T[0]) come first: the
+// first m = len - T[0] entries take V[1], the rest V[0].  Within a wavefront
+// positions below min(m) or from max(m) on take one value for every lane (a
+// scalar operand, no per-lane select); only positions between the two need a
+// per-lane select.  For the 27-point stencil every row has m = 1, so no entry
+// needs a select.  KK = 0: no value table, every value raw (canonical order),
+// entries past the row length masked.  RPT rows per thread (rows per block =
+// 256 * RPT); each thread's row IDs and T are loaded before the windows are
+// staged, so their latency overlaps the staging.  MAXW: entries per row.
 __device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
     if (id_bytes == 1) return static_cast<const uint8_t *>(ids)[row];
     if (id_bytes == 2) return static_cast<const uint16_t *>(ids)[row];
     return static_cast<const uint32_t *>(ids)[row];
 }
 
-template <class Real, int KK, bool TAB_LDS, bool SAME_LO, int RPT>
+// A value known to be the same in every lane, kept in scalar registers (so it
+// can feed an FMA as a scalar operand instead of costing a per-lane select).
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(b));
+    const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
 __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
@@ -321,18 +383,20 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
     }
     extern __shared__ __align__(16) unsigned char smem[];
     Real *xs = reinterpret_cast<Real *>(smem);
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * (kBlock * RPT);
+    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * (kBlock * RPT);
     double dotc = 0.0;
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
 
     uint32_t idv[RPT];
     int t0v[RPT];
+    Real xrow[RPT];  // x at the row itself, for the optional dot product
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int64_t row = r0 + threadIdx.x + j * kBlock;
         const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
         idv[j] = load_id(a.ids, a.id_bytes, rc);
         t0v[j] = KK >= 1 ? static_cast<int>(a.T[rc]) : 0;
+        xrow[j] = a.dot ? x[rc] : Real(0);
     }
     stage_windows<Real>(a, x, xs, r0);
     uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
@@ -343,22 +407,24 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
     }
     __syncthreads();
     const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
-
-    const double v0 = a.V[0], v1 = a.V[KK >= 2 ? 1 : 0];
-    const float f0 = a.V32[0], f1 = a.V32[KK >= 2 ? 1 : 0];
-    const uint32_t lo = static_cast<uint32_t>(__double_as_longlong(v0));
-    const uint32_t hi0 = static_cast<uint32_t>(__double_as_longlong(v0) >> 32);
-    const uint32_t hi1 = static_cast<uint32_t>(__double_as_longlong(v1) >> 32);
+    Real v0, v1;
+    if constexpr (sizeof(Real) == 8) {
+        v0 = a.V[0];
+        v1 = a.V[KK >= 2 ? 1 : 0];
+    } else {
+        v0 = a.V32[0];
+        v1 = a.V32[KK >= 2 ? 1 : 0];
+    }
 
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int rel = threadIdx.x + j * kBlock;
         const int64_t row = r0 + rel;
-        if (row >= a.n_rows || idv[j] == esc) continue;
-        const uint4 *tp = tab + static_cast<int64_t>(idv[j]) * (kRegTw * 2 / 16);
-        uint32_t w[20];
+        const bool active = row < a.n_rows && idv[j] != esc;
+        const uint4 *tp = tab + static_cast<int64_t>(active ? idv[j] : 0u) * (kRegTw * 2 / 16);
+        uint32_t w[16];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
+        for (int q = 0; q < (MAXW + 8) / 8; ++q) {
             const uint4 u = tp[q];
             w[4 * q + 0] = u.x;
             w[4 * q + 1] = u.y;
@@ -366,39 +432,52 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
             w[4 * q + 3] = u.w;
         }
         const int len = static_cast<int>(w[0] & 0xFFFFu);
+        const int m = KK == 2 ? len - t0v[j] : 0;  // leading entries that take V[1]
+        int m_lo = 0, m_hi = 0;
+        if constexpr (KK == 2) {
+            m_lo = wave_min(active ? m : MAXW);
+            m_hi = wave_max(active ? m : 0);
+        }
+        if (!active) continue;
         const uint32_t relb = static_cast<uint32_t>(rel) * sizeof(Real);
-        const int t0 = t0v[j];
         const Real *raw = static_cast<const Real *>(a.raw);
         const int64_t rb = KK == 0 ? a.raw_slice[row / kSlice] + (row % kSlice) : 0;
         Real acc = Real(0);
-#pragma unroll
-        for (int k = 0; k < kRegW; ++k) {
+        auto xat = [&](int k) -> Real {
             const uint32_t word = w[(k + 1) >> 1];
             const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
-            if constexpr (KK == 0) {
-                if (k < len) {
-                    const Real xv = *reinterpret_cast<const Real *>(smem + relb + off);
-                    acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xv, acc);
-                }
+            return *reinterpret_cast<const Real *>(smem + relb + off);
+        };
+        if constexpr (KK == 0) {
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k)
+                if (k < len) acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xat(k), acc);
+        } else if (KK == 1 || m_lo == m_hi) {
+            // every lane of the wave splits at the same position: scalar values;
+            // the common splits are compiled with the split position fixed
+            const int ms = KK == 1 ? 0 : m_lo;
+            if (ms == 0) {
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k) acc = fma(v0, xat(k), acc);
+            } else if (ms == 1) {
+                acc = fma(v1, xat(0), acc);
+#pragma unroll
+                for (int k = 1; k < MAXW; ++k) acc = fma(v0, xat(k), acc);
+            } else if (ms == 2) {
+                acc = fma(v1, xat(0), acc);
+                acc = fma(v1, xat(1), acc);
+#pragma unroll
+                for (int k = 2; k < MAXW; ++k) acc = fma(v0, xat(k), acc);
             } else {
-                const Real xv = *reinterpret_cast<const Real *>(smem + relb + off);
-                Real v;
-                if constexpr (KK == 1) {
-                    if constexpr (sizeof(Real) == 8) v = v0; else v = f0;
-                } else if constexpr (sizeof(Real) == 8) {
-                    if constexpr (SAME_LO)
-                        v = __hiloint2double(static_cast<int>(k < t0 ? hi0 : hi1), static_cast<int>(lo));
-                    else
-                        v = k < t0 ? v0 : v1;
-                } else {
-                    v = k < t0 ? f0 : f1;
-                }
-                acc = fma(v, xv, acc);
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k) acc = fma(uniform(k < ms ? v1 : v0), xat(k), acc);
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) acc = fma(k < m ? v1 : v0, xat(k), acc);
         }
-        (void)len;
         y[row] = acc;
-        if (a.dot) dotc += static_cast<double>(x[row]) * static_cast<double>(acc);
+        if (a.dot) dotc += static_cast<double>(xrow[j]) * static_cast<double>(acc);
     }
     emit_dot(a, dotc);
 }
@@ -429,6 +508,7 @@ template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *ski
     a.esc_col = M->esc_col.as<int32_t>();
     a.esc_val = f32 ? M->esc_val32.p : M->esc_val.p;
     a.n_esc = M->n_esc;
+    a.n_xcd = M->n_xcd;
     for (int c = 0; c < kMaxK; ++c) {
         a.V[c] = M->V[c];
         a.V32[c] = M->V32[c];
@@ -495,6 +575,7 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
         a.win_base[w] = p.base[w];
     }
     a.n_main_blocks = static_cast<unsigned>((M->n_rows + p.rows - 1) / p.rows);
+    a.async_lds = (reinterpret_cast<uintptr_t>(x) % 16) == 0;
     const unsigned grid = a.n_main_blocks + escape_blocks(M);
     const Real *xp = static_cast<const Real *>(x);
     Real *yp = static_cast<Real *>(y);
@@ -508,34 +589,39 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
         a.lds_x_bytes = (x_bytes + 15) & ~15;
         size_t shmem = a.lds_x_bytes;
         if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
-        const bool same_lo = p.v_same_lo;
         const int rpt = p.rows / kBlock;
-#define SPMVC_REG_R(KK, TL, SL)                                                                                 \
-    if (rpt == 1)                                                                                               \
-        k_dit_reg<Real, KK, TL, SL, 1><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
-    else if (rpt == 2)                                                                                          \
-        k_dit_reg<Real, KK, TL, SL, 2><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
-    else if (rpt == 4)                                                                                          \
-        k_dit_reg<Real, KK, TL, SL, 4><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
+        const bool w28 = M->width <= 28;
+#define SPMVC_REG_W(KK, TL, R)                                                                                  \
+    if (w28)                                                                                                    \
+        k_dit_reg<Real, KK, TL, R, 28><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
     else                                                                                                        \
-        k_dit_reg<Real, KK, TL, SL, 8><<<grid, kBlock, shmem, s>>>(a, xp, yp);
-#define SPMVC_REG_T(KK, SL)          \
-    if (p.reg_tab_in_lds) {          \
-        SPMVC_REG_R(KK, true, SL)    \
-    } else {                         \
-        SPMVC_REG_R(KK, false, SL)   \
+        k_dit_reg<Real, KK, TL, R, kRegW><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+#define SPMVC_REG_R(KK, TL)      \
+    if (rpt == 1) {              \
+        SPMVC_REG_W(KK, TL, 1)   \
+    } else if (rpt == 2) {       \
+        SPMVC_REG_W(KK, TL, 2)   \
+    } else if (rpt == 4) {       \
+        SPMVC_REG_W(KK, TL, 4)   \
+    } else {                     \
+        SPMVC_REG_W(KK, TL, 8)   \
+    }
+#define SPMVC_REG_T(KK)          \
+    if (p.reg_tab_in_lds) {      \
+        SPMVC_REG_R(KK, true)    \
+    } else {                     \
+        SPMVC_REG_R(KK, false)   \
     }
         if (rv == 1) {
-            SPMVC_REG_T(0, false)
+            SPMVC_REG_T(0)
         } else if (rv == 2) {
-            SPMVC_REG_T(1, false)
-        } else if (same_lo && sizeof(Real) == 8) {
-            SPMVC_REG_T(2, true)
+            SPMVC_REG_T(1)
         } else {
-            SPMVC_REG_T(2, false)
+            SPMVC_REG_T(2)
         }
 #undef SPMVC_REG_T
 #undef SPMVC_REG_R
+#undef SPMVC_REG_W
         SPMVC_CHECK_LAUNCH();
         return;
     }
@@ -632,8 +718,10 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
     int64_t total = 0;
     int64_t lo[kMaxWindows], base[kMaxWindows], len[kMaxWindows];
     for (size_t w = 0; w < win.size(); ++w) {
-        lo[w] = win[w].first;
-        len[w] = rows + win[w].second - win[w].first;
+        // start at a multiple of 4 elements (rows is a multiple of 256, so every
+        // block's window start is 16-byte aligned), length a multiple of 4
+        lo[w] = win[w].first - (((win[w].first % 4) + 4) % 4);
+        len[w] = (rows + win[w].second - lo[w] + 3) / 4 * 4;
         base[w] = total;
         total += len[w];
     }
@@ -641,7 +729,7 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
     auto lds_index = [&](int64_t d) -> int64_t {
         size_t w = 0;
         while (!(d >= win[w].first && d <= win[w].second)) ++w;
-        return base[w] + d - lo[w];
+        return base[w] + d - lo[w];  // lo[w] <= win[w].first
     };
     // walk-kernel table: [len, element index...]
     const int64_t tab_bytes = static_cast<int64_t>(M->P) * (W + 1) * static_cast<int64_t>(sizeof(uint16_t));
@@ -686,8 +774,11 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
                 const int L = M->h_pat_len[q];
                 uint16_t *r = rt.data() + static_cast<size_t>(q) * kRegTw;
                 r[0] = static_cast<uint16_t>(L);
+                // dictionary kernels take the entries in reverse canonical order
+                const bool rev = M->K >= 1;
                 for (int k = 0; k < kRegW; ++k) {
-                    const int64_t e = k < L ? lds_index(M->h_pat_off[static_cast<size_t>(q) * W + k]) : total;
+                    const int src = rev ? L - 1 - k : k;
+                    const int64_t e = k < L ? lds_index(M->h_pat_off[static_cast<size_t>(q) * W + src]) : total;
                     r[1 + k] = static_cast<uint16_t>(e * es);
                 }
             }
