@@ -120,6 +120,12 @@ typedef struct {
     double inner_rtol;   /* MIXED: inner FP32 solve tolerance relative to ||r||, 1e-5      */
     int32_t max_outer;   /* MIXED: refinement steps cap, default 20                        */
     int32_t check_every; /* iterations between host convergence checks, default 16         */
+    int32_t batched;     /* several systems or right-hand sides (FP64 mode): 0 = one solve  */
+                         /* after another, 1 = all pairs advanced together by batched       */
+                         /* kernels, 2 = the same with check_every iterations recorded once */
+                         /* in a hipGraph and replayed (default).  Batched kernels take DIT */
+                         /* matrices with at most two table values and no raw values;       */
+                         /* other matrices are solved one after another.                    */
 } spmvc_cg_opts;
 
 /* Per (system, rhs) result (host struct). */

@@ -50,7 +50,7 @@ class CompressOpts(ctypes.Structure):
 class CgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("batched", ctypes.c_int32)]
 
 
 class CgStat(ctypes.Structure):
@@ -249,7 +249,7 @@ def compress(row_ptr, col, val, n_cols=None, fmt="DIT", k_max=15, p_max=65535, m
 
 
 def cg_solve(mats, bs, xs=None, rtol=1e-10, max_iter=10000, mode=0, inner_rtol=1e-5, max_outer=20,
-             check_every=16, nrhs=1, stream=None):
+             check_every=16, nrhs=1, batched=2, stream=None):
     """CG on one or more systems; bs/xs: lists of CUDA float64 tensors (n,) or (n, nrhs)."""
     import torch
 
@@ -262,7 +262,7 @@ def cg_solve(mats, bs, xs=None, rtol=1e-10, max_iter=10000, mode=0, inner_rtol=1
     H = (ctypes.c_void_p * n_sys)(*[m.handle for m in mats])
     B = (ctypes.c_void_p * n_sys)(*[_dev(b, torch.float64, "b").value for b in bs])
     X = (ctypes.c_void_p * n_sys)(*[_dev(x, torch.float64, "x").value for x in xs])
-    o = CgOpts(rtol, max_iter, mode, inner_rtol, max_outer, check_every)
+    o = CgOpts(rtol, max_iter, mode, inner_rtol, max_outer, check_every, batched)
     stats = (CgStat * (n_sys * nrhs))()
     st = load().cg_solve(H, n_sys, nrhs, B, X, ctypes.byref(o), stats, _stream(stream))
     out = [{"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status,

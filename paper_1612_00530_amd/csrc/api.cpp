@@ -158,9 +158,10 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs, const 
         if (!A || !b || !x || !stat) return fail(SPMVC_EINVAL, "null argument");
         if (n_sys < 1) return fail(SPMVC_EINVAL, "n_sys must be >= 1");
         if (nrhs < 1 || nrhs > 16) return fail(SPMVC_EINVAL, "nrhs must be in 1..16");
-        spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16};
+        spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16, 2};
         if (opts) o = *opts;
-        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || (o.mode != 0 && o.mode != 1))
+        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || (o.mode != 0 && o.mode != 1) ||
+            o.batched < 0 || o.batched > 2)
             return fail(SPMVC_EINVAL, "invalid cg options");
         if (o.mode == 1 && (n_sys != 1 || nrhs != 1))
             return fail(SPMVC_EUNSUPPORTED, "mixed-precision mode takes one system with one right-hand side");

@@ -1,0 +1,545 @@
+// Batched conjugate gradients: many independent systems, each with several
+// right-hand sides, advanced together.
+//
+// Every launch covers all systems: the row tiles of all systems form one grid
+// (tile -> system through a table), so a batch of uneven systems costs the
+// same number of launches as one system.  Each (system, rhs) pair runs its own
+// textbook CG (the CG part of Table I) with its own scalars and stops at its
+// own tolerance; a finished pair is frozen and a system whose pairs are all
+// finished drops out of the tile loops.
+//
+// One iteration is five launches:
+//   bspmv      Q = A_s P for the active systems (one lane per row, all nrhs
+//              right-hand sides of the row-interleaved block per decoded entry)
+//              and per-tile partials of p.q for every rhs;
+//   fin_alpha  one block per system: sigma = sum of its tiles' partials (fixed
+//              order), alpha = rho / sigma, breakdown test;
+//   update     X += alpha P, R -= alpha Q for the active pairs; partials of r.r;
+//   fin_beta   one block per system: rho', convergence, beta, pair/system flags;
+//   pupdate    P = R + beta P for the pairs still running.
+// All reductions are fixed-order, so results repeat exactly.  Iterations are
+// recorded once into a hipGraph and the graph is replayed; the host reads one
+// counter (active pairs) per replay.  No memset is recorded in the graph.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace spmvc {
+namespace {
+
+constexpr int kT = 256;     // threads per block = rows per tile
+constexpr int kMaxRhs = 16;
+
+struct SysDesc {
+    int64_t row0, n;   // first global row, rows
+    int64_t n_pad;
+    int64_t tile0;     // first tile
+    int32_t ntiles, K, width, id_bytes;
+    const void *ids;
+    const uint8_t *T;
+    const int32_t *pat_off;
+    const uint8_t *pat_len;
+    const int64_t *esc_rows, *esc_ptr;
+    const int32_t *esc_col;
+    const double *esc_val;
+    int64_t n_esc;
+    double V[2];
+};
+
+struct Batch {
+    const SysDesc *sys;
+    const int32_t *tile_sys;
+    int32_t n_sys, nrhs, n_tiles;
+    int64_t n_total;
+    // row-interleaved [n_total][nrhs]
+    const double *B;
+    double *X, *R, *P, *Q;
+    double *part;    // [n_tiles][nrhs]
+    // per pair (s*nrhs + r)
+    double *rho;     // [2][pairs]
+    double *rho0, *alpha, *beta, *relres;
+    int32_t *iters, *status, *done;
+    int32_t *sys_active;  // [n_sys]
+    int32_t *n_active;    // [1]: pairs still running
+    double rtol;
+    int32_t max_iter;
+};
+
+__device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
+    if (id_bytes == 1) return static_cast<const uint8_t *>(ids)[row];
+    if (id_bytes == 2) return static_cast<const uint16_t *>(ids)[row];
+    return static_cast<const uint32_t *>(ids)[row];
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[kT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kT / 64; ++i) s += sh[i];
+    return s;
+}
+
+// Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs (NR >= nrhs).
+template <int NR>
+__global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict__ Pin, double *__restrict__ Qout,
+                                              double *part, int with_dot) {
+    const int tile = blockIdx.x;
+    const int s = b.tile_sys[tile];
+    if (!b.sys_active[s]) return;  // uniform per block
+    const SysDesc &d = b.sys[s];
+    const int nr = b.nrhs;
+    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const bool valid = lrow < d.n;
+    if (valid) {
+        const int64_t grow = d.row0 + lrow;
+        const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+        const uint32_t id = load_id(d.ids, d.id_bytes, lrow);
+        auto apply = [&](double v, int64_t gcol) {
+            const double *xp = Pin + gcol * nr;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (r < nr) acc[r] = fma(v, xp[r], acc[r]);
+        };
+        if (id != esc) {
+            const int32_t *pat = d.pat_off + static_cast<int64_t>(id) * d.width;
+            const int len = d.pat_len[id];
+            int k = 0;
+            for (int c = 0; c < d.K; ++c) {
+                const int tend = d.T[static_cast<int64_t>(c) * d.n_pad + lrow];
+                const double v = d.V[c];
+                for (; k < tend; ++k) apply(v, d.row0 + lrow + pat[k]);
+            }
+            (void)len;
+        } else {
+            // escape row: position in the (ascending) escape-row list by bisection
+            int64_t lo = 0, hi = d.n_esc;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) / 2;
+                if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
+            }
+            for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) apply(d.esc_val[e], d.row0 + d.esc_col[e]);
+        }
+        double *yp = Qout + grow * nr;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r < nr) yp[r] = acc[r];
+    }
+    if (!with_dot) return;
+    const double *pp = Pin + (d.row0 + (valid ? lrow : 0)) * nr;
+    for (int r = 0; r < nr; ++r) {
+        const double c = valid ? pp[r] * acc[r] : 0.0;
+        const double t = block_sum(c);
+        if (threadIdx.x == 0) part[static_cast<int64_t>(tile) * nr + r] = t;
+    }
+}
+
+// Sum of the tiles' partials of system s for rhs r (fixed order), in every thread.
+__device__ __forceinline__ double sys_sum(const Batch &b, const SysDesc &d, int r) {
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < d.ntiles; t += kT) acc += b.part[(d.tile0 + t) * b.nrhs + r];
+    return block_sum(acc);
+}
+
+// X = 0, R = B, P = B; partials of b.b
+__global__ __launch_bounds__(kT) void k_bstart(Batch b) {
+    const int tile = blockIdx.x;
+    const int s = b.tile_sys[tile];
+    const SysDesc &d = b.sys[s];
+    const int nr = b.nrhs;
+    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
+    const bool valid = lrow < d.n;
+    const int64_t g = (d.row0 + (valid ? lrow : 0)) * nr;
+    for (int r = 0; r < nr; ++r) {
+        double v = 0.0;
+        if (valid) {
+            v = b.B[g + r];
+            b.X[g + r] = 0.0;
+            b.R[g + r] = v;
+            b.P[g + r] = v;
+        }
+        const double t = block_sum(v * v);
+        if (threadIdx.x == 0) b.part[static_cast<int64_t>(tile) * nr + r] = t;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_bstart_fin(Batch b) {
+    const int s = blockIdx.x;
+    const SysDesc &d = b.sys[s];
+    int active = 0;
+    for (int r = 0; r < b.nrhs; ++r) {
+        const double rr = sys_sum(b, d, r);
+        if (threadIdx.x == 0) {
+            const int q = s * b.nrhs + r;
+            b.rho[q] = rr;
+            b.rho[b.n_sys * b.nrhs + q] = 0.0;
+            b.rho0[q] = rr;
+            b.iters[q] = 0;
+            b.relres[q] = rr > 0.0 ? 1.0 : 0.0;
+            b.status[q] = SPMVC_OK;
+            b.done[q] = rr > 0.0 ? 0 : 1;
+            if (rr > 0.0) {
+                ++active;
+                atomicAdd(b.n_active, 1);
+            }
+        }
+    }
+    if (threadIdx.x == 0) b.sys_active[s] = active > 0 ? 1 : 0;
+}
+
+// alpha per pair (breakdown stops the pair).  rho is double-buffered by the
+// parity of the pair's own iteration count, so the kernels take no iteration
+// index and one recorded graph serves every replay.
+__global__ __launch_bounds__(kT) void k_bfin_alpha(Batch b) {
+    const int s = blockIdx.x;
+    if (!b.sys_active[s]) return;
+    const SysDesc &d = b.sys[s];
+    for (int r = 0; r < b.nrhs; ++r) {
+        const double sigma = sys_sum(b, d, r);
+        if (threadIdx.x == 0) {
+            const int q = s * b.nrhs + r;
+            if (b.done[q]) continue;
+            if (!(sigma > 0.0) || !isfinite(sigma)) {
+                b.done[q] = 1;
+                b.status[q] = SPMVC_ENOTSPD;
+                b.iters[q] += 1;
+                b.alpha[q] = 0.0;
+                atomicSub(b.n_active, 1);
+            } else {
+                b.alpha[q] = b.rho[(b.iters[q] & 1) * b.n_sys * b.nrhs + q] / sigma;
+            }
+        }
+    }
+}
+
+// X += alpha P, R -= alpha Q for running pairs; partials of r.r
+__global__ __launch_bounds__(kT) void k_bupdate(Batch b) {
+    const int tile = blockIdx.x;
+    const int s = b.tile_sys[tile];
+    if (!b.sys_active[s]) return;
+    const SysDesc &d = b.sys[s];
+    const int nr = b.nrhs;
+    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
+    const bool valid = lrow < d.n;
+    const int64_t g = (d.row0 + (valid ? lrow : 0)) * nr;
+    for (int r = 0; r < nr; ++r) {
+        const int q = s * nr + r;
+        const bool run = !b.done[q];
+        double c = 0.0;
+        if (valid && run) {
+            const double a = b.alpha[q];
+            b.X[g + r] += a * b.P[g + r];
+            const double rv = b.R[g + r] - a * b.Q[g + r];
+            b.R[g + r] = rv;
+            c = rv * rv;
+        }
+        const double t = block_sum(c);
+        if (threadIdx.x == 0) b.part[static_cast<int64_t>(tile) * nr + r] = t;
+    }
+}
+
+// rho', convergence, beta
+__global__ __launch_bounds__(kT) void k_bfin_beta(Batch b) {
+    const int s = blockIdx.x;
+    if (!b.sys_active[s]) return;
+    const SysDesc &d = b.sys[s];
+    const int np = b.n_sys * b.nrhs;
+    int still = 0;
+    for (int r = 0; r < b.nrhs; ++r) {
+        const double rho_new = sys_sum(b, d, r);
+        if (threadIdx.x == 0) {
+            const int q = s * b.nrhs + r;
+            if (b.done[q]) continue;
+            const int it = b.iters[q];
+            const int par = it & 1;
+            const double rho = b.rho[par * np + q];
+            b.iters[q] = it + 1;
+            b.relres[q] = sqrt(rho_new) / sqrt(b.rho0[q]);
+            b.rho[(par ^ 1) * np + q] = rho_new;
+            b.beta[q] = rho_new / rho;
+            int st = -1;
+            if (sqrt(rho_new) <= b.rtol * sqrt(b.rho0[q]))
+                st = SPMVC_OK;
+            else if (!isfinite(rho_new))
+                st = SPMVC_ENOTSPD;
+            else if (it + 1 >= b.max_iter)
+                st = SPMVC_ENOCONV;
+            if (st != -1) {
+                b.done[q] = 1;  // finished this step: pupdate skips it
+                b.status[q] = st;
+                atomicSub(b.n_active, 1);
+            } else {
+                ++still;
+            }
+        }
+    }
+    if (threadIdx.x == 0 && still == 0) {
+        // every pair of the system has finished (the pupdate of this step has nothing to do)
+        bool any = false;
+        for (int r = 0; r < b.nrhs; ++r) any |= (b.done[s * b.nrhs + r] == 0);
+        if (!any) b.sys_active[s] = 0;
+    }
+}
+
+// P = R + beta P for running pairs
+__global__ __launch_bounds__(kT) void k_bpupdate(Batch b) {
+    const int tile = blockIdx.x;
+    const int s = b.tile_sys[tile];
+    if (!b.sys_active[s]) return;
+    const SysDesc &d = b.sys[s];
+    const int nr = b.nrhs;
+    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
+    if (lrow >= d.n) return;
+    const int64_t g = (d.row0 + lrow) * nr;
+    for (int r = 0; r < nr; ++r) {
+        const int q = s * nr + r;
+        if (b.done[q]) continue;
+        b.P[g + r] = b.R[g + r] + b.beta[q] * b.P[g + r];
+    }
+}
+
+// partials of (b - Ax).(b - Ax) per rhs, with Ax in Q (all systems)
+__global__ __launch_bounds__(kT) void k_bresid(Batch b) {
+    const int tile = blockIdx.x;
+    const int s = b.tile_sys[tile];
+    const SysDesc &d = b.sys[s];
+    const int nr = b.nrhs;
+    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
+    const bool valid = lrow < d.n;
+    const int64_t g = (d.row0 + (valid ? lrow : 0)) * nr;
+    for (int r = 0; r < nr; ++r) {
+        const double v = valid ? b.B[g + r] - b.Q[g + r] : 0.0;
+        const double t = block_sum(v * v);
+        if (threadIdx.x == 0) b.part[static_cast<int64_t>(tile) * nr + r] = t;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_bresid_fin(Batch b, double *out) {
+    const int s = blockIdx.x;
+    const SysDesc &d = b.sys[s];
+    for (int r = 0; r < b.nrhs; ++r) {
+        const double rr = sys_sum(b, d, r);
+        if (threadIdx.x == 0) out[s * b.nrhs + r] = rr;
+    }
+}
+
+__global__ void k_set_all(int32_t *p, int32_t v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
+    const unsigned g = static_cast<unsigned>(b.n_tiles);
+    if (b.nrhs <= 1)
+        k_bspmv<1><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
+    else if (b.nrhs <= 4)
+        k_bspmv<4><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
+    else if (b.nrhs <= 8)
+        k_bspmv<8><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
+    else
+        k_bspmv<16><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
+}
+
+// One CG iteration for every running pair.
+void record_iteration(const Batch &b, hipStream_t s) {
+    const unsigned g = static_cast<unsigned>(b.n_tiles), ns = static_cast<unsigned>(b.n_sys);
+    launch_bspmv(b, b.P, b.Q, 1, s);
+    k_bfin_alpha<<<ns, kT, 0, s>>>(b);
+    k_bupdate<<<g, kT, 0, s>>>(b);
+    k_bfin_beta<<<ns, kT, 0, s>>>(b);
+    k_bpupdate<<<g, kT, 0, s>>>(b);
+}
+
+}  // namespace
+
+// Is the batched solver able to take these matrices (DIT, value table <= 2, no raw values)?
+bool batched_supported(const spmvc_matrix *A, int n_sys) {
+    for (int s = 0; s < n_sys; ++s) {
+        const spmvc_matrix_s *M = A[s];
+        if (M->fmt != SPMVC_FMT_DIT || M->K > 2 || M->raw_elems > 0 || M->n_rows != M->n_cols) return false;
+    }
+    return true;
+}
+
+spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *bvec,
+                              double *const *xvec, const spmvc_cg_opts &o, spmvc_cg_stat *stat, hipStream_t st,
+                              bool use_graph) {
+    // layout: all systems stacked, row-interleaved [n_total][nrhs]
+    std::vector<SysDesc> sd(n_sys);
+    std::vector<int32_t> tile_sys;
+    int64_t row0 = 0, tile0 = 0;
+    for (int s = 0; s < n_sys; ++s) {
+        const spmvc_matrix_s *M = A[s];
+        SysDesc &d = sd[s];
+        d.row0 = row0;
+        d.n = M->n_rows;
+        d.n_pad = M->n_pad;
+        d.tile0 = tile0;
+        d.ntiles = static_cast<int32_t>((M->n_rows + kT - 1) / kT);
+        d.K = M->K;
+        d.width = M->width;
+        d.id_bytes = M->id_bytes;
+        d.ids = M->ids.p;
+        d.T = M->T.as<uint8_t>();
+        d.pat_off = M->pat_off.as<int32_t>();
+        d.pat_len = M->pat_len.as<uint8_t>();
+        d.esc_rows = M->esc_rows.as<int64_t>();
+        d.esc_ptr = M->esc_ptr.as<int64_t>();
+        d.esc_col = M->esc_col.as<int32_t>();
+        d.esc_val = M->esc_val.as<double>();
+        d.n_esc = M->n_esc;
+        d.V[0] = M->V[0];
+        d.V[1] = M->V[1];
+        for (int t = 0; t < d.ntiles; ++t) tile_sys.push_back(s);
+        row0 += M->n_rows;
+        tile0 += d.ntiles;
+    }
+    const int64_t n_total = row0;
+    const int n_tiles = static_cast<int>(tile0);
+    const int np = n_sys * nrhs;
+    DevBuf dsys, dtile, B, X, R, P, Q, part, rho, rho0, alpha, beta, relres, iters, status, done, sact, nact, rr;
+    dsys.alloc(sizeof(SysDesc) * n_sys);
+    dtile.alloc(sizeof(int32_t) * std::max(n_tiles, 1));
+    const size_t vb = sizeof(double) * static_cast<size_t>(std::max<int64_t>(n_total, 1)) * nrhs;
+    B.alloc(vb);
+    X.alloc(vb);
+    R.alloc(vb);
+    P.alloc(vb);
+    Q.alloc(vb);
+    part.alloc(sizeof(double) * static_cast<size_t>(std::max(n_tiles, 1)) * nrhs);
+    rho.alloc(sizeof(double) * 2 * np);
+    rho0.alloc(sizeof(double) * np);
+    alpha.alloc(sizeof(double) * np);
+    beta.alloc(sizeof(double) * np);
+    relres.alloc(sizeof(double) * np);
+    rr.alloc(sizeof(double) * np * 2);
+    iters.alloc(sizeof(int32_t) * np);
+    status.alloc(sizeof(int32_t) * np);
+    done.alloc(sizeof(int32_t) * np);
+    sact.alloc(sizeof(int32_t) * n_sys);
+    nact.alloc(sizeof(int32_t));
+    SPMVC_HIP(hipMemcpyAsync(dsys.p, sd.data(), dsys.bytes, hipMemcpyHostToDevice, st));
+    SPMVC_HIP(hipMemcpyAsync(dtile.p, tile_sys.data(), sizeof(int32_t) * n_tiles, hipMemcpyHostToDevice, st));
+    for (int s = 0; s < n_sys; ++s)
+        SPMVC_HIP(hipMemcpyAsync(B.as<double>() + sd[s].row0 * nrhs, bvec[s], sizeof(double) * sd[s].n * nrhs,
+                                 hipMemcpyDeviceToDevice, st));
+    SPMVC_HIP(hipMemsetAsync(nact.p, 0, sizeof(int32_t), st));
+
+    Batch b{};
+    b.sys = dsys.as<SysDesc>();
+    b.tile_sys = dtile.as<int32_t>();
+    b.n_sys = n_sys;
+    b.nrhs = nrhs;
+    b.n_tiles = n_tiles;
+    b.n_total = n_total;
+    b.B = B.as<double>();
+    b.X = X.as<double>();
+    b.R = R.as<double>();
+    b.P = P.as<double>();
+    b.Q = Q.as<double>();
+    b.part = part.as<double>();
+    b.rho = rho.as<double>();
+    b.rho0 = rho0.as<double>();
+    b.alpha = alpha.as<double>();
+    b.beta = beta.as<double>();
+    b.relres = relres.as<double>();
+    b.iters = iters.as<int32_t>();
+    b.status = status.as<int32_t>();
+    b.done = done.as<int32_t>();
+    b.sys_active = sact.as<int32_t>();
+    b.n_active = nact.as<int32_t>();
+    b.rtol = o.rtol;
+    b.max_iter = o.max_iter;
+
+    k_bstart<<<static_cast<unsigned>(n_tiles), kT, 0, st>>>(b);
+    k_bstart_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b);
+    SPMVC_CHECK_LAUNCH();
+
+    int32_t *h_active = nullptr;
+    SPMVC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_active), sizeof(int32_t), hipHostMallocDefault));
+    struct HostFree {
+        int32_t *p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } hf{h_active};
+    auto active = [&]() {
+        SPMVC_HIP(hipMemcpyAsync(h_active, nact.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SPMVC_HIP(hipStreamSynchronize(st));
+        return *h_active;
+    };
+
+    const int chunk = std::max(1, o.check_every);
+    int it = 0;
+    if (use_graph) {
+        // `chunk` iterations recorded once, replayed until every pair has stopped
+        hipStream_t cs;
+        SPMVC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        struct StreamFree {
+            hipStream_t s;
+            ~StreamFree() { (void)hipStreamDestroy(s); }
+        } sf{cs};
+        SPMVC_HIP(hipStreamSynchronize(st));
+        hipGraph_t graph = nullptr;
+        SPMVC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < chunk; ++j) record_iteration(b, cs);
+        SPMVC_HIP(hipStreamEndCapture(cs, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        SPMVC_HIP(ie);
+        struct ExecFree {
+            hipGraphExec_t e;
+            ~ExecFree() { (void)hipGraphExecDestroy(e); }
+        } ef{exec};
+        while (it < o.max_iter && active() > 0) {
+            SPMVC_HIP(hipGraphLaunch(exec, cs));
+            SPMVC_HIP(hipStreamSynchronize(cs));
+            it += chunk;
+        }
+    } else {
+        while (it < o.max_iter && active() > 0) {
+            for (int j = 0; j < chunk; ++j) record_iteration(b, st);
+            SPMVC_CHECK_LAUNCH();
+            it += chunk;
+        }
+    }
+
+    // true residuals ||b - A x|| / ||b|| per pair
+    k_set_all<<<static_cast<unsigned>((n_sys + 255) / 256), 256, 0, st>>>(b.sys_active, 1, n_sys);
+    launch_bspmv(b, b.X, b.Q, 0, st);
+    k_bresid<<<static_cast<unsigned>(n_tiles), kT, 0, st>>>(b);
+    k_bresid_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b, rr.as<double>());
+    SPMVC_CHECK_LAUNCH();
+    std::vector<double> h_rr(np), h_rho0(np), h_rel(np);
+    std::vector<int32_t> h_it(np), h_st(np), h_done(np);
+    SPMVC_HIP(hipMemcpyAsync(h_rr.data(), rr.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    SPMVC_HIP(hipMemcpyAsync(h_rho0.data(), rho0.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    SPMVC_HIP(hipMemcpyAsync(h_rel.data(), relres.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    SPMVC_HIP(hipMemcpyAsync(h_it.data(), iters.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost, st));
+    SPMVC_HIP(hipMemcpyAsync(h_st.data(), status.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost, st));
+    SPMVC_HIP(hipMemcpyAsync(h_done.data(), done.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost, st));
+    for (int s = 0; s < n_sys; ++s)
+        SPMVC_HIP(hipMemcpyAsync(xvec[s], X.as<double>() + sd[s].row0 * nrhs, sizeof(double) * sd[s].n * nrhs,
+                                 hipMemcpyDeviceToDevice, st));
+    SPMVC_HIP(hipStreamSynchronize(st));
+    spmvc_status first_bad = SPMVC_OK;
+    for (int q = 0; q < np; ++q) {
+        spmvc_cg_stat &c = stat[q];
+        c.iters = h_it[q];
+        c.outer_iters = 0;
+        c.status = h_done[q] ? h_st[q] : SPMVC_ENOCONV;
+        c.relres_recursive = h_rel[q];
+        c.relres_true = h_rho0[q] > 0.0 ? std::sqrt(h_rr[q]) / std::sqrt(h_rho0[q]) : std::sqrt(h_rr[q]);
+        if (c.status != SPMVC_OK && first_bad == SPMVC_OK) first_bad = static_cast<spmvc_status>(c.status);
+    }
+    return first_bad;
+}
+
+}  // namespace spmvc

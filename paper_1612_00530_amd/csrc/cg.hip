@@ -430,6 +430,11 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
         SPMVC_HIP(hipStreamSynchronize(s));
         return st;
     }
+    if ((n_sys > 1 || nrhs > 1) && o.batched != 0 && batched_supported(A, n_sys)) {
+        const spmvc_status st = cg_solve_batched(A, n_sys, nrhs, b, x, o, stat, s, o.batched != 1);
+        SPMVC_HIP(hipStreamSynchronize(s));
+        return st;
+    }
     for (int sy = 0; sy < n_sys; ++sy) {
         const spmvc_matrix_s *M = A[sy];
         const int64_t n = M->n_rows;

@@ -103,7 +103,7 @@ struct spmvc_matrix_s {
     std::vector<int32_t> h_pat_off; // [P][width]
     std::vector<uint8_t> h_pat_len; // [P]
     // kernel configuration
-    int32_t rows_per_block = 1024;
+    int32_t rows_per_block = 512;
     int32_t lds_mode = 1; // 1 = stage in LDS when a plan fits
     spmvc::LdsPlan plan;
     int32_t block_rows = 256;   // spmv_block: rows per block
@@ -136,6 +136,12 @@ int64_t spmv_dot_blocks(const spmvc_matrix_s *M);
 spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                            double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,
                            hipStream_t s);
+
+// batched.hip
+bool batched_supported(const spmvc_matrix *A, int n_sys);
+spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
+                              double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,
+                              hipStream_t s, bool use_graph);
 
 // scan.hip: exclusive prefix sum of n int64 values (in may equal out); returns the total.
 int64_t exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

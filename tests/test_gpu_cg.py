@@ -110,3 +110,71 @@ def test_zero_rhs():
     A = stencil27(8, 8, 8)
     st, x, stats = solve(A, np.zeros(A.n_rows))
     assert st == 0 and stats[0]["iters"] == 0 and np.all(x == 0)
+
+
+# ---- batched CG: uneven systems x several right-hand sides ---------------------------
+
+def batched_case(grids, nrhs, seed=0):
+    torch = torch_mod()
+    mats, As, bs = [], [], []
+    rng = np.random.default_rng(seed)
+    for g in grids:
+        A = stencil27(*g)
+        As.append(A)
+        mats.append(compress(A))
+        B = rng.uniform(-1, 1, (A.n_rows, nrhs))
+        bs.append(torch.from_numpy(B).cuda())
+    return mats, As, bs
+
+
+@pytest.mark.parametrize("batched", [1, 2])
+def test_batched_matches_oracle(batched):
+    say("case: batched", batched)
+    torch = torch_mod()
+    P = lib()
+    grids = [(10, 12, 9), (16, 11, 13), (20, 7, 5), (3, 3, 3)]
+    mats, As, bs = batched_case(grids, 8)
+    st, xs, stats = P.cg_solve(mats, bs, nrhs=8, batched=batched, check_every=5)
+    torch.cuda.synchronize()
+    assert st == 0
+    for s, A in enumerate(As):
+        X = xs[s].cpu().numpy()
+        B = bs[s].cpu().numpy()
+        for r in range(8):
+            assert stats[s * 8 + r]["status"] == 0
+            assert oracle.relres(A, B[:, r], X[:, r]) <= 1.5e-10
+            _, _, it_ref, _ = oracle.cg(A, B[:, r])
+            assert abs(stats[s * 8 + r]["iters"] - it_ref) <= 2
+            assert abs(stats[s * 8 + r]["relres_true"] - oracle.relres(A, B[:, r], X[:, r])) <= 1e-12
+
+
+def test_batched_graph_replays_equal_eager():
+    """The graph path (many replays of a 3-iteration graph) equals the eager launches bit for bit."""
+    say("case: batched graph vs eager")
+    torch = torch_mod()
+    P = lib()
+    grids = [(12, 10, 8), (17, 9, 6)]
+    mats, As, bs = batched_case(grids, 5, seed=3)
+    _, x_eager, s_eager = P.cg_solve(mats, bs, nrhs=5, batched=1, check_every=3)
+    for _ in range(2):  # the graph is recorded and replayed afresh in each call
+        _, x_graph, s_graph = P.cg_solve(mats, bs, nrhs=5, batched=2, check_every=3)
+        torch.cuda.synchronize()
+        for a, b in zip(x_eager, x_graph):
+            assert torch.equal(a, b)
+        assert [s["iters"] for s in s_eager] == [s["iters"] for s in s_graph]
+
+
+def test_batched_failures_are_per_pair():
+    say("case: batched failures")
+    torch = torch_mod()
+    P = lib()
+    good = stencil27(8, 7, 6)
+    bad = stencil27(6, 6, 6)
+    bad.val[:] = -bad.val
+    mats = [compress(good), compress(bad)]
+    bs = [torch.from_numpy(np.ones((A.n_rows, 2))).cuda() for A in (good, bad)]
+    st, xs, stats = P.cg_solve(mats, bs, nrhs=2)
+    assert st == -6
+    assert [s["status"] for s in stats] == [0, 0, -6, -6]
+    st, xs, stats = P.cg_solve([mats[0]], [bs[0]], nrhs=2, max_iter=4)
+    assert st == -7 and all(s["iters"] == 4 for s in stats)
