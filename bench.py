@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--grid", type=int, default=104)
     ap.add_argument("--cg-grid", type=int, default=192)
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-irregular", action="store_true")
+    ap.add_argument("--batched-systems", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true")
@@ -173,9 +176,19 @@ def main():
                                "sample": f"{reps} full CSR SpMVs of the {g}^3 stencil matrix (FP64, OpenMP rows)"}
         log(f"[bench] CPU oracle: {out['cpu_baseline']['value']:.2f} Gflops on {oracle.threads()} threads")
 
+    # FP32 DIT SpMV of the same matrix (the inner kernel of the mixed-precision CG)
+    x32, y32 = x.float(), y.float()
+    f_mean, _, _ = time_launches(lambda: D.spmv(x32, y32), max(20, args.steps // 2), torch)
+
+    irregular = None
+    if not args.no_irregular:
+        irregular = run_irregular(P, torch, dev, args.steps)
     cg = None
     if not args.no_cg:
         cg = run_cg(args.cg_grid, P, torch, dev)
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(P, torch, dev, args.batched_systems)
 
     res = {
         "metric": "SpMV Gflops + effective HBM GB/s, compressed vs plain ELL; CG time to 1e-10",
@@ -209,10 +222,71 @@ def main():
                           "DIT_paper_widths": round(dinf["bytes_paper"] / n, 3)},
         "parity_max_rel_err": out.get("parity_max_rel_err"),
         "tuned": tuned,
+        "dit_f32": {"launch_us_mean": round(f_mean * 1000, 3), "gflops": round(2.0 * nnz / (f_mean * 1e-3) / 1e9, 2)},
+        "irregular": irregular,
         "cg": cg,
+        "batched_cg": batched,
         "paper_context_gflops_per_chip": {"uncompressed": 11.6, "compressed": 32.4, "hardware": "PEZY-SC"},
     }
     print(json.dumps(res), flush=True)
+
+
+def run_irregular(P, torch, dev, steps):
+    """SpMV on the irregularised 128^3 stencil: DIT (pattern IDs + raw values + escapes) vs ELL."""
+    from synthetic import stencil27_irregular, uniform_vector
+
+    log("[bench] irregular 128^3")
+    A = stencil27_irregular(128, 128, 128, seed=0)
+    rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+    D = P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT")
+    E = P.compress(rp, col, val, n_cols=A.n_cols, fmt="ELL")
+    del rp, col, val
+    tuned = D.tune(torch.float64)
+    x = torch.from_numpy(uniform_vector(A.n_cols, seed=0)).to(dev)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    d_us = time_launches(lambda: D.spmv(x, y), max(20, steps // 2), torch)[0] * 1000
+    e_us = time_launches(lambda: E.spmv(x, y), max(20, steps // 2), torch)[0] * 1000
+    di, ei = D.info(), E.info()
+    res = {"grid": [128, 128, 128], "n": A.n_rows, "nnz": A.nnz, "P": di["P"], "K": di["K"],
+           "escape_rows": di["n_escape_rows"], "dit_us": round(d_us, 3), "ell_us": round(e_us, 3),
+           "dit_gflops": round(2.0 * A.nnz / (d_us * 1e-6) / 1e9, 2),
+           "ell_gflops": round(2.0 * A.nnz / (e_us * 1e-6) / 1e9, 2), "speedup": round(e_us / d_us, 3),
+           "dit_bytes": di["bytes_stream"] + 16 * A.n_rows, "ell_bytes": ei["bytes_stream"] + 16 * A.n_rows,
+           "dit_GBps": round((di["bytes_stream"] + 16 * A.n_rows) / (d_us * 1e-6) / 1e9, 1), "tuned": tuned}
+    log(f"[bench] irregular: DIT {d_us:.1f} us vs ELL {e_us:.1f} us")
+    return res
+
+
+def run_batched(P, torch, dev, n_sys):
+    """64 systems, grid dims U{16..96} (seed 0), 8 right-hand sides U[-1,1]: batched CG to 1e-10."""
+    from synthetic import batched_grids, stencil27
+
+    grids = batched_grids(n_sys, 16, 96, seed=0)
+    log(f"[bench] batched: generating {n_sys} systems")
+    mats, bs = [], []
+    rows = nnz = 0
+    for s, g in enumerate(grids):
+        A = stencil27(*g)
+        rows += A.n_rows
+        nnz += A.nnz
+        rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+        mats.append(P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT"))
+        rng = np.random.default_rng(1000 + s)
+        bs.append(torch.from_numpy(rng.uniform(-1.0, 1.0, (A.n_rows, 8))).to(dev))
+    res = {"systems": n_sys, "nrhs": 8, "rows": rows, "nnz": nnz, "rtol": 1e-10}
+    P.cg_solve(mats, bs, nrhs=8, batched=2, max_iter=4)  # warm the code path
+    for name, mode in (("graph", 2), ("batched_kernels", 1), ("sequential", 0)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, xs, stats = P.cg_solve(mats, bs, nrhs=8, batched=mode, max_iter=5000)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        its = [q["iters"] for q in stats]
+        res[name] = {"status": st, "seconds": round(t, 4), "iters_min": min(its), "iters_max": max(its),
+                     "relres_true_max": max(q["relres_true"] for q in stats)}
+        log(f"[bench] batched {name}: {t * 1000:.1f} ms, iters {min(its)}..{max(its)}")
+    res["speedup_graph_vs_sequential"] = round(res["sequential"]["seconds"] / res["graph"]["seconds"], 2)
+    return res
 
 
 def run_cg(g, P, torch, dev):
@@ -225,9 +299,10 @@ def run_cg(g, P, torch, dev):
     D = P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT")
     E = P.compress(rp, col, val, n_cols=A.n_cols, fmt="ELL")
     del rp, col, val
+    res_tune = {"f64": D.tune(torch.float64)}
     ones = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
     b = D.spmv(ones)
-    res = {"grid": [g, g, g], "n": A.n_rows, "nnz": A.nnz, "rtol": 1e-10}
+    res = {"grid": [g, g, g], "n": A.n_rows, "nnz": A.nnz, "rtol": 1e-10, "tuned": res_tune}
     for name, M, mode in (("fp64_dit", D, 0), ("mixed_dit", D, 1), ("fp64_ell", E, 0)):
         P.cg_solve(M, b, mode=mode, max_iter=20)  # warm-up of the code path
         torch.cuda.synchronize()

@@ -9,9 +9,10 @@
 // finished drops out of the tile loops.
 //
 // One iteration is five launches:
-//   bspmv      Q = A_s P for the active systems (one lane per row, all nrhs
-//              right-hand sides of the row-interleaved block per decoded entry)
-//              and per-tile partials of p.q for every rhs;
+//   bspmv      Q = A_s P for the active systems (a group of lanes per row,
+//              one lane per right-hand side of the row-interleaved block, so
+//              every gather is a contiguous run) and per-tile partials of p.q
+//              for every rhs;
 //   fin_alpha  one block per system: sigma = sum of its tiles' partials (fixed
 //              order), alpha = rho / sigma, breakdown test;
 //   update     X += alpha P, R -= alpha Q for the active pairs; partials of r.r;
@@ -72,6 +73,29 @@ __device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64
     return static_cast<const uint32_t *>(ids)[row];
 }
 
+// Lane layout.  A tile is 256 rows of one system, handled by one block of 256
+// threads.  Thread t serves right-hand side r = t % LPR (LPR = nrhs rounded up
+// to a power of two) of rows t / LPR, t / LPR + 256/LPR, ... -- so the LPR
+// lanes of a row read that row's nrhs contiguous values of a row-interleaved
+// block (coalesced), the matrix entry is decoded once per lane group, and each
+// thread keeps one rhs for the per-rhs partial sums.
+
+// Sum over the threads of the block that share t % LPR; result valid in
+// threads r < LPR (r = the rhs).
+template <int LPR> __device__ __forceinline__ double rhs_sum(double v) {
+    __shared__ double sh[kT / 64][LPR];
+#pragma unroll
+    for (int off = LPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) < LPR) sh[threadIdx.x >> 6][threadIdx.x & 63] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x < LPR)
+#pragma unroll
+        for (int w = 0; w < kT / 64; ++w) s += sh[w][threadIdx.x];
+    return s;
+}
+
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double sh[kT / 64];
 #pragma unroll
@@ -85,8 +109,8 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-// Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs (NR >= nrhs).
-template <int NR>
+// Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs.
+template <int LPR>
 __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict__ Pin, double *__restrict__ Qout,
                                               double *part, int with_dot) {
     const int tile = blockIdx.x;
@@ -94,31 +118,26 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
     if (!b.sys_active[s]) return;  // uniform per block
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
-    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
-    double acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-    const bool valid = lrow < d.n;
-    if (valid) {
+    const int r = threadIdx.x % LPR;
+    const bool lane_on = r < nr;
+    const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+    double dotc = 0.0;
+    for (int pass = 0; pass < LPR; ++pass) {
+        const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + pass * (kT / LPR) + threadIdx.x / LPR;
+        if (lrow >= d.n) break;
         const int64_t grow = d.row0 + lrow;
-        const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
         const uint32_t id = load_id(d.ids, d.id_bytes, lrow);
-        auto apply = [&](double v, int64_t gcol) {
-            const double *xp = Pin + gcol * nr;
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (r < nr) acc[r] = fma(v, xp[r], acc[r]);
-        };
+        const double *pr = Pin + d.row0 * nr + r;
+        double acc = 0.0;
         if (id != esc) {
             const int32_t *pat = d.pat_off + static_cast<int64_t>(id) * d.width;
-            const int len = d.pat_len[id];
             int k = 0;
             for (int c = 0; c < d.K; ++c) {
                 const int tend = d.T[static_cast<int64_t>(c) * d.n_pad + lrow];
                 const double v = d.V[c];
-                for (; k < tend; ++k) apply(v, d.row0 + lrow + pat[k]);
+                for (; k < tend; ++k)
+                    if (lane_on) acc = fma(v, pr[(lrow + pat[k]) * nr], acc);
             }
-            (void)len;
         } else {
             // escape row: position in the (ascending) escape-row list by bisection
             int64_t lo = 0, hi = d.n_esc;
@@ -126,20 +145,17 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
                 const int64_t mid = (lo + hi) / 2;
                 if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
             }
-            for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) apply(d.esc_val[e], d.row0 + d.esc_col[e]);
+            for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e)
+                if (lane_on) acc = fma(d.esc_val[e], pr[static_cast<int64_t>(d.esc_col[e]) * nr], acc);
         }
-        double *yp = Qout + grow * nr;
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (r < nr) yp[r] = acc[r];
+        if (lane_on) {
+            Qout[grow * nr + r] = acc;
+            if (with_dot) dotc += Pin[grow * nr + r] * acc;
+        }
     }
     if (!with_dot) return;
-    const double *pp = Pin + (d.row0 + (valid ? lrow : 0)) * nr;
-    for (int r = 0; r < nr; ++r) {
-        const double c = valid ? pp[r] * acc[r] : 0.0;
-        const double t = block_sum(c);
-        if (threadIdx.x == 0) part[static_cast<int64_t>(tile) * nr + r] = t;
-    }
+    const double t = rhs_sum<LPR>(dotc);
+    if (threadIdx.x < nr) part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 // Sum of the tiles' partials of system s for rhs r (fixed order), in every thread.
@@ -149,26 +165,30 @@ __device__ __forceinline__ double sys_sum(const Batch &b, const SysDesc &d, int 
     return block_sum(acc);
 }
 
+// Element loop of a tile: f(global element index, rhs) for the tile's rows.
+#define SPMVC_TILE_ELEMS(BODY)                                                                      \
+    {                                                                                               \
+        const int r = threadIdx.x % LPR;                                                            \
+        if (r < nr)                                                                                 \
+            for (int pass = 0; pass < LPR; ++pass) {                                                \
+                const int64_t lrow =                                                                \
+                    static_cast<int64_t>(tile - d.tile0) * kT + pass * (kT / LPR) + threadIdx.x / LPR; \
+                if (lrow >= d.n) break;                                                             \
+                const int64_t g = (d.row0 + lrow) * nr + r;                                         \
+                BODY                                                                                \
+            }                                                                                       \
+    }
+
 // X = 0, R = B, P = B; partials of b.b
-__global__ __launch_bounds__(kT) void k_bstart(Batch b) {
+template <int LPR> __global__ __launch_bounds__(kT) void k_bstart(Batch b) {
     const int tile = blockIdx.x;
     const int s = b.tile_sys[tile];
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
-    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
-    const bool valid = lrow < d.n;
-    const int64_t g = (d.row0 + (valid ? lrow : 0)) * nr;
-    for (int r = 0; r < nr; ++r) {
-        double v = 0.0;
-        if (valid) {
-            v = b.B[g + r];
-            b.X[g + r] = 0.0;
-            b.R[g + r] = v;
-            b.P[g + r] = v;
-        }
-        const double t = block_sum(v * v);
-        if (threadIdx.x == 0) b.part[static_cast<int64_t>(tile) * nr + r] = t;
-    }
+    double acc = 0.0;
+    SPMVC_TILE_ELEMS(const double v = b.B[g]; b.X[g] = 0.0; b.R[g] = v; b.P[g] = v; acc += v * v;)
+    const double t = rhs_sum<LPR>(acc);
+    if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kT) void k_bstart_fin(Batch b) {
@@ -221,29 +241,22 @@ __global__ __launch_bounds__(kT) void k_bfin_alpha(Batch b) {
 }
 
 // X += alpha P, R -= alpha Q for running pairs; partials of r.r
-__global__ __launch_bounds__(kT) void k_bupdate(Batch b) {
+template <int LPR> __global__ __launch_bounds__(kT) void k_bupdate(Batch b) {
     const int tile = blockIdx.x;
     const int s = b.tile_sys[tile];
     if (!b.sys_active[s]) return;
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
-    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
-    const bool valid = lrow < d.n;
-    const int64_t g = (d.row0 + (valid ? lrow : 0)) * nr;
-    for (int r = 0; r < nr; ++r) {
-        const int q = s * nr + r;
-        const bool run = !b.done[q];
-        double c = 0.0;
-        if (valid && run) {
-            const double a = b.alpha[q];
-            b.X[g + r] += a * b.P[g + r];
-            const double rv = b.R[g + r] - a * b.Q[g + r];
-            b.R[g + r] = rv;
-            c = rv * rv;
-        }
-        const double t = block_sum(c);
-        if (threadIdx.x == 0) b.part[static_cast<int64_t>(tile) * nr + r] = t;
+    const int rr_ = threadIdx.x % LPR;
+    const int q = s * nr + (rr_ < nr ? rr_ : 0);
+    const bool run = rr_ < nr && !b.done[q];
+    const double a = run ? b.alpha[q] : 0.0;
+    double acc = 0.0;
+    if (run) {
+        SPMVC_TILE_ELEMS(b.X[g] += a * b.P[g]; const double rv = b.R[g] - a * b.Q[g]; b.R[g] = rv; acc += rv * rv;)
     }
+    const double t = rhs_sum<LPR>(acc);
+    if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 // rho', convergence, beta
@@ -282,7 +295,6 @@ __global__ __launch_bounds__(kT) void k_bfin_beta(Batch b) {
         }
     }
     if (threadIdx.x == 0 && still == 0) {
-        // every pair of the system has finished (the pupdate of this step has nothing to do)
         bool any = false;
         for (int r = 0; r < b.nrhs; ++r) any |= (b.done[s * b.nrhs + r] == 0);
         if (!any) b.sys_active[s] = 0;
@@ -290,36 +302,29 @@ __global__ __launch_bounds__(kT) void k_bfin_beta(Batch b) {
 }
 
 // P = R + beta P for running pairs
-__global__ __launch_bounds__(kT) void k_bpupdate(Batch b) {
+template <int LPR> __global__ __launch_bounds__(kT) void k_bpupdate(Batch b) {
     const int tile = blockIdx.x;
     const int s = b.tile_sys[tile];
     if (!b.sys_active[s]) return;
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
-    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
-    if (lrow >= d.n) return;
-    const int64_t g = (d.row0 + lrow) * nr;
-    for (int r = 0; r < nr; ++r) {
-        const int q = s * nr + r;
-        if (b.done[q]) continue;
-        b.P[g + r] = b.R[g + r] + b.beta[q] * b.P[g + r];
-    }
+    const int rr_ = threadIdx.x % LPR;
+    const int q = s * nr + (rr_ < nr ? rr_ : 0);
+    if (rr_ >= nr || b.done[q]) return;
+    const double beta = b.beta[q];
+    SPMVC_TILE_ELEMS(b.P[g] = b.R[g] + beta * b.P[g];)
 }
 
 // partials of (b - Ax).(b - Ax) per rhs, with Ax in Q (all systems)
-__global__ __launch_bounds__(kT) void k_bresid(Batch b) {
+template <int LPR> __global__ __launch_bounds__(kT) void k_bresid(Batch b) {
     const int tile = blockIdx.x;
     const int s = b.tile_sys[tile];
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
-    const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x;
-    const bool valid = lrow < d.n;
-    const int64_t g = (d.row0 + (valid ? lrow : 0)) * nr;
-    for (int r = 0; r < nr; ++r) {
-        const double v = valid ? b.B[g + r] - b.Q[g + r] : 0.0;
-        const double t = block_sum(v * v);
-        if (threadIdx.x == 0) b.part[static_cast<int64_t>(tile) * nr + r] = t;
-    }
+    double acc = 0.0;
+    SPMVC_TILE_ELEMS(const double v = b.B[g] - b.Q[g]; acc += v * v;)
+    const double t = rhs_sum<LPR>(acc);
+    if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kT) void k_bresid_fin(Batch b, double *out) {
@@ -336,16 +341,24 @@ __global__ void k_set_all(int32_t *p, int32_t v, int n) {
     if (i < n) p[i] = v;
 }
 
+// Launch a tile kernel with LPR = nrhs rounded up to a power of two.
+#define SPMVC_LPR_LAUNCH(KERNEL, GRID, STREAM, ...)                                  \
+    do {                                                                             \
+        if (b.nrhs <= 1)                                                             \
+            KERNEL<1><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                         \
+        else if (b.nrhs <= 2)                                                        \
+            KERNEL<2><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                         \
+        else if (b.nrhs <= 4)                                                        \
+            KERNEL<4><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                         \
+        else if (b.nrhs <= 8)                                                        \
+            KERNEL<8><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                         \
+        else                                                                         \
+            KERNEL<16><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                        \
+    } while (0)
+
 void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles);
-    if (b.nrhs <= 1)
-        k_bspmv<1><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
-    else if (b.nrhs <= 4)
-        k_bspmv<4><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
-    else if (b.nrhs <= 8)
-        k_bspmv<8><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
-    else
-        k_bspmv<16><<<g, kT, 0, s>>>(b, Pin, Qout, b.part, with_dot);
+    SPMVC_LPR_LAUNCH(k_bspmv, g, s, b, Pin, Qout, b.part, with_dot);
 }
 
 // One CG iteration for every running pair.
@@ -353,9 +366,9 @@ void record_iteration(const Batch &b, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles), ns = static_cast<unsigned>(b.n_sys);
     launch_bspmv(b, b.P, b.Q, 1, s);
     k_bfin_alpha<<<ns, kT, 0, s>>>(b);
-    k_bupdate<<<g, kT, 0, s>>>(b);
+    SPMVC_LPR_LAUNCH(k_bupdate, g, s, b);
     k_bfin_beta<<<ns, kT, 0, s>>>(b);
-    k_bpupdate<<<g, kT, 0, s>>>(b);
+    SPMVC_LPR_LAUNCH(k_bpupdate, g, s, b);
 }
 
 }  // namespace
@@ -459,7 +472,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     b.rtol = o.rtol;
     b.max_iter = o.max_iter;
 
-    k_bstart<<<static_cast<unsigned>(n_tiles), kT, 0, st>>>(b);
+    SPMVC_LPR_LAUNCH(k_bstart, static_cast<unsigned>(n_tiles), st, b);
     k_bstart_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b);
     SPMVC_CHECK_LAUNCH();
 
@@ -514,7 +527,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     // true residuals ||b - A x|| / ||b|| per pair
     k_set_all<<<static_cast<unsigned>((n_sys + 255) / 256), 256, 0, st>>>(b.sys_active, 1, n_sys);
     launch_bspmv(b, b.X, b.Q, 0, st);
-    k_bresid<<<static_cast<unsigned>(n_tiles), kT, 0, st>>>(b);
+    SPMVC_LPR_LAUNCH(k_bresid, static_cast<unsigned>(n_tiles), st, b);
     k_bresid_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b, rr.as<double>());
     SPMVC_CHECK_LAUNCH();
     std::vector<double> h_rr(np), h_rho0(np), h_rel(np);
