@@ -179,6 +179,8 @@ typedef struct {
     int32_t lds_windows;   /* x windows staged in LDS by the DIT kernel (0 = direct gather) */
     int32_t rows_per_block;
     double V[15];          /* the value table (first K entries)                           */
+    int32_t kernel;        /* what spmv launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register */
+    int32_t pad_;
 } spmvc_info;
 
 spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info /* host */);

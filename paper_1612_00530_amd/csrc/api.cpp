@@ -225,6 +225,7 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
         r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode == 1) ? A->plan.n_win : 0;
         r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan.rows : kBlock;
         for (int c = 0; c < A->K; ++c) r.V[c] = A->V[c];
+        r.kernel = kernel_kind(A);
         *info = r;
         return SPMVC_OK;
     });

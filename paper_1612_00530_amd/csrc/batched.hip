@@ -65,6 +65,7 @@ struct Batch {
     int32_t *n_active;    // [1]: pairs still running
     double rtol;
     int32_t max_iter;
+    int32_t max_width;  // longest pattern of any system
 };
 
 __device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
@@ -109,8 +110,31 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
+// Sum over a row's pattern entries with value V[0] (k < t0) and with V[1]
+// (t0 <= k < len) of x at the entries' columns.  All MAXW pattern offsets are
+// read first and all MAXW loads issued before any add, so a row's gathers are
+// in flight together; entries past len read the row's own element and add 0.
+template <int MAXW>
+__device__ __forceinline__ void gather_row(const int32_t *__restrict__ pat, int len, int t0, const double *pr,
+                                           int64_t lrow, int nr, double &s0, double &s1) {
+    int32_t off[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) off[k] = k < len ? pat[k] : 0;
+    double xv[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) xv[k] = pr[(lrow + off[k]) * nr];
+    s0 = 0.0;
+    s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        s0 += k < t0 ? xv[k] : 0.0;
+        s1 += (k >= t0 && k < len) ? xv[k] : 0.0;
+    }
+}
+
 // Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs.
-template <int LPR>
+// Rows with at most MAXW entries take the unrolled gather; longer ones a loop.
+template <int LPR, int MAXW>
 __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict__ Pin, double *__restrict__ Qout,
                                               double *part, int with_dot) {
     const int tile = blockIdx.x;
@@ -120,6 +144,7 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
     const int nr = b.nrhs;
     const int r = threadIdx.x % LPR;
     const bool lane_on = r < nr;
+    const int rc = lane_on ? r : 0;  // idle lanes mirror rhs 0 and store nothing
     const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     double dotc = 0.0;
     for (int pass = 0; pass < LPR; ++pass) {
@@ -127,16 +152,25 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
         if (lrow >= d.n) break;
         const int64_t grow = d.row0 + lrow;
         const uint32_t id = load_id(d.ids, d.id_bytes, lrow);
-        const double *pr = Pin + d.row0 * nr + r;
+        const double *pr = Pin + d.row0 * nr + rc;
         double acc = 0.0;
         if (id != esc) {
-            const int32_t *pat = d.pat_off + static_cast<int64_t>(id) * d.width;
-            int k = 0;
-            for (int c = 0; c < d.K; ++c) {
-                const int tend = d.T[static_cast<int64_t>(c) * d.n_pad + lrow];
-                const double v = d.V[c];
-                for (; k < tend; ++k)
-                    if (lane_on) acc = fma(v, pr[(lrow + pat[k]) * nr], acc);
+            if (d.K > 0) {
+                const int32_t *pat = d.pat_off + static_cast<int64_t>(id) * d.width;
+                // exclusive run ends: entries [0, t0) take V[0], [t0, len) V[1]
+                const int len = d.T[static_cast<int64_t>(d.K - 1) * d.n_pad + lrow];
+                const int t0 = d.K > 1 ? static_cast<int>(d.T[lrow]) : len;
+                double s0, s1;
+                if (len <= MAXW) {
+                    gather_row<MAXW>(pat, len, t0, pr, lrow, nr, s0, s1);
+                } else {
+                    s0 = 0.0;
+                    s1 = 0.0;
+                    for (int k = 0; k < t0; ++k) s0 += pr[(lrow + pat[k]) * nr];
+                    for (int k = t0; k < len; ++k) s1 += pr[(lrow + pat[k]) * nr];
+                }
+                acc = d.V[0] * s0;
+                if (d.K > 1) acc = fma(d.V[1], s1, acc);
             }
         } else {
             // escape row: position in the (ascending) escape-row list by bisection
@@ -146,7 +180,7 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
                 if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
             }
             for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e)
-                if (lane_on) acc = fma(d.esc_val[e], pr[static_cast<int64_t>(d.esc_col[e]) * nr], acc);
+                acc = fma(d.esc_val[e], pr[static_cast<int64_t>(d.esc_col[e]) * nr], acc);
         }
         if (lane_on) {
             Qout[grow * nr + r] = acc;
@@ -356,9 +390,27 @@ __global__ void k_set_all(int32_t *p, int32_t v, int n) {
             KERNEL<16><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                        \
     } while (0)
 
+// The same for k_bspmv with its second template argument W.
+#define SPMVC_BSPMV_LAUNCH(W, GRID, STREAM, ...)                                     \
+    do {                                                                             \
+        if (b.nrhs <= 1)                                                             \
+            k_bspmv<1, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+        else if (b.nrhs <= 2)                                                        \
+            k_bspmv<2, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+        else if (b.nrhs <= 4)                                                        \
+            k_bspmv<4, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+        else if (b.nrhs <= 8)                                                        \
+            k_bspmv<8, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+        else                                                                         \
+            k_bspmv<16, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                    \
+    } while (0)
+
 void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles);
-    SPMVC_LPR_LAUNCH(k_bspmv, g, s, b, Pin, Qout, b.part, with_dot);
+    if (b.max_width <= 28)
+        SPMVC_BSPMV_LAUNCH(28, g, s, b, Pin, Qout, b.part, with_dot);
+    else
+        SPMVC_BSPMV_LAUNCH(32, g, s, b, Pin, Qout, b.part, with_dot);
 }
 
 // One CG iteration for every running pair.
@@ -453,6 +505,8 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     b.nrhs = nrhs;
     b.n_tiles = n_tiles;
     b.n_total = n_total;
+    b.max_width = 0;
+    for (int q = 0; q < n_sys; ++q) b.max_width = std::max(b.max_width, sd[q].width);
     b.B = B.as<double>();
     b.X = X.as<double>();
     b.R = R.as<double>();

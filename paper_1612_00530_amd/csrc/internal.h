@@ -138,6 +138,8 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
                            hipStream_t s);
 
 // batched.hip
+// Kernel one spmv of the handle launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register.
+int kernel_kind(const spmvc_matrix_s *M);
 bool batched_supported(const spmvc_matrix *A, int n_sys);
 spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                               double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,

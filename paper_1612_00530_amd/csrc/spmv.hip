@@ -791,6 +791,11 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
     }
 }
 
+int kernel_kind(const spmvc_matrix_s *M) {
+    if (!uses_lds(M)) return 0;
+    return reg_variant(M) > 0 ? 2 : 1;
+}
+
 void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s, const int *skip) {
     if (dt == SPMVC_F64)
         launch_spmv_t<double>(M, x, y, s, skip);

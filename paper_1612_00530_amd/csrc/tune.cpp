@@ -3,7 +3,8 @@
 // Candidates (single right-hand side, DIT): rows per block in {256 .. 4096}
 // with the x windows staged in LDS, and the direct-gather kernel (x read
 // through the L1/L2 caches).  Every candidate gives the same result; only the
-// time differs.  Winners are cached per (arch, format, rows, P, K, dtype, nrhs)
+// time differs.  A candidate's time is the median over repetitions of the mean
+// of a run of back-to-back launches.  Winners are cached per (arch, format, rows, P, K, dtype, nrhs)
 // in the JSON object stored in the file named by $SPMVC_TUNE_CACHE.
 #include <algorithm>
 #include <cstdio>
@@ -15,6 +16,9 @@
 
 namespace spmvc {
 namespace {
+
+constexpr int kTuneReps = 7;    // timed repetitions per candidate (median kept)
+constexpr int kTuneBatch = 20;  // launches per repetition
 
 struct Cand {
     int rows, lds;
@@ -122,16 +126,18 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
                 else
                     launch_spmv_block(A, dt, nrhs, x.p, nrhs, y.p, nrhs, s);
             };
-            for (int w = 0; w < 3; ++w) run();
+            for (int w = 0; w < 5; ++w) run();
+            // back-to-back launches between one event pair: the rate a solver
+            // loop sees, without the per-launch event overhead
             std::vector<float> ts;
-            for (int r = 0; r < 15; ++r) {
+            for (int r = 0; r < kTuneReps; ++r) {
                 SPMVC_HIP(hipEventRecord(e0, s));
-                run();
+                for (int l = 0; l < kTuneBatch; ++l) run();
                 SPMVC_HIP(hipEventRecord(e1, s));
                 SPMVC_HIP(hipEventSynchronize(e1));
                 float ms = 0;
                 SPMVC_HIP(hipEventElapsedTime(&ms, e0, e1));
-                ts.push_back(ms);
+                ts.push_back(ms / kTuneBatch);
             }
             std::sort(ts.begin(), ts.end());
             const double us = 1000.0 * ts[ts.size() / 2];
