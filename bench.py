@@ -39,19 +39,25 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(n_launch_bytes_alg):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it is current."""
+def traffic_from_profile(kernel, rows_per_block):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken from this kernel source in this launch configuration (else None)."""
     if not os.path.exists(PROFILE_PMC):
         return None
     txt = open(PROFILE_PMC).read()
-    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
-    if not m or m.group(1) != kernel_source_hash():
+
+    def field(name):
+        m = re.search(name + r":\s*(\S+)", txt)
+        return m.group(1) if m else None
+
+    if field("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    f = re.search(r"fetch_bytes_per_launch:\s*([\d.eE+]+)", txt)
-    w = re.search(r"write_bytes_per_launch:\s*([\d.eE+]+)", txt)
-    if not f or not w:
+    if field("kernel") != kernel or field("rows_per_block") != str(rows_per_block):
         return None
-    return float(f.group(1)) + float(w.group(1))
+    f, w = field("fetch_bytes_per_launch"), field("write_bytes_per_launch")
+    if f is None or w is None:
+        return None
+    return float(f) + float(w)
 
 
 def time_launches(fn, reps, torch):
@@ -64,6 +70,19 @@ def time_launches(fn, reps, torch):
     torch.cuda.synchronize()
     t = np.array([a.elapsed_time(b) for a, b in ev])
     return float(t.mean()), float(np.median(t)), float(t.min())
+
+
+def time_cold(fn, reps, torch, flush):
+    """Median duration (ms) of one launch after the 256 MB last-level (MALL) cache
+    has been overwritten by a 1 GiB fill, so the launch reads HBM, not MALL."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        flush.fill_(1.0)
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
 def main():
@@ -148,7 +167,7 @@ def main():
     _, k_med, k_min = time_launches(lambda: D.spmv(x, y), args.steps, torch)
     alg_dit = dinf["bytes_stream"] + 8 * n + 8 * n
     achieved = alg_dit / (k_mean * 1e-3) / 1e9
-    traffic = traffic_from_profile(alg_dit)
+    traffic = traffic_from_profile(dinf["kernel_name"], dinf["rows_per_block"])
 
     # ELL baseline, same matrix and vectors
     for _ in range(args.warmup):
@@ -185,6 +204,17 @@ def main():
     # FP32 DIT SpMV of the same matrix (the inner kernel of the mixed-precision CG)
     x32, y32 = x.float(), y.float()
     f_mean, _, _ = time_launches(lambda: D.spmv(x32, y32), max(20, args.steps // 2), torch)
+
+    # cold-cache launches: the MALL flushed before each one
+    flush = torch.empty(128 << 20, dtype=torch.float64, device=dev)
+    c_dit = time_cold(lambda: D.spmv(x, y), 30, torch, flush)
+    c_ell = time_cold(lambda: E.spmv(x, y), 30, torch, flush)
+    del flush
+    cold = {"dit_us": round(c_dit * 1000, 3), "dit_gflops": round(2.0 * nnz / (c_dit * 1e-3) / 1e9, 1),
+            "dit_GBps": round(alg_dit / (c_dit * 1e-3) / 1e9, 1),
+            "ell_us": round(c_ell * 1000, 3), "ell_gflops": round(2.0 * nnz / (c_ell * 1e-3) / 1e9, 1),
+            "ell_GBps": round(alg_ell / (c_ell * 1e-3) / 1e9, 1), "speedup_vs_ell": round(c_ell / c_dit, 2)}
+    log(f"[bench] cold MALL: DIT {cold['dit_us']} us, ELL {cold['ell_us']} us ({cold['ell_GBps']} GB/s)")
 
     irregular = None
     if not args.no_irregular:
@@ -229,6 +259,7 @@ def main():
                           "DIT_paper_widths": round(dinf["bytes_paper"] / n, 3)},
         "parity_max_rel_err": out.get("parity_max_rel_err"),
         "tuned": tuned,
+        "cold_mall": cold,
         "dit_f32": {"launch_us_mean": round(f_mean * 1000, 3), "gflops": round(2.0 * nnz / (f_mean * 1e-3) / 1e9, 2)},
         "irregular": irregular,
         "cg": cg,

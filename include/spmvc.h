@@ -210,7 +210,8 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
  * Kernel configuration of a handle's spmv (rows per block, LDS staging).
  * rows_per_block: 256..4096, a multiple of 256 (0 = keep).  lds: 1 = stage x
  * windows in LDS when they fit, 0 = gather x directly, -1 = keep.  Used by the
- * autotuner; any valid setting gives the same results.
+ * autotuner; every valid setting gives y within the same accuracy bound (the
+ * kernels sum a row's products in different orders).
  */
 spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds);
 

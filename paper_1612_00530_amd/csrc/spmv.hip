@@ -17,12 +17,13 @@
 // x[row + d] -- the indirect access the paper names as its bottleneck --
 // becomes an LDS read.
 //
-// The register kernel (k_dit_reg) holds a row's whole pattern (at most 32
-// entries, 80 bytes) in registers, so its 32 LDS reads are independent and
-// issue back to back.  Per entry it costs one add (offset + row), one LDS read,
-// one compare against T and one select of the value, and one FMA.  Rows shorter
-// than 32 read a zero window in LDS for the missing entries (exact when every
-// table value is finite); patterns with raw values use a per-entry predicate.
+// The register kernel (k_dit_reg) holds a row's whole pattern (at most 31
+// entries, 64 bytes of LDS offsets) in registers, so its LDS reads are
+// independent and issue back to back.  Per entry it costs one add (offset +
+// row), one LDS read and one add (one FMA where the value must be selected per
+// lane).  Rows shorter than the table width read a zero window in LDS for the
+// missing entries (exact when every table value is finite); patterns with raw
+// values use a per-entry predicate.
 //
 // Escape rows (plain CSR) are served by extra blocks appended to the same grid;
 // the main blocks skip them (ID == all-ones, or column -2 in slot 0).
@@ -254,12 +255,15 @@ __device__ __forceinline__ void lds_load16(const void *g, void *lds) {
 #endif
 }
 
+// Issues the copies of the block's x windows for rows [r0, r0 + rows) into xs.
+// Direct loads are left in flight (the caller waits for them); the register
+// path (edge windows, unaligned x) has completed its LDS stores on return.
 template <class Real>
-__device__ __forceinline__ void stage_windows(const SpmvArgs &a, const Real *__restrict__ x, Real *xs, int64_t r0) {
+__device__ __forceinline__ void stage_windows_async(const SpmvArgs &a, const Real *__restrict__ x, Real *xs,
+                                                    int64_t r0) {
     constexpr int PER = 16 / sizeof(Real);  // elements per lane per direct load
     constexpr int CH = 64 * PER;            // elements per wavefront per direct load
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bool direct = false;
     for (int w = 0; w < a.n_win; ++w) {
         const int64_t g0 = r0 + a.win_lo[w];
         const int n = a.win_len[w];
@@ -270,7 +274,6 @@ __device__ __forceinline__ void stage_windows(const SpmvArgs &a, const Real *__r
                 const int e = c * CH + lane * PER;
                 if (e < n) lds_load16(x + g0 + e, dst + c * CH);
             }
-            direct = true;
         } else {
             const int64_t last = a.n_cols - 1;
             for (int e = threadIdx.x; e < n; e += kBlock) {
@@ -280,8 +283,13 @@ __device__ __forceinline__ void stage_windows(const SpmvArgs &a, const Real *__r
             }
         }
     }
+}
+
+template <class Real>
+__device__ __forceinline__ void stage_windows(const SpmvArgs &a, const Real *__restrict__ x, Real *xs, int64_t r0) {
+    stage_windows_async<Real>(a, x, xs, r0);
     for (int e = threadIdx.x; e < a.zero_len; e += kBlock) xs[a.zero_base + e] = Real(0);
-    if (direct) __builtin_amdgcn_s_waitcnt(0);  // direct loads have landed in LDS
+    __builtin_amdgcn_s_waitcnt(0);  // direct loads have landed in LDS
 }
 
 // ---- DIT, LDS windows, generic walk (any K, raw values, any pattern length) --------
@@ -335,11 +343,12 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
 // KK = 1 or 2: value table of KK entries, no raw values, short rows padded with
 // zero-window entries.  The table lists each pattern's entries in *reverse*
 // canonical order, so a row's V[1] entries (positions >= T[0]) come first: the
-// first m = len - T[0] entries take V[1], the rest V[0].  Within a wavefront
-// positions below min(m) or from max(m) on take one value for every lane (a
-// scalar operand, no per-lane select); only positions between the two need a
-// per-lane select.  For the 27-point stencil every row has m = 1, so no entry
-// needs a select.  KK = 0: no value table, every value raw (canonical order),
+// first m = len - T[0] entries take V[1], the rest V[0].  When every active
+// lane of a wavefront has the same m (two ballots decide), the row is
+// V[1] * (sum of its first m x values) + V[0] * (sum of the rest): values are
+// scalar operands and there are two multiplies per row instead of one per
+// entry.  Otherwise each entry selects its value per lane.  For the 27-point
+// stencil every row has m = 1.  KK = 0: no value table, every value raw (canonical order),
 // entries past the row length masked.  RPT rows per thread (rows per block =
 // 256 * RPT); each thread's row IDs and T are loaded before the windows are
 // staged, so their latency overlaps the staging.  MAXW: entries per row.
@@ -361,35 +370,36 @@ __device__ __forceinline__ float uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-__device__ __forceinline__ int wave_min(int v) {
+// Sum of xat(k) for k in [LO, HI).  Every read is issued first; the adds run
+// in groups of four, each group starting from its last element, so one wait
+// for that element's read covers the whole group (reads complete in order);
+// the group sums are added pairwise.
+template <int LO, int HI, class F> __device__ __forceinline__ auto sum_entries(F xat) -> decltype(xat(0)) {
+    using R = decltype(xat(0));
+    constexpr int N = HI - LO, G = 4, NG = (N + G - 1) / G;
+    R xv[N];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ int wave_max(int v) {
+    for (int k = 0; k < N; ++k) xv[k] = xat(LO + k);
+    R g[NG];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
-__global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
-    if (a.skip && *a.skip) return;
-    if (blockIdx.x >= a.n_main_blocks) {
-        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
-                                        1, x, 1, y, 1));
-        return;
+    for (int q = 0; q < NG; ++q) {
+        const int a = q * G, b = (a + G < N) ? a + G : N;
+        R t = xv[b - 1];
+#pragma unroll
+        for (int k = b - 2; k >= a; --k) t += xv[k];
+        g[q] = t;
     }
-    extern __shared__ __align__(16) unsigned char smem[];
-    Real *xs = reinterpret_cast<Real *>(smem);
-    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * (kBlock * RPT);
-    double dotc = 0.0;
-    const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+#pragma unroll
+    for (int w = 1; w < NG; w *= 2)
+#pragma unroll
+        for (int q = 0; q + w < NG; q += 2 * w) g[q] += g[q + w];
+    return g[0];
+}
 
-    uint32_t idv[RPT];
-    int t0v[RPT];
-    Real xrow[RPT];  // x at the row itself, for the optional dot product
+// Row metadata of one tile (IDs, T[0], x at the row) for the RPT rows of this thread.
+template <class Real, int KK, int RPT>
+__device__ __forceinline__ void load_tile_meta(const SpmvArgs &a, const Real *__restrict__ x, int64_t r0,
+                                               uint32_t (&idv)[RPT], int (&t0v)[RPT], Real (&xrow)[RPT]) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int64_t row = r0 + threadIdx.x + j * kBlock;
@@ -398,24 +408,16 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
         t0v[j] = KK >= 1 ? static_cast<int>(a.T[rc]) : 0;
         xrow[j] = a.dot ? x[rc] : Real(0);
     }
-    stage_windows<Real>(a, x, xs, r0);
-    uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
-    if constexpr (TAB_LDS) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.reg_tab);
-        const int n16 = a.P * (kRegTw * 2 / 16);
-        for (int e = threadIdx.x; e < n16; e += kBlock) tab_s[e] = src[e];
-    }
-    __syncthreads();
-    const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
-    Real v0, v1;
-    if constexpr (sizeof(Real) == 8) {
-        v0 = a.V[0];
-        v1 = a.V[KK >= 2 ? 1 : 0];
-    } else {
-        v0 = a.V32[0];
-        v1 = a.V32[KK >= 2 ? 1 : 0];
-    }
+}
 
+// The rows of one tile, x windows already in LDS at `buf` (byte base of the
+// windows + zero window), pattern rows at `tab`.  Adds the tile's x.y to dotc.
+template <class Real, int KK, int RPT, int MAXW>
+__device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char *buf, const uint4 *tab, int64_t r0,
+                                         const uint32_t (&idv)[RPT], const int (&t0v)[RPT],
+                                         const Real (&xrow)[RPT], Real v0, Real v1, Real *__restrict__ y,
+                                         double &dotc) {
+    const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int rel = threadIdx.x + j * kBlock;
@@ -433,10 +435,15 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
         }
         const int len = static_cast<int>(w[0] & 0xFFFFu);
         const int m = KK == 2 ? len - t0v[j] : 0;  // leading entries that take V[1]
-        int m_lo = 0, m_hi = 0;
+        // Is the split the same in every active lane?  Reference: the lowest
+        // active lane's m (two ballots and one lane read, all scalar results).
+        int ms = 0;
+        bool uni = true;
         if constexpr (KK == 2) {
-            m_lo = wave_min(active ? m : MAXW);
-            m_hi = wave_max(active ? m : 0);
+            const uint64_t act = __ballot(active);
+            if (act == 0) continue;  // no active lane: uniform exit
+            ms = __builtin_amdgcn_readlane(m, static_cast<int>(__builtin_ctzll(act)));
+            uni = __ballot(active && m != ms) == 0;
         }
         if (!active) continue;
         const uint32_t relb = static_cast<uint32_t>(rel) * sizeof(Real);
@@ -446,28 +453,22 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
         auto xat = [&](int k) -> Real {
             const uint32_t word = w[(k + 1) >> 1];
             const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
-            return *reinterpret_cast<const Real *>(smem + relb + off);
+            return *reinterpret_cast<const Real *>(buf + relb + off);
         };
         if constexpr (KK == 0) {
 #pragma unroll
             for (int k = 0; k < MAXW; ++k)
                 if (k < len) acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xat(k), acc);
-        } else if (KK == 1 || m_lo == m_hi) {
-            // every lane of the wave splits at the same position: scalar values;
-            // the common splits are compiled with the split position fixed
-            const int ms = KK == 1 ? 0 : m_lo;
+        } else if (KK == 1 || uni) {
+            // every lane of the wave splits at the same position: one sum per
+            // value, scaled once (scalar values); the common splits are compiled
+            // with the split position fixed
             if (ms == 0) {
-#pragma unroll
-                for (int k = 0; k < MAXW; ++k) acc = fma(v0, xat(k), acc);
+                acc = v0 * sum_entries<0, MAXW>(xat);
             } else if (ms == 1) {
-                acc = fma(v1, xat(0), acc);
-#pragma unroll
-                for (int k = 1; k < MAXW; ++k) acc = fma(v0, xat(k), acc);
+                acc = fma(v0, sum_entries<1, MAXW>(xat), v1 * xat(0));
             } else if (ms == 2) {
-                acc = fma(v1, xat(0), acc);
-                acc = fma(v1, xat(1), acc);
-#pragma unroll
-                for (int k = 2; k < MAXW; ++k) acc = fma(v0, xat(k), acc);
+                acc = fma(v0, sum_entries<2, MAXW>(xat), v1 * (xat(1) + xat(0)));
             } else {
 #pragma unroll
                 for (int k = 0; k < MAXW; ++k) acc = fma(uniform(k < ms ? v1 : v0), xat(k), acc);
@@ -479,6 +480,46 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
         y[row] = acc;
         if (a.dot) dotc += static_cast<double>(xrow[j]) * static_cast<double>(acc);
     }
+}
+
+template <class Real, int KK> __device__ __forceinline__ void value_pair(const SpmvArgs &a, Real &v0, Real &v1) {
+    if constexpr (sizeof(Real) == 8) {
+        v0 = a.V[0];
+        v1 = a.V[KK >= 2 ? 1 : 0];
+    } else {
+        v0 = a.V32[0];
+        v1 = a.V32[KK >= 2 ? 1 : 0];
+    }
+}
+
+template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
+__global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
+    if (a.skip && *a.skip) return;
+    if (blockIdx.x >= a.n_main_blocks) {
+        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
+                                        1, x, 1, y, 1));
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    Real *xs = reinterpret_cast<Real *>(smem);
+    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * (kBlock * RPT);
+    double dotc = 0.0;
+    uint32_t idv[RPT];
+    int t0v[RPT];
+    Real xrow[RPT];  // x at the row itself, for the optional dot product
+    load_tile_meta<Real, KK, RPT>(a, x, r0, idv, t0v, xrow);
+    stage_windows<Real>(a, x, xs, r0);
+    uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
+    if constexpr (TAB_LDS) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.reg_tab);
+        const int n16 = a.P * (kRegTw * 2 / 16);
+        for (int e = threadIdx.x; e < n16; e += kBlock) tab_s[e] = src[e];
+    }
+    __syncthreads();
+    const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
+    Real v0, v1;
+    value_pair<Real, KK>(a, v0, v1);
+    reg_tile<Real, KK, RPT, MAXW>(a, smem, tab, r0, idv, t0v, xrow, v0, v1, y, dotc);
     emit_dot(a, dotc);
 }
 
@@ -563,8 +604,9 @@ int reg_variant(const spmvc_matrix_s *M) {
     return 0;
 }
 
+// Returns the number of blocks launched (one dot partial each).
 template <class Real>
-void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hipStream_t s) {
+unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hipStream_t s) {
     const LdsPlan &p = M->plan;
     a.rows = p.rows;
     a.n_win = p.n_win;
@@ -587,10 +629,10 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
         a.reg_tab = f64 ? p.reg_tab64.as<uint16_t>() : p.reg_tab32.as<uint16_t>();
         const int x_bytes = static_cast<int>(sizeof(Real)) * (p.zero_base + p.rows);
         a.lds_x_bytes = (x_bytes + 15) & ~15;
-        size_t shmem = a.lds_x_bytes;
-        if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
         const int rpt = p.rows / kBlock;
         const bool w28 = M->width <= 28;
+        size_t shmem = a.lds_x_bytes;
+        if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
 #define SPMVC_REG_W(KK, TL, R)                                                                                  \
     if (w28)                                                                                                    \
         k_dit_reg<Real, KK, TL, R, 28><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
@@ -623,7 +665,7 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
 #undef SPMVC_REG_R
 #undef SPMVC_REG_W
         SPMVC_CHECK_LAUNCH();
-        return;
+        return grid;
     }
     a.zero_len = 0;
     a.tab = p.tab.as<uint16_t>();
@@ -652,6 +694,7 @@ void launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hip
     }
 #undef SPMVC_LDS
     SPMVC_CHECK_LAUNCH();
+    return grid;
 }
 
 template <class Real>
@@ -672,15 +715,14 @@ bool uses_lds(const spmvc_matrix_s *M) {
     return M->fmt == SPMVC_FMT_DIT && M->lds_mode == 1 && M->plan.n_win > 0 && M->P > 0;
 }
 
+// Returns the number of blocks launched (one dot partial each).
 template <class Real>
-void launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStream_t s, const int *skip,
-                   double *dot = nullptr) {
-    if (M->n_rows == 0) return;
-    if (uses_lds(M)) {
-        launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
-        return;
-    }
+unsigned launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStream_t s, const int *skip,
+                       double *dot = nullptr) {
+    if (M->n_rows == 0) return 0;
+    if (uses_lds(M)) return launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
     launch_block_t<Real>(M, 1, x, 1, y, 1, s, skip, dot);
+    return static_cast<unsigned>((M->n_pad + kBlock - 1) / kBlock + escape_blocks(M));
 }
 
 }  // namespace
@@ -814,11 +856,8 @@ int64_t spmv_dot_blocks(const spmvc_matrix_s *M) {
 unsigned launch_spmv_dot(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s, const int *skip,
                          double *dot) {
     if (M->n_rows == 0) return 0;
-    if (dt == SPMVC_F64)
-        launch_spmv_t<double>(M, x, y, s, skip, dot);
-    else
-        launch_spmv_t<float>(M, x, y, s, skip, dot);
-    return static_cast<unsigned>(spmv_dot_blocks(M));
+    if (dt == SPMVC_F64) return launch_spmv_t<double>(M, x, y, s, skip, dot);
+    return launch_spmv_t<float>(M, x, y, s, skip, dot);
 }
 
 void launch_spmv_block(const spmvc_matrix_s *M, int dt, int nrhs, const void *X, int64_t ldx, void *Y,

@@ -71,7 +71,7 @@ def test_stencil104_full_size_parity(fmt):
     assert np.array_equal(y1, oracle.spmv(A, np.ones(A.n_cols)))
 
 
-@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (2048, 1), (4096, 1), (1024, 0)])
+@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (1024, 1), (2048, 1), (4096, 1), (1024, 0)])
 def test_dit_kernel_configs_agree(rows, lds):
     say("case: DIT config", rows, lds)
     A = stencil27(40, 37, 23)
