@@ -15,9 +15,10 @@
 //              for every rhs;
 //   fin_alpha  one block per system: sigma = sum of its tiles' partials (fixed
 //              order), alpha = rho / sigma, breakdown test;
-//   update     X += alpha P, R -= alpha Q for the active pairs; partials of r.r;
+//   update     R -= alpha Q for the pairs taking a step; partials of r.r;
 //   fin_beta   one block per system: rho', convergence, beta, pair/system flags;
-//   pupdate    P = R + beta P for the pairs still running.
+//   pupdate    X += alpha P for the pairs that took the step (P is read once),
+//              and P = R + beta P for those still running.
 // All reductions are fixed-order, so results repeat exactly.  Iterations are
 // recorded once into a hipGraph and the graph is replayed; the host reads one
 // counter (active pairs) per replay.  No memset is recorded in the graph.
@@ -36,7 +37,7 @@ struct SysDesc {
     int64_t row0, n;   // first global row, rows
     int64_t n_pad;
     int64_t tile0;     // first tile
-    int32_t ntiles, K, width, id_bytes;
+    int32_t ntiles, K, width, id_bytes, P;
     const void *ids;
     const uint8_t *T;
     const int32_t *pat_off;
@@ -61,11 +62,16 @@ struct Batch {
     double *rho;     // [2][pairs]
     double *rho0, *alpha, *beta, *relres;
     int32_t *iters, *status, *done;
+    int32_t *step;        // the pair took this iteration's step (set with alpha)
     int32_t *sys_active;  // [n_sys]
+    int32_t *sys_step;    // [n_sys]: some pair of the system took this iteration's step
     int32_t *n_active;    // [1]: pairs still running
     double rtol;
     int32_t max_iter;
     int32_t max_width;  // longest pattern of any system
+    int32_t tab_lds;    // every system's pattern table fits the LDS copy of the SpMV
+    int32_t tab_ints;   // largest pattern table (P * width entries)
+    int32_t n_xcd;      // XCDs the blocks are dispatched over (tile mapping of the SpMV)
 };
 
 __device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
@@ -134,10 +140,27 @@ __device__ __forceinline__ void gather_row(const int32_t *__restrict__ pat, int 
 
 // Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs.
 // Rows with at most MAXW entries take the unrolled gather; longer ones a loop.
+// Blocks are dispatched round-robin over the XCDs.  Tiles are handed out in
+// chunks of kChunk consecutive tiles, chunk k to XCD k % n_xcd: the rows a
+// tile gathers from (adjacent lines and planes of its grid) mostly lie in its
+// own chunk and hit that XCD's L2, while every system's chunks stay spread
+// over all XCDs, so the work stays balanced as systems finish.  Tiles past the
+// last whole round of chunks keep their own index.
+constexpr int kChunk = 32;
+
+__device__ __forceinline__ int chunk_tile(unsigned bid, unsigned nb, int n_xcd) {
+    const unsigned round = static_cast<unsigned>(kChunk) * n_xcd;
+    const unsigned full = nb / round * round;
+    if (n_xcd <= 1 || bid >= full) return static_cast<int>(bid);
+    const unsigned x = bid % n_xcd, j = bid / n_xcd;
+    return static_cast<int>(((j / kChunk) * n_xcd + x) * kChunk + j % kChunk);
+}
+
 template <int LPR, int MAXW>
 __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict__ Pin, double *__restrict__ Qout,
                                               double *part, int with_dot) {
-    const int tile = blockIdx.x;
+    extern __shared__ int32_t pat_s[];
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd);
     const int s = b.tile_sys[tile];
     if (!b.sys_active[s]) return;  // uniform per block
     const SysDesc &d = b.sys[s];
@@ -146,20 +169,40 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
     const bool lane_on = r < nr;
     const int rc = lane_on ? r : 0;  // idle lanes mirror rhs 0 and store nothing
     const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
-    double dotc = 0.0;
+    // metadata of all of this thread's rows first: independent loads, in flight together
+    const int64_t lbase = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x / LPR;
+    uint32_t idv[LPR];
+    int lenv[LPR], t0v[LPR];
+#pragma unroll
     for (int pass = 0; pass < LPR; ++pass) {
-        const int64_t lrow = static_cast<int64_t>(tile - d.tile0) * kT + pass * (kT / LPR) + threadIdx.x / LPR;
+        int64_t lrow = lbase + pass * (kT / LPR);
+        lrow = lrow < d.n ? lrow : d.n - 1;
+        idv[pass] = load_id(d.ids, d.id_bytes, lrow);
+        lenv[pass] = d.K > 0 ? static_cast<int>(d.T[static_cast<int64_t>(d.K - 1) * d.n_pad + lrow]) : 0;
+        t0v[pass] = d.K > 1 ? static_cast<int>(d.T[lrow]) : lenv[pass];
+    }
+    // the system's pattern table, copied to LDS once per block
+    const int32_t *ptab = d.pat_off;
+    if (b.tab_lds) {
+        const int ne = d.P * d.width;
+        for (int e = threadIdx.x; e < ne; e += kT) pat_s[e] = d.pat_off[e];
+        __syncthreads();
+        ptab = pat_s;
+    }
+    const double *pr = Pin + d.row0 * nr + rc;
+    double dotc = 0.0;
+#pragma unroll
+    for (int pass = 0; pass < LPR; ++pass) {
+        const int64_t lrow = lbase + pass * (kT / LPR);
         if (lrow >= d.n) break;
         const int64_t grow = d.row0 + lrow;
-        const uint32_t id = load_id(d.ids, d.id_bytes, lrow);
-        const double *pr = Pin + d.row0 * nr + rc;
+        const uint32_t id = idv[pass];
         double acc = 0.0;
         if (id != esc) {
             if (d.K > 0) {
-                const int32_t *pat = d.pat_off + static_cast<int64_t>(id) * d.width;
+                const int32_t *pat = ptab + static_cast<int64_t>(id) * d.width;
                 // exclusive run ends: entries [0, t0) take V[0], [t0, len) V[1]
-                const int len = d.T[static_cast<int64_t>(d.K - 1) * d.n_pad + lrow];
-                const int t0 = d.K > 1 ? static_cast<int>(d.T[lrow]) : len;
+                const int len = lenv[pass], t0 = t0v[pass];
                 double s0, s1;
                 if (len <= MAXW) {
                     gather_row<MAXW>(pat, len, t0, pr, lrow, nr, s0, s1);
@@ -254,12 +297,17 @@ __global__ __launch_bounds__(kT) void k_bstart_fin(Batch b) {
 // index and one recorded graph serves every replay.
 __global__ __launch_bounds__(kT) void k_bfin_alpha(Batch b) {
     const int s = blockIdx.x;
-    if (!b.sys_active[s]) return;
+    if (!b.sys_active[s]) {
+        if (threadIdx.x == 0) b.sys_step[s] = 0;
+        return;
+    }
     const SysDesc &d = b.sys[s];
+    int any = 0;
     for (int r = 0; r < b.nrhs; ++r) {
         const double sigma = sys_sum(b, d, r);
         if (threadIdx.x == 0) {
             const int q = s * b.nrhs + r;
+            b.step[q] = 0;
             if (b.done[q]) continue;
             if (!(sigma > 0.0) || !isfinite(sigma)) {
                 b.done[q] = 1;
@@ -269,25 +317,29 @@ __global__ __launch_bounds__(kT) void k_bfin_alpha(Batch b) {
                 atomicSub(b.n_active, 1);
             } else {
                 b.alpha[q] = b.rho[(b.iters[q] & 1) * b.n_sys * b.nrhs + q] / sigma;
+                b.step[q] = 1;
+                any = 1;
             }
         }
     }
+    if (threadIdx.x == 0) b.sys_step[s] = any;
 }
 
-// X += alpha P, R -= alpha Q for running pairs; partials of r.r
+// R -= alpha Q for the pairs taking a step; partials of r.r (X advances in the
+// p-update, which reads P anyway)
 template <int LPR> __global__ __launch_bounds__(kT) void k_bupdate(Batch b) {
     const int tile = blockIdx.x;
     const int s = b.tile_sys[tile];
-    if (!b.sys_active[s]) return;
+    if (!b.sys_step[s]) return;
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
     const int rr_ = threadIdx.x % LPR;
     const int q = s * nr + (rr_ < nr ? rr_ : 0);
-    const bool run = rr_ < nr && !b.done[q];
+    const bool run = rr_ < nr && b.step[q];
     const double a = run ? b.alpha[q] : 0.0;
     double acc = 0.0;
     if (run) {
-        SPMVC_TILE_ELEMS(b.X[g] += a * b.P[g]; const double rv = b.R[g] - a * b.Q[g]; b.R[g] = rv; acc += rv * rv;)
+        SPMVC_TILE_ELEMS(const double rv = b.R[g] - a * b.Q[g]; b.R[g] = rv; acc += rv * rv;)
     }
     const double t = rhs_sum<LPR>(acc);
     if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
@@ -335,18 +387,24 @@ __global__ __launch_bounds__(kT) void k_bfin_beta(Batch b) {
     }
 }
 
-// P = R + beta P for running pairs
+// X += alpha P for the pairs that took this iteration's step, then
+// P = R + beta P for those still running
 template <int LPR> __global__ __launch_bounds__(kT) void k_bpupdate(Batch b) {
     const int tile = blockIdx.x;
     const int s = b.tile_sys[tile];
-    if (!b.sys_active[s]) return;
+    if (!b.sys_step[s]) return;
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
     const int rr_ = threadIdx.x % LPR;
     const int q = s * nr + (rr_ < nr ? rr_ : 0);
-    if (rr_ >= nr || b.done[q]) return;
+    if (rr_ >= nr || !b.step[q]) return;
+    const double alpha = b.alpha[q];
+    if (b.done[q]) {
+        SPMVC_TILE_ELEMS(b.X[g] += alpha * b.P[g];)
+        return;
+    }
     const double beta = b.beta[q];
-    SPMVC_TILE_ELEMS(b.P[g] = b.R[g] + beta * b.P[g];)
+    SPMVC_TILE_ELEMS(const double pv = b.P[g]; b.X[g] += alpha * pv; b.P[g] = b.R[g] + beta * pv;)
 }
 
 // partials of (b - Ax).(b - Ax) per rhs, with Ax in Q (all systems)
@@ -390,27 +448,30 @@ __global__ void k_set_all(int32_t *p, int32_t v, int n) {
             KERNEL<16><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                        \
     } while (0)
 
-// The same for k_bspmv with its second template argument W.
-#define SPMVC_BSPMV_LAUNCH(W, GRID, STREAM, ...)                                     \
+// The same for k_bspmv with its second template argument W and LDS bytes SH.
+#define SPMVC_BSPMV_LAUNCH(W, GRID, SH, STREAM, ...)                                 \
     do {                                                                             \
         if (b.nrhs <= 1)                                                             \
-            k_bspmv<1, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+            k_bspmv<1, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
         else if (b.nrhs <= 2)                                                        \
-            k_bspmv<2, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+            k_bspmv<2, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
         else if (b.nrhs <= 4)                                                        \
-            k_bspmv<4, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+            k_bspmv<4, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
         else if (b.nrhs <= 8)                                                        \
-            k_bspmv<8, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                     \
+            k_bspmv<8, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
         else                                                                         \
-            k_bspmv<16, W><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                    \
+            k_bspmv<16, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                   \
     } while (0)
+
+constexpr int kTabLdsInts = 4096;  // pattern tables up to 16 KB are copied to LDS
 
 void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles);
+    const size_t sh = b.tab_lds ? sizeof(int32_t) * static_cast<size_t>(b.tab_ints) : 0;
     if (b.max_width <= 28)
-        SPMVC_BSPMV_LAUNCH(28, g, s, b, Pin, Qout, b.part, with_dot);
+        SPMVC_BSPMV_LAUNCH(28, g, sh, s, b, Pin, Qout, b.part, with_dot);
     else
-        SPMVC_BSPMV_LAUNCH(32, g, s, b, Pin, Qout, b.part, with_dot);
+        SPMVC_BSPMV_LAUNCH(32, g, sh, s, b, Pin, Qout, b.part, with_dot);
 }
 
 // One CG iteration for every running pair.
@@ -451,6 +512,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         d.ntiles = static_cast<int32_t>((M->n_rows + kT - 1) / kT);
         d.K = M->K;
         d.width = M->width;
+        d.P = M->P;
         d.id_bytes = M->id_bytes;
         d.ids = M->ids.p;
         d.T = M->T.as<uint8_t>();
@@ -470,7 +532,8 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     const int64_t n_total = row0;
     const int n_tiles = static_cast<int>(tile0);
     const int np = n_sys * nrhs;
-    DevBuf dsys, dtile, B, X, R, P, Q, part, rho, rho0, alpha, beta, relres, iters, status, done, sact, nact, rr;
+    DevBuf dsys, dtile, B, X, R, P, Q, part, rho, rho0, alpha, beta, relres, iters, status, done, step, sact, sstep,
+        nact, rr;
     dsys.alloc(sizeof(SysDesc) * n_sys);
     dtile.alloc(sizeof(int32_t) * std::max(n_tiles, 1));
     const size_t vb = sizeof(double) * static_cast<size_t>(std::max<int64_t>(n_total, 1)) * nrhs;
@@ -490,6 +553,8 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     status.alloc(sizeof(int32_t) * np);
     done.alloc(sizeof(int32_t) * np);
     sact.alloc(sizeof(int32_t) * n_sys);
+    step.alloc(sizeof(int32_t) * np);
+    sstep.alloc(sizeof(int32_t) * n_sys);
     nact.alloc(sizeof(int32_t));
     SPMVC_HIP(hipMemcpyAsync(dsys.p, sd.data(), dsys.bytes, hipMemcpyHostToDevice, st));
     SPMVC_HIP(hipMemcpyAsync(dtile.p, tile_sys.data(), sizeof(int32_t) * n_tiles, hipMemcpyHostToDevice, st));
@@ -505,8 +570,14 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     b.nrhs = nrhs;
     b.n_tiles = n_tiles;
     b.n_total = n_total;
+    b.n_xcd = n_sys > 0 ? A[0]->n_xcd : 1;
     b.max_width = 0;
-    for (int q = 0; q < n_sys; ++q) b.max_width = std::max(b.max_width, sd[q].width);
+    b.tab_ints = 0;
+    for (int q = 0; q < n_sys; ++q) {
+        b.max_width = std::max(b.max_width, sd[q].width);
+        b.tab_ints = std::max(b.tab_ints, sd[q].P * sd[q].width);
+    }
+    b.tab_lds = b.tab_ints > 0 && b.tab_ints <= kTabLdsInts;
     b.B = B.as<double>();
     b.X = X.as<double>();
     b.R = R.as<double>();
@@ -522,6 +593,8 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     b.status = status.as<int32_t>();
     b.done = done.as<int32_t>();
     b.sys_active = sact.as<int32_t>();
+    b.step = step.as<int32_t>();
+    b.sys_step = sstep.as<int32_t>();
     b.n_active = nact.as<int32_t>();
     b.rtol = o.rtol;
     b.max_iter = o.max_iter;

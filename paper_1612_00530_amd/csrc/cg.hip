@@ -18,7 +18,9 @@
 // hold the identical scalar and no block waits for another.  (An agent-scope
 // release per block -- the usual last-block-done pattern -- writes back the
 // whole L2 of an XCD on this chip and costs more than the streaming itself.)
-// The SpMV of the iteration writes the p.q partials itself.  Scalars that
+// The SpMV of the iteration writes the p.q partials itself, and x advances in
+// the p-update kernel (which reads p anyway), so an iteration is three
+// launches: SpMV + p.q, r-update + r.r, x- and p-update.  Scalars that
 // persist across iterations are written by block 0 only, into slots other
 // blocks of the same kernel do not read (rho is double-buffered by iteration
 // parity; the iteration index comes from the host).  Results do not depend on
@@ -32,12 +34,13 @@ namespace spmvc {
 namespace {
 
 constexpr int kRT = 512;                // threads per BLAS-1 block (8 waves)
-constexpr unsigned kRMaxBlocks = 1024;  // partials per reduction
+constexpr unsigned kRMaxBlocks = 256;   // partials per reduction (fewer partials: cheaper consumer sums)
 
 struct CgScal {
     double rho[2];    // r.r of the current iterate, by iteration parity
     double rho0, rtol, rel, sigma;
     int32_t iters, max_iter, done, status;
+    int32_t go[2];    // the update step of the iteration (by parity) ran: the p-update must run
     double aux[4];
 };
 
@@ -120,6 +123,7 @@ __global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, in
     st->rel = tot > 0.0 ? 1.0 : 0.0;
     st->done = (tot == 0.0) ? 1 : 0;
     st->status = SPMVC_OK;
+    st->go[0] = st->go[1] = 0;
     if (!(tot == tot) || tot > 1.7e308) {
         st->done = 1;
         st->status = SPMVC_EINVAL;
@@ -127,40 +131,44 @@ __global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, in
 }
 
 // sigma = sum of the p.q partials of the SpMV; alpha = rho / sigma;
-// x += alpha p; r -= alpha q; partials of r.r.  A breakdown (sigma <= 0 or not
-// finite) stops the solve.
+// r -= alpha q; partials of r.r.  A breakdown (sigma <= 0 or not finite) stops
+// the solve.  Block 0 records sigma and whether the step ran (go), which the
+// p-update reads: it must not read `done`, which its own block 0 may set.
 template <class Real>
-__global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__ x, Real *__restrict__ r,
-                                                   const Real *__restrict__ p, const Real *__restrict__ q,
+__global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__ r, const Real *__restrict__ q,
                                                    const double *sig_part, int n_sig, double *rr_part, CgScal *st,
                                                    int par, int it) {
-    if (st->done) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st->done) {
+        if (lead) st->go[par] = 0;
+        return;
+    }
     const double sigma = sum_partials<kRT>(sig_part, n_sig);
     if (!(sigma > 0.0) || !isfinite(sigma)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (lead) {
             st->sigma = sigma;
             st->done = 1;
             st->status = SPMVC_ENOTSPD;
             st->iters = it + 1;
+            st->go[par] = 0;
         }
         return;
+    }
+    if (lead) {
+        st->sigma = sigma;
+        st->go[par] = 1;
     }
     const Real alpha = static_cast<Real>(st->rho[par] / sigma);
     double acc = 0.0;
     SPMVC_STREAM4(
-        Real xv[4]; Real rv[4]; Real pv[4]; Real qv[4];
+        Real rv[4]; Real qv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = r[i + u * stride_]; qv[u] = q[i + u * stride_]; }
 _Pragma("unroll") for (int u = 0; u < 4; ++u) {
-            xv[u] = x[i + u * stride_]; rv[u] = r[i + u * stride_];
-            pv[u] = p[i + u * stride_]; qv[u] = q[i + u * stride_];
-        }
-_Pragma("unroll") for (int u = 0; u < 4; ++u) {
-            x[i + u * stride_] = xv[u] + alpha * pv[u];
             const Real ri = rv[u] - alpha * qv[u];
             r[i + u * stride_] = ri;
             acc += dd(ri) * dd(ri);
         }
         ,
-        x[i] = x[i] + alpha * p[i];
         const Real ri = r[i] - alpha * q[i];
         r[i] = ri;
         acc += dd(ri) * dd(ri);
@@ -169,11 +177,14 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
     if (threadIdx.x == 0) rr_part[blockIdx.x] = b;
 }
 
-// rho' = sum of the r.r partials; convergence test; beta = rho'/rho; p = r + beta p.
+// rho' = sum of the r.r partials; convergence test; x += alpha p (with the
+// update step's alpha); unless the solve stops here, beta = rho'/rho and
+// p = r + beta p.  x is updated here, not in k_cg_update, so p is read once.
 template <class Real>
-__global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, const Real *__restrict__ r, Real *__restrict__ p,
-                                                    const double *rr_part, int n_rr, CgScal *st, int par, int it) {
-    if (st->done) return;
+__global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, Real *__restrict__ x, const Real *__restrict__ r,
+                                                    Real *__restrict__ p, const double *rr_part, int n_rr,
+                                                    CgScal *st, int par, int it) {
+    if (!st->go[par]) return;
     const double rho_new = sum_partials<kRT>(rr_part, n_rr);
     const double rho = st->rho[par];
     const bool conv = sqrt(rho_new) <= st->rtol * sqrt(st->rho0);
@@ -193,13 +204,29 @@ __global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, const Real *__res
             st->status = SPMVC_ENOCONV;
         }
     }
-    if (stop) return;
+    const Real alpha = static_cast<Real>(rho / st->sigma);
+    if (stop) {
+        SPMVC_STREAM4(
+            Real xv[4]; Real pv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { xv[u] = x[i + u * stride_]; pv[u] = p[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) x[i + u * stride_] = xv[u] + alpha * pv[u];
+            ,
+            x[i] = x[i] + alpha * p[i];
+        )
+        return;
+    }
     const Real beta = static_cast<Real>(rho_new / rho);
     SPMVC_STREAM4(
-        Real rv[4]; Real pv[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = r[i + u * stride_]; pv[u] = p[i + u * stride_]; }
-_Pragma("unroll") for (int u = 0; u < 4; ++u) p[i + u * stride_] = rv[u] + beta * pv[u];
+        Real xv[4]; Real rv[4]; Real pv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            xv[u] = x[i + u * stride_]; rv[u] = r[i + u * stride_]; pv[u] = p[i + u * stride_];
+        }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            x[i + u * stride_] = xv[u] + alpha * pv[u];
+            p[i + u * stride_] = rv[u] + beta * pv[u];
+        }
         ,
+        x[i] = x[i] + alpha * p[i];
         p[i] = r[i] + beta * p[i];
     )
 }
@@ -312,9 +339,9 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Rea
         for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
             const int par = it & 1;
             const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.part_sig.as<double>());
-            k_cg_update<Real><<<g, kRT, 0, sv.s>>>(n, z, r, p, q, sv.part_sig.as<double>(), static_cast<int>(ns),
+            k_cg_update<Real><<<g, kRT, 0, sv.s>>>(n, r, q, sv.part_sig.as<double>(), static_cast<int>(ns),
                                                    sv.part_b.as<double>(), sv.st(), par, it);
-            k_cg_pupdate<Real><<<g, kRT, 0, sv.s>>>(n, r, p, sv.part_b.as<double>(), static_cast<int>(g), sv.st(),
+            k_cg_pupdate<Real><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.part_b.as<double>(), static_cast<int>(g), sv.st(),
                                                     par, it);
         }
         SPMVC_CHECK_LAUNCH();
