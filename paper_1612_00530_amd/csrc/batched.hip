@@ -256,6 +256,22 @@ __device__ __forceinline__ double sys_sum(const Batch &b, const SysDesc &d, int 
             }                                                                                       \
     }
 
+// Two-phase form for the update kernels: BODY runs for every row slot of the
+// thread (ok: the row exists; g is clamped to a valid element otherwise), so
+// a first loop can issue all loads and a second do the stores: the loads are
+// then all in flight together (the vectors are not marked non-aliasing, so a
+// store would otherwise order every later load behind it).
+#define SPMVC_TILE_SLOTS(BODY)                                                                   \
+    {                                                                                            \
+        const int64_t lb_ = static_cast<int64_t>(tile - d.tile0) * kT + threadIdx.x / LPR;       \
+        _Pragma("unroll") for (int pass = 0; pass < LPR; ++pass) {                               \
+            const int64_t lrow = lb_ + pass * (kT / LPR);                                        \
+            const bool ok = lrow < d.n;                                                          \
+            const int64_t g = (d.row0 + (ok ? lrow : 0)) * nr + rr_;                             \
+            BODY                                                                                 \
+        }                                                                                        \
+    }
+
 // X = 0, R = B, P = B; partials of b.b
 template <int LPR> __global__ __launch_bounds__(kT) void k_bstart(Batch b) {
     const int tile = blockIdx.x;
@@ -339,7 +355,13 @@ template <int LPR> __global__ __launch_bounds__(kT) void k_bupdate(Batch b) {
     const double a = run ? b.alpha[q] : 0.0;
     double acc = 0.0;
     if (run) {
-        SPMVC_TILE_ELEMS(const double rv = b.R[g] - a * b.Q[g]; b.R[g] = rv; acc += rv * rv;)
+        double rv[LPR], qv[LPR];
+        SPMVC_TILE_SLOTS(rv[pass] = b.R[g]; qv[pass] = b.Q[g];)
+        SPMVC_TILE_SLOTS(if (ok) {
+            const double t = rv[pass] - a * qv[pass];
+            b.R[g] = t;
+            acc += t * t;
+        })
     }
     const double t = rhs_sum<LPR>(acc);
     if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
@@ -399,12 +421,19 @@ template <int LPR> __global__ __launch_bounds__(kT) void k_bpupdate(Batch b) {
     const int q = s * nr + (rr_ < nr ? rr_ : 0);
     if (rr_ >= nr || !b.step[q]) return;
     const double alpha = b.alpha[q];
+    double xv[LPR], pv[LPR];
     if (b.done[q]) {
-        SPMVC_TILE_ELEMS(b.X[g] += alpha * b.P[g];)
+        SPMVC_TILE_SLOTS(xv[pass] = b.X[g]; pv[pass] = b.P[g];)
+        SPMVC_TILE_SLOTS(if (ok) b.X[g] = xv[pass] + alpha * pv[pass];)
         return;
     }
     const double beta = b.beta[q];
-    SPMVC_TILE_ELEMS(const double pv = b.P[g]; b.X[g] += alpha * pv; b.P[g] = b.R[g] + beta * pv;)
+    double rv[LPR];
+    SPMVC_TILE_SLOTS(xv[pass] = b.X[g]; pv[pass] = b.P[g]; rv[pass] = b.R[g];)
+    SPMVC_TILE_SLOTS(if (ok) {
+        b.X[g] = xv[pass] + alpha * pv[pass];
+        b.P[g] = rv[pass] + beta * pv[pass];
+    })
 }
 
 // partials of (b - Ax).(b - Ax) per rhs, with Ax in Q (all systems)
