@@ -630,12 +630,12 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
         const int x_bytes = static_cast<int>(sizeof(Real)) * (p.zero_base + p.rows);
         a.lds_x_bytes = (x_bytes + 15) & ~15;
         const int rpt = p.rows / kBlock;
-        const bool w28 = M->width <= 28;
+        const bool w27 = M->width <= 27;  // the 27-point stencil: no padded step
         size_t shmem = a.lds_x_bytes;
         if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
 #define SPMVC_REG_W(KK, TL, R)                                                                                  \
-    if (w28)                                                                                                    \
-        k_dit_reg<Real, KK, TL, R, 28><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
+    if (w27)                                                                                                    \
+        k_dit_reg<Real, KK, TL, R, 27><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
     else                                                                                                        \
         k_dit_reg<Real, KK, TL, R, kRegW><<<grid, kBlock, shmem, s>>>(a, xp, yp);
 #define SPMVC_REG_R(KK, TL)      \
