@@ -72,6 +72,18 @@ def time_launches(fn, reps, torch):
     return float(t.mean()), float(np.median(t)), float(t.min())
 
 
+def time_batch(fn, reps, torch):
+    """Mean duration (ms) of one launch over `reps` back-to-back launches (one event pair)."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def time_cold(fn, reps, torch, flush):
     """Median duration (ms) of one launch after the 256 MB last-level (MALL) cache
     has been overwritten by a 1 GiB fill, so the launch reads HBM, not MALL."""
@@ -141,7 +153,8 @@ def main():
     tuned = None
     if not args.no_tune:
         tuned = D.tune(torch.float64)
-        log(f"[bench] tuned DIT: {tuned}")
+        tuned_f32 = D.tune(torch.float32)
+        log(f"[bench] tuned DIT: FP64 {tuned}, FP32 {tuned_f32}")
     dinf, einf = D.info(), E.info()
 
     # timed region: K back-to-back compressed SpMVs, bracketed by host clock and
@@ -172,7 +185,7 @@ def main():
     # ELL baseline, same matrix and vectors
     for _ in range(args.warmup):
         E.spmv(x, y)
-    e_mean, e_med, e_min = time_launches(lambda: E.spmv(x, y), max(20, args.steps // 2), torch)
+    e_mean = time_batch(lambda: E.spmv(x, y), max(20, args.steps // 2), torch)
     alg_ell = einf["bytes_stream"] + 8 * n + 8 * n
     ell_gflops = 2.0 * nnz / (e_mean * 1e-3) / 1e9
     log(f"[bench] ELL: {e_mean * 1000:.2f} us/launch, {ell_gflops:.1f} Gflops, "
@@ -203,7 +216,9 @@ def main():
 
     # FP32 DIT SpMV of the same matrix (the inner kernel of the mixed-precision CG)
     x32, y32 = x.float(), y.float()
-    f_mean, _, _ = time_launches(lambda: D.spmv(x32, y32), max(20, args.steps // 2), torch)
+    for _ in range(5):
+        D.spmv(x32, y32)
+    f_mean = time_batch(lambda: D.spmv(x32, y32), max(20, args.steps // 2), torch)
 
     # cold-cache launches: the MALL flushed before each one
     flush = torch.empty(128 << 20, dtype=torch.float64, device=dev)
@@ -282,8 +297,8 @@ def run_irregular(P, torch, dev, steps):
     tuned = D.tune(torch.float64)
     x = torch.from_numpy(uniform_vector(A.n_cols, seed=0)).to(dev)
     y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
-    d_us = time_launches(lambda: D.spmv(x, y), max(20, steps // 2), torch)[0] * 1000
-    e_us = time_launches(lambda: E.spmv(x, y), max(20, steps // 2), torch)[0] * 1000
+    d_us = time_batch(lambda: D.spmv(x, y), max(20, steps // 2), torch) * 1000
+    e_us = time_batch(lambda: E.spmv(x, y), max(20, steps // 2), torch) * 1000
     di, ei = D.info(), E.info()
     res = {"grid": [128, 128, 128], "n": A.n_rows, "nnz": A.nnz, "P": di["P"], "K": di["K"],
            "escape_rows": di["n_escape_rows"], "dit_us": round(d_us, 3), "ell_us": round(e_us, 3),
@@ -337,7 +352,7 @@ def run_cg(g, P, torch, dev):
     D = P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT")
     E = P.compress(rp, col, val, n_cols=A.n_cols, fmt="ELL")
     del rp, col, val
-    res_tune = {"f64": D.tune(torch.float64)}
+    res_tune = {"f64": D.tune(torch.float64), "f32": D.tune(torch.float32)}
     ones = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
     b = D.spmv(ones)
     res = {"grid": [g, g, g], "n": A.n_rows, "nnz": A.nnz, "rtol": 1e-10, "tuned": res_tune}

@@ -176,10 +176,12 @@ typedef struct {
     int64_t bytes_stream;  /* bytes one FP64 spmv must read for the matrix (all arrays)   */
     int64_t bytes_ell;     /* the same matrix as FP64 ELL: 12 bytes per slot              */
     int64_t bytes_paper;   /* at the paper's widths: ELL 12/slot, DT 4*(len+K), DIT 4*(1+K) per row */
-    int32_t lds_windows;   /* x windows staged in LDS by the DIT kernel (0 = direct gather) */
-    int32_t rows_per_block;
+    int32_t lds_windows;   /* x windows staged in LDS by the FP64 DIT kernel (0 = direct gather) */
+    int32_t rows_per_block; /* rows per block of the FP64 spmv                             */
     double V[15];          /* the value table (first K entries)                           */
-    int32_t kernel;        /* what spmv launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register */
+    int32_t kernel;        /* what an FP64 spmv launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register */
+    int32_t kernel_f32;    /* the same for FP32 (each dtype has its own configuration)   */
+    int32_t rows_per_block_f32;
     int32_t pad_;
 } spmvc_info;
 
@@ -207,7 +209,9 @@ typedef enum {
 spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *bytes, void *stream);
 
 /*
- * Kernel configuration of a handle's spmv (rows per block, LDS staging).
+ * Kernel configuration of a handle's spmv (rows per block, LDS staging), set
+ * for both dtypes (each dtype keeps its own configuration; spmv_tune sets the
+ * tuned dtype's only).
  * rows_per_block: 256..4096, a multiple of 256 (0 = keep).  lds: 1 = stage x
  * windows in LDS when they fit, 0 = gather x directly, -1 = keep.  Used by the
  * autotuner; every valid setting gives y within the same accuracy bound (the
@@ -218,7 +222,8 @@ spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds
 /*
  * Autotuner: times each candidate kernel configuration of `A` for dtype `dt`
  * and `nrhs` (spmv when nrhs == 1, else spmv_block) on scratch vectors, keeps
- * the fastest in the handle and reports it (host outputs, may be NULL).
+ * the fastest in the handle as that dtype's configuration and reports it (host
+ * outputs, may be NULL).
  * Results are cached per (arch, format, n_rows, P, K, dtype, nrhs) in the JSON
  * file named by $SPMVC_TUNE_CACHE when set.  Blocking.
  */

@@ -67,7 +67,8 @@ class Info(ctypes.Structure):
                 ("n_raw", ctypes.c_int64), ("bytes_stream", ctypes.c_int64),
                 ("bytes_ell", ctypes.c_int64), ("bytes_paper", ctypes.c_int64),
                 ("lds_windows", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
-                ("V", ctypes.c_double * 15), ("kernel", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("V", ctypes.c_double * 15), ("kernel", ctypes.c_int32), ("kernel_f32", ctypes.c_int32),
+                ("rows_per_block_f32", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _lib = None
@@ -163,7 +164,9 @@ class Matrix:
         d = {f: getattr(inf, f) for f, _ in Info._fields_ if f != "V"}
         d["V"] = [inf.V[i] for i in range(inf.K)]
         d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT"}[inf.fmt]
-        d["kernel_name"] = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg"}[inf.kernel]
+        names = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg"}
+        d["kernel_name"] = names[inf.kernel]
+        d["kernel_name_f32"] = names[inf.kernel_f32]
         return d
 
     def spmv(self, x, y=None, dtype=None, stream=None):

@@ -56,11 +56,13 @@ int xcd_count() {
 void default_plan(spmvc_matrix_s *M) {
     M->n_xcd = xcd_count();
     if (M->fmt != SPMVC_FMT_DIT) return;
-    for (int rows : {M->rows_per_block, 1024, 512, 256}) {
-        build_lds_plan(M, rows);
-        if (M->plan.n_win > 0) {
-            M->rows_per_block = rows;
-            return;
+    for (int dt : {SPMVC_F64, SPMVC_F32}) {
+        for (int rows : {M->rows_per_block[dt], 1024, 512, 256}) {
+            build_lds_plan(M, dt, rows);
+            if (M->plan[dt].n_win > 0) {
+                M->rows_per_block[dt] = rows;
+                break;
+            }
         }
     }
 }
@@ -222,10 +224,12 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
                             8 * A->n_raw;
         else
             r.bytes_paper = (4 + k4) * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
-        r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode == 1) ? A->plan.n_win : 0;
-        r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan.rows : kBlock;
+        r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode[SPMVC_F64] == 1) ? A->plan[SPMVC_F64].n_win : 0;
+        r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan[SPMVC_F64].rows : kBlock;
         for (int c = 0; c < A->K; ++c) r.V[c] = A->V[c];
-        r.kernel = kernel_kind(A);
+        r.kernel = kernel_kind(A, SPMVC_F64);
+        r.kernel_f32 = kernel_kind(A, SPMVC_F32);
+        r.rows_per_block_f32 = A->fmt == SPMVC_FMT_DIT ? A->plan[SPMVC_F32].rows : kBlock;
         *info = r;
         return SPMVC_OK;
     });
@@ -268,10 +272,12 @@ spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds
         if (rows_per_block != 0 && (rows_per_block < 256 || rows_per_block > 4096 || rows_per_block % 256))
             return fail(SPMVC_EINVAL, "rows_per_block must be a multiple of 256 in 256..4096");
         if (lds < -1 || lds > 1) return fail(SPMVC_EINVAL, "lds must be -1, 0 or 1");
-        if (lds >= 0) A->lds_mode = lds;
-        if (rows_per_block) {
-            A->rows_per_block = rows_per_block;
-            build_lds_plan(A, rows_per_block);
+        for (int dt : {SPMVC_F64, SPMVC_F32}) {
+            if (lds >= 0) A->lds_mode[dt] = lds;
+            if (rows_per_block) {
+                A->rows_per_block[dt] = rows_per_block;
+                build_lds_plan(A, dt, rows_per_block);
+            }
         }
         return SPMVC_OK;
     });

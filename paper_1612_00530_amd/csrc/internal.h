@@ -103,9 +103,9 @@ struct spmvc_matrix_s {
     std::vector<int32_t> h_pat_off; // [P][width]
     std::vector<uint8_t> h_pat_len; // [P]
     // kernel configuration
-    int32_t rows_per_block = 512;
-    int32_t lds_mode = 1; // 1 = stage in LDS when a plan fits
-    spmvc::LdsPlan plan;
+    int32_t rows_per_block[2] = {512, 512};  // per dtype (index SPMVC_F64 / SPMVC_F32)
+    int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits
+    spmvc::LdsPlan plan[2];                // per dtype
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
 };
@@ -119,7 +119,7 @@ void decompress(const spmvc_matrix_s *M, int64_t *row_ptr, int32_t *col, double 
                 hipStream_t s);
 
 // spmv.hip
-void build_lds_plan(spmvc_matrix_s *M, int rows);
+void build_lds_plan(spmvc_matrix_s *M, int dt, int rows);
 // `skip` (device int, may be null): when *skip != 0 the kernels return at once.
 void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s,
                  const int *skip = nullptr);
@@ -138,8 +138,8 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
                            hipStream_t s);
 
 // batched.hip
-// Kernel one spmv of the handle launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register.
-int kernel_kind(const spmvc_matrix_s *M);
+// Kernel one spmv of dtype dt launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register.
+int kernel_kind(const spmvc_matrix_s *M, int dt);
 bool batched_supported(const spmvc_matrix *A, int n_sys);
 spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                               double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,

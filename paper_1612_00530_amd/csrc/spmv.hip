@@ -596,8 +596,8 @@ void launch_direct_nr(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
 }
 
 // Which register-kernel variant fits the matrix: 0 = none, else KK + 1.
-int reg_variant(const spmvc_matrix_s *M) {
-    const LdsPlan &p = M->plan;
+int reg_variant(const spmvc_matrix_s *M, int dt) {
+    const LdsPlan &p = M->plan[dt];
     if (!p.reg) return 0;
     if (M->K == 0 && M->raw_elems > 0) return 1;                       // KK = 0
     if ((M->K == 1 || M->K == 2) && M->raw_elems == 0 && p.v_finite) return M->K + 1;
@@ -607,7 +607,8 @@ int reg_variant(const spmvc_matrix_s *M) {
 // Returns the number of blocks launched (one dot partial each).
 template <class Real>
 unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hipStream_t s) {
-    const LdsPlan &p = M->plan;
+    constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
+    const LdsPlan &p = M->plan[dt];
     a.rows = p.rows;
     a.n_win = p.n_win;
     a.lds_total = p.total;
@@ -621,7 +622,7 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
     const unsigned grid = a.n_main_blocks + escape_blocks(M);
     const Real *xp = static_cast<const Real *>(x);
     Real *yp = static_cast<Real *>(y);
-    const int rv = reg_variant(M);
+    const int rv = reg_variant(M, dt);
     if (rv > 0) {
         const bool f64 = sizeof(Real) == 8;
         a.zero_base = p.zero_base;
@@ -711,8 +712,8 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
         launch_direct_nr<Real, 16>(M, a, nrhs, X, ldx, Y, ldy, s);
 }
 
-bool uses_lds(const spmvc_matrix_s *M) {
-    return M->fmt == SPMVC_FMT_DIT && M->lds_mode == 1 && M->plan.n_win > 0 && M->P > 0;
+bool uses_lds(const spmvc_matrix_s *M, int dt) {
+    return M->fmt == SPMVC_FMT_DIT && M->lds_mode[dt] == 1 && M->plan[dt].n_win > 0 && M->P > 0;
 }
 
 // Returns the number of blocks launched (one dot partial each).
@@ -720,7 +721,8 @@ template <class Real>
 unsigned launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStream_t s, const int *skip,
                        double *dot = nullptr) {
     if (M->n_rows == 0) return 0;
-    if (uses_lds(M)) return launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
+    constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
+    if (uses_lds(M, dt)) return launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
     launch_block_t<Real>(M, 1, x, 1, y, 1, s, skip, dot);
     return static_cast<unsigned>((M->n_pad + kBlock - 1) / kBlock + escape_blocks(M));
 }
@@ -728,10 +730,11 @@ unsigned launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStrea
 }  // namespace
 
 // Cut the displacement set into dense windows for `rows` rows per block and
-// express the pattern table in LDS offsets.  All LDS use stays within
-// kLdsBudgetBytes for FP64 elements (FP32 uses half of the x part).
-void build_lds_plan(spmvc_matrix_s *M, int rows) {
-    LdsPlan &p = M->plan;
+// express the pattern table in LDS offsets (the plan of dtype dt).  All LDS
+// use stays within kLdsBudgetBytes for FP64 elements (FP32 uses half of the x
+// part).
+void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
+    LdsPlan &p = M->plan[dt];
     p.tab.release();
     p.reg_tab64.release();
     p.reg_tab32.release();
@@ -833,9 +836,9 @@ void build_lds_plan(spmvc_matrix_s *M, int rows) {
     }
 }
 
-int kernel_kind(const spmvc_matrix_s *M) {
-    if (!uses_lds(M)) return 0;
-    return reg_variant(M) > 0 ? 2 : 1;
+int kernel_kind(const spmvc_matrix_s *M, int dt) {
+    if (!uses_lds(M, dt)) return 0;
+    return reg_variant(M, dt) > 0 ? 2 : 1;
 }
 
 void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s, const int *skip) {
@@ -845,11 +848,16 @@ void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStr
         launch_spmv_t<float>(M, x, y, s, skip);
 }
 
-// Blocks of the single-vector launch (main + escape): one dot partial each.
+// Blocks of the single-vector launch (main + escape), one dot partial each:
+// the larger of the two dtypes' counts.
 int64_t spmv_dot_blocks(const spmvc_matrix_s *M) {
     if (M->n_rows == 0) return 0;
-    const int64_t main = uses_lds(M) ? (M->n_rows + M->plan.rows - 1) / M->plan.rows
-                                     : (M->n_pad + kBlock - 1) / kBlock;
+    int64_t main = 0;
+    for (int dt : {SPMVC_F64, SPMVC_F32}) {
+        const int64_t m = uses_lds(M, dt) ? (M->n_rows + M->plan[dt].rows - 1) / M->plan[dt].rows
+                                          : (M->n_pad + kBlock - 1) / kBlock;
+        main = std::max(main, m);
+    }
     return main + escape_blocks(M);
 }
 

@@ -89,9 +89,9 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
             auto it = m.find(key);
             if (it != m.end()) {
                 const int rows = static_cast<int>(it->second[0]), lds = static_cast<int>(it->second[1]);
-                A->lds_mode = lds;
-                A->rows_per_block = rows;
-                build_lds_plan(A, rows);
+                A->lds_mode[dt] = lds;
+                A->rows_per_block[dt] = rows;
+                build_lds_plan(A, dt, rows);
                 if (best_rows) *best_rows = rows;
                 if (best_lds) *best_lds = lds;
                 if (best_us) *best_us = it->second[2];
@@ -101,9 +101,9 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         std::vector<Cand> cands;
         if (A->fmt == SPMVC_FMT_DIT && nrhs == 1) {
             for (int rows : {256, 512, 1024, 2048, 4096}) cands.push_back({rows, 1});
-            cands.push_back({A->rows_per_block, 0});
+            cands.push_back({A->rows_per_block[dt], 0});
         } else {
-            cands.push_back({A->rows_per_block, A->lds_mode});
+            cands.push_back({A->rows_per_block[dt], A->lds_mode[dt]});
         }
         const size_t es = dt == SPMVC_F64 ? 8 : 4;
         DevBuf x, y;
@@ -116,10 +116,10 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         double best = 1e300;
         Cand win = cands.front();
         for (const Cand &c : cands) {
-            A->lds_mode = c.lds;
-            A->rows_per_block = c.rows;
-            build_lds_plan(A, c.rows);
-            if (c.lds == 1 && A->fmt == SPMVC_FMT_DIT && A->plan.n_win == 0) continue;  // does not fit
+            A->lds_mode[dt] = c.lds;
+            A->rows_per_block[dt] = c.rows;
+            build_lds_plan(A, dt, c.rows);
+            if (c.lds == 1 && A->fmt == SPMVC_FMT_DIT && A->plan[dt].n_win == 0) continue;  // does not fit
             auto run = [&]() {
                 if (nrhs == 1)
                     launch_spmv(A, dt, x.p, y.p, s);
@@ -148,9 +148,9 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        A->lds_mode = win.lds;
-        A->rows_per_block = win.rows;
-        build_lds_plan(A, win.rows);
+        A->lds_mode[dt] = win.lds;
+        A->rows_per_block[dt] = win.rows;
+        build_lds_plan(A, dt, win.rows);
         if (cpath) {
             auto m = read_cache(cpath);
             m[key] = {static_cast<double>(win.rows), static_cast<double>(win.lds), best};
