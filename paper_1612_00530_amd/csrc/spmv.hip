@@ -348,8 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
 // V[1] * (sum of its first m x values) + V[0] * (sum of the rest): values are
 // scalar operands and there are two multiplies per row instead of one per
 // entry.  Otherwise each entry selects its value per lane.  For the 27-point
-// stencil every row has m = 1.  KK = 0: no value table, every value raw (canonical order),
-// entries past the row length masked.  RPT rows per thread (rows per block =
+// stencil every row has m = 1.  KK = 0: no value table, every value raw
+// (canonical order), read up to the width of the row's 64-row raw slice.  RPT rows per thread (rows per block =
 // 256 * RPT); each thread's row IDs and T are loaded before the windows are
 // staged, so their latency overlaps the staging.  MAXW: entries per row.
 __device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
@@ -447,8 +447,6 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
         }
         if (!active) continue;
         const uint32_t relb = static_cast<uint32_t>(rel) * sizeof(Real);
-        const Real *raw = static_cast<const Real *>(a.raw);
-        const int64_t rb = KK == 0 ? a.raw_slice[row / kSlice] + (row % kSlice) : 0;
         Real acc = Real(0);
         auto xat = [&](int k) -> Real {
             const uint32_t word = w[(k + 1) >> 1];
@@ -456,9 +454,19 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
             return *reinterpret_cast<const Real *>(buf + relb + off);
         };
         if constexpr (KK == 0) {
+            // Raw values up to the width of the row's 64-row slice (the same for
+            // every lane of the wave; the slice's padding is zero): these loads
+            // do not wait for the pattern row.  Entries past the row's length
+            // meet the zero window, so they add 0 * 0.
+            const Real *raw = static_cast<const Real *>(a.raw);
+            const int64_t s0 = a.raw_slice[row / kSlice];
+            const int sw = static_cast<int>((a.raw_slice[row / kSlice + 1] - s0) / kSlice);
+            const Real *rp = raw + s0 + (row % kSlice);
+            Real rv[MAXW];
 #pragma unroll
-            for (int k = 0; k < MAXW; ++k)
-                if (k < len) acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xat(k), acc);
+            for (int k = 0; k < MAXW; ++k) rv[k] = k < sw ? ldg_stream(rp + static_cast<int64_t>(k) * kSlice) : Real(0);
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) acc = fma(rv[k], xat(k), acc);
         } else if (KK == 1 || uni) {
             // every lane of the wave splits at the same position: one sum per
             // value, scaled once (scalar values); the common splits are compiled
