@@ -179,7 +179,8 @@ typedef struct {
     int32_t lds_windows;   /* x windows staged in LDS by the FP64 DIT kernel (0 = direct gather) */
     int32_t rows_per_block; /* rows per block of the FP64 spmv                             */
     double V[15];          /* the value table (first K entries)                           */
-    int32_t kernel;        /* what an FP64 spmv launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register */
+    int32_t kernel;        /* what an FP64 spmv launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register,
+                              3 DIT register, plane-marching */
     int32_t kernel_f32;    /* the same for FP32 (each dtype has its own configuration)   */
     int32_t rows_per_block_f32;
     int32_t pad_;
@@ -213,7 +214,10 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
  * for both dtypes (each dtype keeps its own configuration; spmv_tune sets the
  * tuned dtype's only).
  * rows_per_block: 256..4096, a multiple of 256 (0 = keep).  lds: 1 = stage x
- * windows in LDS when they fit, 0 = gather x directly, -1 = keep.  Used by the
+ * windows in LDS when they fit, 2 = as 1, and where the windows are equally
+ * spaced planes (stencil matrices) let each block march a row tile through
+ * consecutive planes, reusing the windows it already holds; 0 = gather x
+ * directly, -1 = keep.  Used by the
  * autotuner; every valid setting gives y within the same accuracy bound (the
  * kernels sum a row's products in different orders).
  */

@@ -164,7 +164,7 @@ class Matrix:
         d = {f: getattr(inf, f) for f, _ in Info._fields_ if f != "V"}
         d["V"] = [inf.V[i] for i in range(inf.K)]
         d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT"}[inf.fmt]
-        names = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg"}
+        names = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg", 3: "k_dit_march"}
         d["kernel_name"] = names[inf.kernel]
         d["kernel_name_f32"] = names[inf.kernel_f32]
         return d

@@ -53,8 +53,17 @@ int xcd_count() {
     return (arch.rfind("gfx94", 0) == 0 || arch.rfind("gfx95", 0) == 0) ? 8 : 1;
 }
 
+int cu_count() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+        return 256;
+    return n;
+}
+
 void default_plan(spmvc_matrix_s *M) {
     M->n_xcd = xcd_count();
+    M->n_cu = cu_count();
     if (M->fmt != SPMVC_FMT_DIT) return;
     for (int dt : {SPMVC_F64, SPMVC_F32}) {
         for (int rows : {M->rows_per_block[dt], 1024, 512, 256}) {
@@ -224,7 +233,7 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
                             8 * A->n_raw;
         else
             r.bytes_paper = (4 + k4) * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
-        r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode[SPMVC_F64] == 1) ? A->plan[SPMVC_F64].n_win : 0;
+        r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode[SPMVC_F64] >= 1) ? A->plan[SPMVC_F64].n_win : 0;
         r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan[SPMVC_F64].rows : kBlock;
         for (int c = 0; c < A->K; ++c) r.V[c] = A->V[c];
         r.kernel = kernel_kind(A, SPMVC_F64);
@@ -271,7 +280,7 @@ spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds
         if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
         if (rows_per_block != 0 && (rows_per_block < 256 || rows_per_block > 4096 || rows_per_block % 256))
             return fail(SPMVC_EINVAL, "rows_per_block must be a multiple of 256 in 256..4096");
-        if (lds < -1 || lds > 1) return fail(SPMVC_EINVAL, "lds must be -1, 0 or 1");
+        if (lds < -1 || lds > 2) return fail(SPMVC_EINVAL, "lds must be -1, 0, 1 or 2");
         for (int dt : {SPMVC_F64, SPMVC_F32}) {
             if (lds >= 0) A->lds_mode[dt] = lds;
             if (rows_per_block) {

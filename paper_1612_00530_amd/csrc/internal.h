@@ -80,6 +80,14 @@ struct LdsPlan {
     DevBuf reg_tab64, reg_tab32;  // byte offsets for FP64 and FP32 elements
     bool v_finite = false;        // every value-table entry finite (v * 0 == 0)
     bool v_same_lo = false;       // value-table entries share their low 32 bits
+    // plane-marching form of the register kernel: windows equally spaced by
+    // m_S rows, a ring of m_NB = windows + 1 buffers of m_L elements, one
+    // table per ring phase (m_NB tables of P rows of kRegTw uint16)
+    bool march = false;
+    bool m_tab_lds = false;       // the phase tables are copied into LDS
+    int64_t m_S = 0, m_nz = 0, m_lo0 = 0;
+    int32_t m_np = 0, m_C = 1, m_L = 0, m_NB = 0, m_NW = 0, m_zero_base = 0;
+    DevBuf m_tab64, m_tab32;
 };
 
 constexpr int kRegW = 31;   // longest pattern the register kernel takes
@@ -104,10 +112,12 @@ struct spmvc_matrix_s {
     std::vector<uint8_t> h_pat_len; // [P]
     // kernel configuration
     int32_t rows_per_block[2] = {512, 512};  // per dtype (index SPMVC_F64 / SPMVC_F32)
-    int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits
+    int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits,
+                                           // 2 = as 1, plane-marching where it applies
     spmvc::LdsPlan plan[2];                // per dtype
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
+    int32_t n_cu = 256;         // compute units of the device (grid sizing)
 };
 
 namespace spmvc {
@@ -138,7 +148,8 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
                            hipStream_t s);
 
 // batched.hip
-// Kernel one spmv of dtype dt launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register.
+// Kernel one spmv of dtype dt launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register,
+// 3 DIT register, plane-marching.
 int kernel_kind(const spmvc_matrix_s *M, int dt);
 bool batched_supported(const spmvc_matrix *A, int n_sys);
 spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,

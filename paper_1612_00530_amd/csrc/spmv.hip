@@ -69,6 +69,15 @@ struct SpmvArgs {
     int32_t lds_x_bytes;           // bytes of windows + zero window (16-byte multiple)
     int32_t n_xcd;                 // XCDs the blocks are spread over (tile mapping)
     int32_t async_lds;             // x is 16-byte aligned: stage windows with direct LDS loads
+    // plane-marching kernel (k_dit_march)
+    int64_t m_S;                   // row distance between consecutive windows (one plane)
+    int64_t m_nz;                  // planes: ceil(n_rows / m_S)
+    int64_t m_lo0;                 // start of window 0 relative to the tile's first row
+    int32_t m_np;                  // row tiles per plane
+    int32_t m_C;                   // planes per block
+    int32_t m_L;                   // elements per window buffer
+    int32_t m_NB;                  // window buffers in the ring (windows + 1)
+    int32_t m_NW;                  // windows a tile reads
 };
 
 template <class Real> __device__ __forceinline__ Real vtab(const SpmvArgs &a, int c);
@@ -414,7 +423,7 @@ __device__ __forceinline__ void load_tile_meta(const SpmvArgs &a, const Real *__
 // windows + zero window), pattern rows at `tab`.  Adds the tile's x.y to dotc.
 template <class Real, int KK, int RPT, int MAXW>
 __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char *buf, const uint4 *tab, int64_t r0,
-                                         const uint32_t (&idv)[RPT], const int (&t0v)[RPT],
+                                         int rel_end, const uint32_t (&idv)[RPT], const int (&t0v)[RPT],
                                          const Real (&xrow)[RPT], Real v0, Real v1, Real *__restrict__ y,
                                          double &dotc) {
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
@@ -422,7 +431,7 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
     for (int j = 0; j < RPT; ++j) {
         const int rel = threadIdx.x + j * kBlock;
         const int64_t row = r0 + rel;
-        const bool active = row < a.n_rows && idv[j] != esc;
+        const bool active = rel < rel_end && row < a.n_rows && idv[j] != esc;
         const uint4 *tp = tab + static_cast<int64_t>(active ? idv[j] : 0u) * (kRegTw * 2 / 16);
         uint32_t w[16];
 #pragma unroll
@@ -527,7 +536,117 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__re
     const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
     Real v0, v1;
     value_pair<Real, KK>(a, v0, v1);
-    reg_tile<Real, KK, RPT, MAXW>(a, smem, tab, r0, idv, t0v, xrow, v0, v1, y, dotc);
+    reg_tile<Real, KK, RPT, MAXW>(a, smem, tab, r0, kBlock * RPT, idv, t0v, xrow, v0, v1, y, dotc);
+    emit_dot(a, dotc);
+}
+
+// ---- DIT, plane-marching register kernel ------------------------------------------
+// For matrices whose x windows are NW equal windows spaced one plane (m_S rows)
+// apart -- the 27-point stencil: planes z-1, z, z+1.  A block owns one row
+// tile (rows p0 .. p0 + R of a plane) in m_C consecutive planes.  Window w of
+// the tile in plane z is plane slot q = z + w, so the tile in plane z + 1
+// needs only one slot the tile in plane z did not: the block keeps NW + 1 window
+// buffers in LDS as a ring (slot q in buffer q mod NB) and, while it computes
+// plane z, copies slot z + NW into the free buffer.  Each plane step thus
+// stages one window instead of NW, and the block's setup (arguments, table,
+// first windows) is paid once per m_C tiles.  The pattern table is held in LDS
+// once per ring phase (z mod NB), with each entry's byte offset resolved for
+// that phase, so the inner loop is the register kernel's (reg_tile).
+template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
+__global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
+    if (a.skip && *a.skip) return;
+    if (blockIdx.x >= a.n_main_blocks) {
+        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
+                                        1, x, 1, y, 1));
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kRows = kBlock * RPT;
+    Real *xs = reinterpret_cast<Real *>(smem);
+    const int64_t ord = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd);
+    const int64_t pt = ord % a.m_np, zc = ord / a.m_np;
+    const int64_t p0 = pt * kRows;
+    const int rel_end = static_cast<int>(a.m_S - p0 < kRows ? a.m_S - p0 : kRows);
+    const int64_t z_beg = zc * a.m_C;
+    const int64_t z_end = z_beg + a.m_C < a.m_nz ? z_beg + a.m_C : a.m_nz;
+    const int L = a.m_L, NB = a.m_NB;
+    // zero window and the per-phase pattern tables
+    for (int e = threadIdx.x; e < a.zero_len; e += kBlock) xs[a.zero_base + e] = Real(0);
+    const int tab_u4 = a.P * (kRegTw * 2 / 16);  // uint4 per phase
+    const uint4 *tab_all = reinterpret_cast<const uint4 *>(a.reg_tab);
+    if constexpr (TAB_LDS) {
+        uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
+        for (int e = threadIdx.x; e < tab_u4 * NB; e += kBlock) tab_s[e] = tab_all[e];
+        tab_all = tab_s;
+    }
+    // copy plane slot q (rows q*S + p0 + lo0 .. + L) into its ring buffer
+    auto stage_slot = [&](int64_t q) {
+        constexpr int PER = 16 / sizeof(Real);
+        constexpr int CH = 64 * PER;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int64_t g0 = q * a.m_S + p0 + a.m_lo0;
+        Real *dst = xs + static_cast<int64_t>(q % NB) * L;
+        if (a.async_lds && g0 >= 0 && g0 + L <= a.n_cols) {
+            const int nch = (L + CH - 1) / CH;
+            for (int c = wave; c < nch; c += kBlock / 64) {
+                const int e = c * CH + lane * PER;
+                if (e < L) lds_load16(x + g0 + e, dst + c * CH);
+            }
+        } else {
+            const int64_t last = a.n_cols - 1;
+            for (int e = threadIdx.x; e < L; e += kBlock) {
+                int64_t g = g0 + e;
+                g = g < 0 ? 0 : (g > last ? last : g);
+                dst[e] = x[g];
+            }
+        }
+    };
+    Real v0, v1;
+    value_pair<Real, KK>(a, v0, v1);
+    double dotc = 0.0;
+    // next step's metadata as the raw aligned words that hold it (read after the wait)
+    uint32_t idw[RPT], t0w[RPT];
+    Real xn[RPT];
+    auto load_raw_meta = [&](int64_t r0) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int64_t row = r0 + threadIdx.x + j * kBlock;
+            const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
+            const int64_t ib = rc * a.id_bytes;
+            idw[j] = *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(a.ids) + (ib & ~int64_t(3)));
+            t0w[j] = KK >= 1 ? *reinterpret_cast<const uint32_t *>(a.T + (rc & ~int64_t(3))) : 0u;
+            xn[j] = a.dot ? x[rc] : Real(0);
+        }
+    };
+    if (z_beg < z_end) {
+        load_raw_meta(z_beg * a.m_S + p0);
+        for (int w = 0; w < a.m_NW; ++w) stage_slot(z_beg + w);
+    }
+    const uint32_t id_mask = a.id_bytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * a.id_bytes)) - 1u);
+    for (int64_t z = z_beg; z < z_end; ++z) {
+        // plane z's windows and metadata have landed (every wave's copies), and
+        // every wave is done with the buffer of slot z - 1
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int64_t r0 = z * a.m_S + p0;
+        uint32_t idv[RPT];
+        int t0v[RPT];
+        Real xrow[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int64_t row = r0 + threadIdx.x + j * kBlock;
+            const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
+            idv[j] = (idw[j] >> (8 * ((rc * a.id_bytes) & 3))) & id_mask;
+            t0v[j] = static_cast<int>((t0w[j] >> (8 * (rc & 3))) & 0xFFu);
+            xrow[j] = xn[j];
+        }
+        if (z + 1 < z_end) {
+            load_raw_meta(r0 + a.m_S);
+            stage_slot(z + a.m_NW);
+        }
+        const uint4 *tab = tab_all + static_cast<int64_t>(z % NB) * tab_u4;
+        reg_tile<Real, KK, RPT, MAXW>(a, smem, tab, r0, rel_end, idv, t0v, xrow, v0, v1, y, dotc);
+    }
     emit_dot(a, dotc);
 }
 
@@ -640,6 +759,61 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
         a.lds_x_bytes = (x_bytes + 15) & ~15;
         const int rpt = p.rows / kBlock;
         const bool w27 = M->width <= 27;  // the 27-point stencil: no padded step
+        if (M->lds_mode[dt] == 2 && p.march) {
+            a.m_S = p.m_S;
+            a.m_nz = p.m_nz;
+            a.m_lo0 = p.m_lo0;
+            a.m_np = p.m_np;
+            a.m_C = p.m_C;
+            a.m_L = p.m_L;
+            a.m_NB = p.m_NB;
+            a.m_NW = p.m_NW;
+            a.zero_base = p.m_zero_base;
+            a.zero_len = p.rows;
+            a.reg_tab = f64 ? p.m_tab64.as<uint16_t>() : p.m_tab32.as<uint16_t>();
+            const int mx_bytes = static_cast<int>(sizeof(Real)) * (p.m_zero_base + p.rows);
+            a.lds_x_bytes = (mx_bytes + 15) & ~15;
+            const size_t msh = a.lds_x_bytes + (p.m_tab_lds ? static_cast<size_t>(p.m_NB) * M->P * kRegTw * 2 : 0);
+            const int64_t nzc = (p.m_nz + p.m_C - 1) / p.m_C;
+            a.n_main_blocks = static_cast<unsigned>(p.m_np * nzc);
+            const unsigned mgrid = a.n_main_blocks + escape_blocks(M);
+#define SPMVC_MARCH_W(KK, TL, R)                                                               \
+    if (w27)                                                                                   \
+        k_dit_march<Real, KK, TL, R, 27><<<mgrid, kBlock, msh, s>>>(a, xp, yp);                \
+    else                                                                                       \
+        k_dit_march<Real, KK, TL, R, kRegW><<<mgrid, kBlock, msh, s>>>(a, xp, yp);
+#define SPMVC_MARCH_R(KK, TL)    \
+    if (rpt == 1) {              \
+        SPMVC_MARCH_W(KK, TL, 1) \
+    } else if (rpt == 2) {       \
+        SPMVC_MARCH_W(KK, TL, 2) \
+    } else {                     \
+        SPMVC_MARCH_W(KK, TL, 4) \
+    }
+            if (rv == 1) {
+                if (p.m_tab_lds) {
+                    SPMVC_MARCH_R(0, true)
+                } else {
+                    SPMVC_MARCH_R(0, false)
+                }
+            } else if (rv == 2) {
+                if (p.m_tab_lds) {
+                    SPMVC_MARCH_R(1, true)
+                } else {
+                    SPMVC_MARCH_R(1, false)
+                }
+            } else {
+                if (p.m_tab_lds) {
+                    SPMVC_MARCH_R(2, true)
+                } else {
+                    SPMVC_MARCH_R(2, false)
+                }
+            }
+#undef SPMVC_MARCH_R
+#undef SPMVC_MARCH_W
+            SPMVC_CHECK_LAUNCH();
+            return mgrid;
+        }
         size_t shmem = a.lds_x_bytes;
         if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
 #define SPMVC_REG_W(KK, TL, R)                                                                                  \
@@ -721,7 +895,7 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
 }
 
 bool uses_lds(const spmvc_matrix_s *M, int dt) {
-    return M->fmt == SPMVC_FMT_DIT && M->lds_mode[dt] == 1 && M->plan[dt].n_win > 0 && M->P > 0;
+    return M->fmt == SPMVC_FMT_DIT && M->lds_mode[dt] >= 1 && M->plan[dt].n_win > 0 && M->P > 0;
 }
 
 // Returns the number of blocks launched (one dot partial each).
@@ -736,6 +910,73 @@ unsigned launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStrea
 }
 
 }  // namespace
+
+// Plane-marching form of the register-kernel plan: applies when the windows
+// are equally spaced (by S rows, a multiple of 4) and equally long, so that
+// window w of the tile in plane z is window w - 1 of the tile in plane z + 1.
+// The ring holds NB = windows + 1 buffers; table phase ph resolves window w
+// of a tile to buffer (ph + w) mod NB.  Planes per block (m_C) are chosen so
+// that the grid about fills the device once.
+static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<std::pair<int64_t, int64_t>> &win,
+                      const int64_t *lo, const int64_t *len, int rows) {
+    if (!p.reg || p.n_win < 2) return;
+    const int NW = p.n_win, NB = NW + 1;
+    const int64_t S = lo[1] - lo[0];
+    if (S <= 0 || S % 4 != 0) return;
+    for (int w = 1; w < NW; ++w)
+        if (lo[w] - lo[w - 1] != S || len[w] != len[0]) return;
+    const int64_t L = len[0];
+    const int64_t x_elems = NB * L + rows;  // ring + zero window
+    const int64_t x_bytes64 = ((x_elems * 8) + 15) & ~int64_t(15);
+    if (rows > 1024) return;  // row tiles of 256, 512 or 1024
+    const int64_t tab_bytes = static_cast<int64_t>(NB) * M->P * kRegTw * 2;
+    const bool tab_lds = tab_bytes <= 16 * 1024 && x_bytes64 + tab_bytes <= kLdsBudgetBytes;
+    if (x_bytes64 > kLdsBudgetBytes || x_elems * 8 > 65535) return;
+    const int W = M->width;
+    auto window_of = [&](int64_t d) {
+        int w = 0;
+        while (!(d >= win[w].first && d <= win[w].second)) ++w;
+        return w;
+    };
+    for (int es : {8, 4}) {
+        std::vector<uint16_t> rt(static_cast<size_t>(NB) * M->P * kRegTw, 0);
+        for (int ph = 0; ph < NB; ++ph)
+            for (int q = 0; q < M->P; ++q) {
+                const int Lq = M->h_pat_len[q];
+                uint16_t *r = rt.data() + (static_cast<size_t>(ph) * M->P + q) * kRegTw;
+                r[0] = static_cast<uint16_t>(Lq);
+                const bool rev = M->K >= 1;
+                for (int k = 0; k < kRegW; ++k) {
+                    int64_t e = NB * L;  // zero window
+                    if (k < Lq) {
+                        const int64_t d = M->h_pat_off[static_cast<size_t>(q) * W + (rev ? Lq - 1 - k : k)];
+                        const int w = window_of(d);
+                        e = ((ph + w) % NB) * L + (d - lo[w]);
+                    }
+                    r[1 + k] = static_cast<uint16_t>(e * es);
+                }
+            }
+        DevBuf &dst = es == 8 ? p.m_tab64 : p.m_tab32;
+        dst.alloc(sizeof(uint16_t) * rt.size());
+        SPMVC_HIP(hipMemcpy(dst.p, rt.data(), dst.bytes, hipMemcpyHostToDevice));
+    }
+    p.m_S = S;
+    p.m_nz = (M->n_rows + S - 1) / S;
+    p.m_lo0 = lo[0];
+    p.m_np = static_cast<int32_t>((S + rows - 1) / rows);
+    p.m_L = static_cast<int32_t>(L);
+    p.m_NB = NB;
+    p.m_NW = NW;
+    p.m_zero_base = static_cast<int32_t>(NB * L);
+    // blocks resident at once: LDS of 160 KB per CU, at most 6 per CU
+    p.m_tab_lds = tab_lds;
+    const int64_t block_lds = x_bytes64 + (tab_lds ? tab_bytes : 0);
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(6, (160 * 1024) / block_lds));
+    const int64_t resident = per_cu * M->n_cu;
+    const int64_t steps = static_cast<int64_t>(p.m_np) * p.m_nz;
+    p.m_C = static_cast<int32_t>(std::max<int64_t>(1, (steps + resident - 1) / resident));
+    p.march = true;
+}
 
 // Cut the displacement set into dense windows for `rows` rows per block and
 // express the pattern table in LDS offsets (the plan of dtype dt).  All LDS
@@ -752,6 +993,9 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     p.tab_in_lds = false;
     p.reg = false;
     p.reg_tab_in_lds = false;
+    p.march = false;
+    p.m_tab64.release();
+    p.m_tab32.release();
     if (M->fmt != SPMVC_FMT_DIT || M->P == 0 || M->width == 0) return;
     const int W = M->width;
     std::set<int64_t> ds;
@@ -842,11 +1086,13 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         p.reg_tab_in_lds = reg_tab_bytes <= 16 * 1024 && x_bytes64 + reg_tab_bytes <= kLdsBudgetBytes;
         p.reg = true;
     }
+    build_march_plan(M, p, win, lo, len, rows);
 }
 
 int kernel_kind(const spmvc_matrix_s *M, int dt) {
     if (!uses_lds(M, dt)) return 0;
-    return reg_variant(M, dt) > 0 ? 2 : 1;
+    if (reg_variant(M, dt) == 0) return 1;
+    return M->lds_mode[dt] == 2 && M->plan[dt].march ? 3 : 2;
 }
 
 void launch_spmv(const spmvc_matrix_s *M, int dt, const void *x, void *y, hipStream_t s, const int *skip) {
@@ -862,8 +1108,9 @@ int64_t spmv_dot_blocks(const spmvc_matrix_s *M) {
     if (M->n_rows == 0) return 0;
     int64_t main = 0;
     for (int dt : {SPMVC_F64, SPMVC_F32}) {
-        const int64_t m = uses_lds(M, dt) ? (M->n_rows + M->plan[dt].rows - 1) / M->plan[dt].rows
-                                          : (M->n_pad + kBlock - 1) / kBlock;
+        const LdsPlan &p = M->plan[dt];
+        int64_t m = uses_lds(M, dt) ? (M->n_rows + p.rows - 1) / p.rows : (M->n_pad + kBlock - 1) / kBlock;
+        if (uses_lds(M, dt) && p.march) m = std::max<int64_t>(m, p.m_np * ((p.m_nz + p.m_C - 1) / p.m_C));
         main = std::max(main, m);
     }
     return main + escape_blocks(M);

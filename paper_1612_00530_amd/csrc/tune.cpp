@@ -1,8 +1,9 @@
 // Autotuner: time each kernel configuration of a handle and keep the fastest.
 //
 // Candidates (single right-hand side, DIT): rows per block in {256 .. 4096}
-// with the x windows staged in LDS, and the direct-gather kernel (x read
-// through the L1/L2 caches).  Every candidate gives the same result; only the
+// with the x windows staged in LDS, the plane-marching form with row tiles of
+// {256, 512, 1024}, and the direct-gather kernel (x read through the L1/L2
+// caches).  Every candidate gives the same result; only the
 // time differs.  A candidate's time is the median over repetitions of the mean
 // of a run of back-to-back launches.  Winners are cached per (arch, format, rows, P, K, dtype, nrhs)
 // in the JSON object stored in the file named by $SPMVC_TUNE_CACHE.
@@ -101,6 +102,7 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         std::vector<Cand> cands;
         if (A->fmt == SPMVC_FMT_DIT && nrhs == 1) {
             for (int rows : {256, 512, 1024, 2048, 4096}) cands.push_back({rows, 1});
+            for (int rows : {256, 512, 1024}) cands.push_back({rows, 2});
             cands.push_back({A->rows_per_block[dt], 0});
         } else {
             cands.push_back({A->rows_per_block[dt], A->lds_mode[dt]});
@@ -119,7 +121,8 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
             A->lds_mode[dt] = c.lds;
             A->rows_per_block[dt] = c.rows;
             build_lds_plan(A, dt, c.rows);
-            if (c.lds == 1 && A->fmt == SPMVC_FMT_DIT && A->plan[dt].n_win == 0) continue;  // does not fit
+            if (c.lds >= 1 && A->fmt == SPMVC_FMT_DIT && A->plan[dt].n_win == 0) continue;  // does not fit
+            if (c.lds == 2 && kernel_kind(A, dt) != 3) continue;  // no plane-marching form
             auto run = [&]() {
                 if (nrhs == 1)
                     launch_spmv(A, dt, x.p, y.p, s);

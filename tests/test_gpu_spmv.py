@@ -71,7 +71,8 @@ def test_stencil104_full_size_parity(fmt):
     assert np.array_equal(y1, oracle.spmv(A, np.ones(A.n_cols)))
 
 
-@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (1024, 1), (2048, 1), (4096, 1), (1024, 0)])
+@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (1024, 1), (2048, 1), (4096, 1), (1024, 0),
+                                      (256, 2), (512, 2), (1024, 2)])
 def test_dit_kernel_configs_agree(rows, lds):
     say("case: DIT config", rows, lds)
     A = stencil27(40, 37, 23)
@@ -80,6 +81,52 @@ def test_dit_kernel_configs_agree(rows, lds):
     M.set_config(rows, lds)
     y = gpu_spmv(M, x)
     assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
+
+
+@pytest.mark.parametrize("grid,rows", [((104, 104, 104), 256), ((104, 104, 104), 512), ((104, 104, 104), 1024),
+                                       ((61, 17, 33), 256), ((128, 128, 128), 512)])
+def test_plane_marching_equals_register_kernel(grid, rows):
+    """The plane-marching kernel computes every row with the register kernel's
+    code, so y agrees bit for bit; also with x not 16-byte aligned (windows
+    copied through registers) and in FP32.  61 x 17: planes of 1037 rows; the
+    march steps by the spacing of the 4-aligned windows (1036 or 1040 rows),
+    which partitions the rows just as well."""
+    say("case: plane marching vs register", grid, rows)
+    torch = torch_mod()
+    A = stencil27(*grid)
+    xh = uniform_vector(A.n_cols, seed=9)
+    M = compress(A, fmt="DIT")
+    marching = True
+    buf = torch.zeros(A.n_cols + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = torch.from_numpy(xh).cuda()
+    for x in (buf[1:].clone(), buf[1:]):
+        M.set_config(rows, 1)
+        y_reg = M.spmv(x).cpu().numpy()
+        M.set_config(rows, 2)
+        assert M.info()["kernel_name"] == ("k_dit_march" if marching else "k_dit_reg")
+        y_m = M.spmv(x).cpu().numpy()
+        assert same_bits(y_m, y_reg)
+        assert max_rel_err(A, xh, y_m, oracle.spmv(A, xh)) <= 1e-14
+        x32 = x.float()
+        M.set_config(rows, 1)
+        y32 = M.spmv(x32).cpu().numpy()
+        M.set_config(rows, 2)
+        assert same_bits(M.spmv(x32).cpu().numpy(), y32)
+
+
+def test_plane_marching_raw_values_irregular():
+    """Every value raw (K = 0): the marching kernel's raw path against the oracle."""
+    say("case: plane marching, irregular 128^3")
+    A = stencil27_irregular(128, 128, 128, seed=0)
+    x = uniform_vector(A.n_cols, seed=4)
+    M = compress(A, fmt="DIT")
+    M.set_config(512, 1)
+    y_reg = gpu_spmv(M, x)
+    M.set_config(512, 2)
+    assert M.info()["kernel_name"] == "k_dit_march"
+    y_m = gpu_spmv(M, x)
+    assert max_rel_err(A, x, y_m, oracle.spmv(A, x)) <= 1e-14
+    assert same_bits(y_m, y_reg)
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
