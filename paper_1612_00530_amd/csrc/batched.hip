@@ -120,22 +120,41 @@ __device__ __forceinline__ double block_sum(double v) {
 // (t0 <= k < len) of x at the entries' columns.  All MAXW pattern offsets are
 // read first and all MAXW loads issued before any add, so a row's gathers are
 // in flight together; entries past len read the row's own element and add 0.
-template <int MAXW>
+// VEC consecutive doubles (one lane's right-hand sides), as one load.
+template <int VEC> struct VecT;
+template <> struct VecT<1> {
+    double v[1];
+    __device__ __forceinline__ static VecT load(const double *p) { return VecT{{*p}}; }
+};
+template <> struct VecT<2> {
+    double v[2];
+    __device__ __forceinline__ static VecT load(const double *p) {
+        const double2 t = *reinterpret_cast<const double2 *>(p);
+        return VecT{{t.x, t.y}};
+    }
+};
+
+template <int MAXW, int VEC>
 __device__ __forceinline__ void gather_row(const int32_t *__restrict__ pat, int len, int t0, const double *pr,
-                                           int64_t lrow, int nr, double &s0, double &s1) {
+                                           int64_t lrow, int nr, double (&s0)[VEC], double (&s1)[VEC]) {
     int32_t off[MAXW];
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) off[k] = k < len ? pat[k] : 0;
-    double xv[MAXW];
+    VecT<VEC> xv[MAXW];
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k) xv[k] = pr[(lrow + off[k]) * nr];
-    s0 = 0.0;
-    s1 = 0.0;
+    for (int k = 0; k < MAXW; ++k) xv[k] = VecT<VEC>::load(pr + (lrow + off[k]) * nr);
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k) {
-        s0 += k < t0 ? xv[k] : 0.0;
-        s1 += (k >= t0 && k < len) ? xv[k] : 0.0;
+    for (int v = 0; v < VEC; ++v) {
+        s0[v] = 0.0;
+        s1[v] = 0.0;
     }
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            s0[v] += k < t0 ? xv[k].v[v] : 0.0;
+            s1[v] += (k >= t0 && k < len) ? xv[k].v[v] : 0.0;
+        }
 }
 
 // Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs.
@@ -156,7 +175,9 @@ __device__ __forceinline__ int chunk_tile(unsigned bid, unsigned nb, int n_xcd) 
     return static_cast<int>(((j / kChunk) * n_xcd + x) * kChunk + j % kChunk);
 }
 
-template <int LPR, int MAXW>
+// VEC = 2 when nrhs is even: each lane takes two adjacent right-hand sides
+// with 16-byte loads, halving the gather instructions per row.
+template <int LPR, int MAXW, int VEC>
 __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict__ Pin, double *__restrict__ Qout,
                                               double *part, int with_dot) {
     extern __shared__ int32_t pat_s[];
@@ -165,7 +186,7 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
     if (!b.sys_active[s]) return;  // uniform per block
     const SysDesc &d = b.sys[s];
     const int nr = b.nrhs;
-    const int r = threadIdx.x % LPR;
+    const int r = (threadIdx.x % LPR) * VEC;  // this lane's first rhs
     const bool lane_on = r < nr;
     const int rc = lane_on ? r : 0;  // idle lanes mirror rhs 0 and store nothing
     const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
@@ -190,30 +211,48 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
         ptab = pat_s;
     }
     const double *pr = Pin + d.row0 * nr + rc;
-    double dotc = 0.0;
+    double dotc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) dotc[v] = 0.0;
 #pragma unroll
     for (int pass = 0; pass < LPR; ++pass) {
         const int64_t lrow = lbase + pass * (kT / LPR);
         if (lrow >= d.n) break;
         const int64_t grow = d.row0 + lrow;
         const uint32_t id = idv[pass];
-        double acc = 0.0;
+        double acc[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
         if (id != esc) {
             if (d.K > 0) {
                 const int32_t *pat = ptab + static_cast<int64_t>(id) * d.width;
                 // exclusive run ends: entries [0, t0) take V[0], [t0, len) V[1]
                 const int len = lenv[pass], t0 = t0v[pass];
-                double s0, s1;
+                double s0[VEC], s1[VEC];
                 if (len <= MAXW) {
-                    gather_row<MAXW>(pat, len, t0, pr, lrow, nr, s0, s1);
+                    gather_row<MAXW, VEC>(pat, len, t0, pr, lrow, nr, s0, s1);
                 } else {
-                    s0 = 0.0;
-                    s1 = 0.0;
-                    for (int k = 0; k < t0; ++k) s0 += pr[(lrow + pat[k]) * nr];
-                    for (int k = t0; k < len; ++k) s1 += pr[(lrow + pat[k]) * nr];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        s0[v] = 0.0;
+                        s1[v] = 0.0;
+                    }
+                    for (int k = 0; k < len; ++k) {
+                        const VecT<VEC> xv = VecT<VEC>::load(pr + (lrow + pat[k]) * nr);
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) {
+                            if (k < t0)
+                                s0[v] += xv.v[v];
+                            else
+                                s1[v] += xv.v[v];
+                        }
+                    }
                 }
-                acc = d.V[0] * s0;
-                if (d.K > 1) acc = fma(d.V[1], s1, acc);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    acc[v] = d.V[0] * s0[v];
+                    if (d.K > 1) acc[v] = fma(d.V[1], s1[v], acc[v]);
+                }
             }
         } else {
             // escape row: position in the (ascending) escape-row list by bisection
@@ -222,17 +261,27 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
                 const int64_t mid = (lo + hi) / 2;
                 if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
             }
-            for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e)
-                acc = fma(d.esc_val[e], pr[static_cast<int64_t>(d.esc_col[e]) * nr], acc);
+            for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) {
+                const VecT<VEC> xv = VecT<VEC>::load(pr + static_cast<int64_t>(d.esc_col[e]) * nr);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] = fma(d.esc_val[e], xv.v[v], acc[v]);
+            }
         }
         if (lane_on) {
-            Qout[grow * nr + r] = acc;
-            if (with_dot) dotc += Pin[grow * nr + r] * acc;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                Qout[grow * nr + r + v] = acc[v];
+                if (with_dot) dotc[v] += Pin[grow * nr + r + v] * acc[v];
+            }
         }
     }
     if (!with_dot) return;
-    const double t = rhs_sum<LPR>(dotc);
-    if (threadIdx.x < nr) part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        const double t = rhs_sum<LPR>(dotc[v]);
+        const int rr = static_cast<int>(threadIdx.x) * VEC + v;
+        if (threadIdx.x < LPR && rr < nr) part[static_cast<int64_t>(tile) * nr + rr] = t;
+    }
 }
 
 // Sum of the tiles' partials of system s for rhs r (fixed order), in every thread.
@@ -477,19 +526,21 @@ __global__ void k_set_all(int32_t *p, int32_t v, int n) {
             KERNEL<16><<<GRID, kT, 0, STREAM>>>(__VA_ARGS__);                        \
     } while (0)
 
-// The same for k_bspmv with its second template argument W and LDS bytes SH.
-#define SPMVC_BSPMV_LAUNCH(W, GRID, SH, STREAM, ...)                                 \
+// The same for k_bspmv (width W, VEC right-hand sides per lane, LDS bytes SH);
+// LPR = ceil(nrhs / VEC) rounded up to a power of two.
+#define SPMVC_BSPMV_LAUNCH(W, VEC, GRID, SH, STREAM, ...)                            \
     do {                                                                             \
-        if (b.nrhs <= 1)                                                             \
-            k_bspmv<1, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
-        else if (b.nrhs <= 2)                                                        \
-            k_bspmv<2, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
-        else if (b.nrhs <= 4)                                                        \
-            k_bspmv<4, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
-        else if (b.nrhs <= 8)                                                        \
-            k_bspmv<8, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                    \
+        const int lanes_ = (b.nrhs + VEC - 1) / VEC;                                 \
+        if (lanes_ <= 1)                                                             \
+            k_bspmv<1, W, VEC><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);               \
+        else if (lanes_ <= 2)                                                        \
+            k_bspmv<2, W, VEC><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);               \
+        else if (lanes_ <= 4)                                                        \
+            k_bspmv<4, W, VEC><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);               \
+        else if (lanes_ <= 8)                                                        \
+            k_bspmv<8, W, VEC><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);               \
         else                                                                         \
-            k_bspmv<16, W><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);                   \
+            k_bspmv<16, W, VEC><<<GRID, kT, SH, STREAM>>>(__VA_ARGS__);              \
     } while (0)
 
 constexpr int kTabLdsInts = 4096;  // pattern tables up to 16 KB are copied to LDS
@@ -497,13 +548,21 @@ constexpr int kTabLdsInts = 4096;  // pattern tables up to 16 KB are copied to L
 void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles);
     const size_t sh = b.tab_lds ? sizeof(int32_t) * static_cast<size_t>(b.tab_ints) : 0;
-    if (b.max_width <= 28)
-        SPMVC_BSPMV_LAUNCH(28, g, sh, s, b, Pin, Qout, b.part, with_dot);
-    else
-        SPMVC_BSPMV_LAUNCH(32, g, sh, s, b, Pin, Qout, b.part, with_dot);
+    // two right-hand sides per lane when every row's block starts 16-byte aligned
+    const bool pairs = b.nrhs % 2 == 0;
+    if (b.max_width <= 28) {
+        if (pairs)
+            SPMVC_BSPMV_LAUNCH(28, 2, g, sh, s, b, Pin, Qout, b.part, with_dot);
+        else
+            SPMVC_BSPMV_LAUNCH(28, 1, g, sh, s, b, Pin, Qout, b.part, with_dot);
+    } else {
+        if (pairs)
+            SPMVC_BSPMV_LAUNCH(32, 2, g, sh, s, b, Pin, Qout, b.part, with_dot);
+        else
+            SPMVC_BSPMV_LAUNCH(32, 1, g, sh, s, b, Pin, Qout, b.part, with_dot);
+    }
 }
 
-// One CG iteration for every running pair.
 void record_iteration(const Batch &b, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles), ns = static_cast<unsigned>(b.n_sys);
     launch_bspmv(b, b.P, b.Q, 1, s);

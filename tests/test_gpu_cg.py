@@ -49,6 +49,31 @@ def test_fp64_cg_ones(fmt, grid):
     assert np.abs(x - 1).max() < 1e-7
 
 
+@pytest.mark.parametrize("rows,lds", [(256, 2), (512, 2), (1024, 1), (512, 0)])
+def test_cg_under_each_spmv_configuration(rows, lds):
+    """CG takes its p.Ap partials from whichever SpMV kernel the handle runs
+    (plane-marching, register, direct gather), with that kernel's own number of
+    blocks; FP64 and mixed precision must still reach the oracle's result."""
+    say("case: cg config", rows, lds)
+    torch = torch_mod()
+    P = lib()
+    A = stencil27(48, 40, 36)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    M = compress(A, fmt="DIT")
+    M.set_config(rows, lds)
+    bt = torch.from_numpy(b).cuda()
+    _, _, it_ref, _ = oracle.cg(A, b)
+    for mode in (0, 1):
+        st, xs, stats = P.cg_solve(M, bt, mode=mode)
+        torch.cuda.synchronize()
+        x = xs[0].cpu().numpy()
+        assert st == 0 and stats[0]["status"] == 0
+        if mode == 0:
+            assert abs(stats[0]["iters"] - it_ref) <= 2
+        assert oracle.relres(A, b, x) <= 1.5e-10
+        assert np.abs(x - 1).max() < 1e-7
+
+
 def test_fp64_cg_random_rhs_irregular():
     say("case: cg irregular")
     A = stencil27_irregular(30, 28, 26, seed=0)
