@@ -220,6 +220,21 @@ def main():
         D.spmv(x32, y32)
     f_mean = time_batch(lambda: D.spmv(x32, y32), max(20, args.steps // 2), torch)
 
+    # block SpMV, 8 right-hand sides (row-interleaved), same matrix: DIT and ELL
+    X8 = torch.from_numpy(np.random.default_rng(5).uniform(-1.0, 1.0, (n, 8))).to(dev)
+    Y8 = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    for _ in range(5):
+        D.spmv_block(X8, Y8)
+        E.spmv_block(X8, Y8)
+    b_dit = time_batch(lambda: D.spmv_block(X8, Y8), max(20, args.steps // 4), torch)
+    b_ell = time_batch(lambda: E.spmv_block(X8, Y8), max(20, args.steps // 4), torch)
+    block8 = {"nrhs": 8, "dit_us": round(b_dit * 1000, 3), "dit_gflops": round(16.0 * nnz / (b_dit * 1e-3) / 1e9, 1),
+              "ell_us": round(b_ell * 1000, 3), "ell_gflops": round(16.0 * nnz / (b_ell * 1e-3) / 1e9, 1),
+              "dit_GBps": round((dinf["bytes_stream"] + 128 * n) / (b_dit * 1e-3) / 1e9, 1)}
+    log(f"[bench] block SpMV x8: DIT {block8['dit_us']} us ({block8['dit_gflops']} Gflops), "
+        f"ELL {block8['ell_us']} us ({block8['ell_gflops']} Gflops)")
+    del X8, Y8
+
     # cold-cache launches: the MALL flushed before each one
     flush = torch.empty(128 << 20, dtype=torch.float64, device=dev)
     c_dit = time_cold(lambda: D.spmv(x, y), 30, torch, flush)
@@ -275,6 +290,7 @@ def main():
         "parity_max_rel_err": out.get("parity_max_rel_err"),
         "tuned": tuned,
         "cold_mall": cold,
+        "block_spmv": block8,
         "dit_f32": {"launch_us_mean": round(f_mean * 1000, 3), "gflops": round(2.0 * nnz / (f_mean * 1e-3) / 1e9, 2)},
         "irregular": irregular,
         "cg": cg,

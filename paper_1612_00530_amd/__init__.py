@@ -136,6 +136,20 @@ def _dev(t, dtype, name):
     return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
 
 
+def _dev_rows(t, dtype, name):
+    """Device pointer of a row-major 2-D block whose rows may be padded (leading
+    dimension stride(0) >= number of columns, unit column stride)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1) or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name} must be a row-major block (unit column stride, leading dimension >= columns)")
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
 class Matrix:
     """A compressed matrix owned by libspmvc (released by ``free`` or garbage collection)."""
 
@@ -194,8 +208,10 @@ class Matrix:
         nrhs = X.shape[1]
         if Y is None:
             Y = torch.empty((self.n_rows, nrhs), dtype=X.dtype, device=X.device)
-        _check(load().spmv_block(self._h, dt, nrhs, _dev(X, X.dtype, "X"), X.stride(0),
-                                 _dev(Y, X.dtype, "Y"), Y.stride(0), _stream(stream)))
+        if Y.shape != (self.n_rows, nrhs):
+            raise ValueError("Y must be (n_rows, nrhs)")
+        _check(load().spmv_block(self._h, dt, nrhs, _dev_rows(X, X.dtype, "X"), max(X.stride(0), nrhs),
+                                 _dev_rows(Y, X.dtype, "Y"), max(Y.stride(0), nrhs), _stream(stream)))
         return Y
 
     def decompress(self):

@@ -650,6 +650,104 @@ __global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__
     emit_dot(a, dotc);
 }
 
+// ---- block SpMV: a group of LPR lanes per row -------------------------------------
+// Y = A X for nrhs row-interleaved right-hand sides.  A row is served by LPR
+// lanes, each taking VEC adjacent right-hand sides (VEC = 2: one 8- or
+// 16-byte load per gather), so the gathers of a row's lanes are one
+// contiguous run of X and every decoded entry serves all right-hand sides.
+// The lanes of a row read the same stream bytes (the loads coincide); rows
+// of a wavefront are consecutive, so those reads stay coalesced.
+template <class Real, int VEC> struct LaneVec;
+template <class Real> struct LaneVec<Real, 1> {
+    Real v[1];
+    __device__ __forceinline__ static LaneVec load(const Real *p) { return LaneVec{{*p}}; }
+};
+template <> struct LaneVec<double, 2> {
+    double v[2];
+    __device__ __forceinline__ static LaneVec load(const double *p) {
+        const double2 t = *reinterpret_cast<const double2 *>(p);
+        return LaneVec{{t.x, t.y}};
+    }
+};
+template <> struct LaneVec<float, 2> {
+    float v[2];
+    __device__ __forceinline__ static LaneVec load(const float *p) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        return LaneVec{{t.x, t.y}};
+    }
+};
+
+template <int FMT, class Real, class IdT, bool RAW, int LPR, int VEC>
+__global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, const Real *__restrict__ x,
+                                                        int64_t ldx, Real *__restrict__ y, int64_t ldy) {
+    if (a.skip && *a.skip) return;
+    if (blockIdx.x >= a.n_main_blocks) {
+        escape_row<Real, 16>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, nrhs, x,
+                             ldx, y, ldy);
+        return;
+    }
+    constexpr int RPB = kBlock / LPR;  // rows per block
+    const int64_t row = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * RPB + threadIdx.x / LPR;
+    if (row >= a.n_rows) return;
+    const int r = (threadIdx.x % LPR) * VEC;
+    const bool lane_on = r < nrhs;
+    const Real *xr = x + (lane_on ? r : 0);
+    Real acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = Real(0);
+    auto apply = [&](Real val, int64_t j) {
+        const LaneVec<Real, VEC> xv = LaneVec<Real, VEC>::load(xr + j * ldx);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = fma(val, xv.v[v], acc[v]);
+    };
+    if constexpr (FMT == SPMVC_FMT_ELL) {
+        if (a.cols[row] == kEscapeColumn) return;
+        for (int k = 0; k < a.width; ++k) {
+            const int64_t o = static_cast<int64_t>(k) * a.n_pad + row;
+            const int32_t c = a.cols[o];
+            if (c >= 0) apply(static_cast<Real>(a.ell_val[o]), c);
+        }
+    } else {
+        const int32_t *pat = nullptr;
+        int len = 0;
+        if constexpr (FMT == SPMVC_FMT_DIT) {
+            const IdT id = static_cast<const IdT *>(a.ids)[row];
+            if (id == esc_id<IdT>()) return;
+            pat = a.pat_off + static_cast<int64_t>(id) * a.width;
+            len = a.pat_len[id];
+        } else {
+            if (a.cols[row] == kEscapeColumn) return;
+            len = a.width;
+        }
+        auto column = [&](int k) -> int64_t {
+            if constexpr (FMT == SPMVC_FMT_DIT)
+                return row + pat[k];
+            else
+                return a.cols[static_cast<int64_t>(k) * a.n_pad + row];
+        };
+        int k = 0;
+        for (int c = 0; c < a.K; ++c) {
+            const int tend = a.T[static_cast<int64_t>(c) * a.n_pad + row];
+            const Real v = vtab<Real>(a, c);
+            for (; k < tend; ++k) apply(v, column(k));
+        }
+        if constexpr (RAW) {
+            const Real *raw = static_cast<const Real *>(a.raw);
+            const int64_t rb = a.raw_slice[row / kSlice] + (row % kSlice) - static_cast<int64_t>(k) * kSlice;
+            for (; k < len; ++k) {
+                const int64_t j = column(k);
+                if (FMT == SPMVC_FMT_DT && j < 0) break;
+                apply(raw[rb + static_cast<int64_t>(k) * kSlice], j);
+            }
+        }
+    }
+    if (lane_on) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            if (VEC == 1 || r + v < nrhs) y[row * ldy + r + v] = acc[v];
+    }
+}
+
 template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *skip, double *dot) {
     SpmvArgs a{};
     a.skip = skip;
@@ -880,10 +978,73 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
     return grid;
 }
 
+template <class Real, int LPR, int VEC>
+void launch_lanes_l(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const Real *xp, int64_t ldx, Real *yp,
+                    int64_t ldy, hipStream_t s) {
+    constexpr int RPB = kBlock / LPR;
+    a.n_main_blocks = static_cast<unsigned>((M->n_rows + RPB - 1) / RPB);
+    const unsigned grid = a.n_main_blocks + escape_blocks(M);
+    const bool raw = M->raw_elems > 0;
+#define SPMVC_LANES(FMT, IDT)                                                                                  \
+    if (raw)                                                                                                   \
+        k_spmv_lanes<FMT, Real, IDT, true, LPR, VEC><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);        \
+    else                                                                                                       \
+        k_spmv_lanes<FMT, Real, IDT, false, LPR, VEC><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+    if (M->fmt == SPMVC_FMT_ELL) {
+        k_spmv_lanes<SPMVC_FMT_ELL, Real, uint8_t, false, LPR, VEC><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+    } else if (M->fmt == SPMVC_FMT_DT) {
+        SPMVC_LANES(SPMVC_FMT_DT, uint8_t)
+    } else if (M->id_bytes == 1) {
+        SPMVC_LANES(SPMVC_FMT_DIT, uint8_t)
+    } else if (M->id_bytes == 2) {
+        SPMVC_LANES(SPMVC_FMT_DIT, uint16_t)
+    } else {
+        SPMVC_LANES(SPMVC_FMT_DIT, uint32_t)
+    }
+#undef SPMVC_LANES
+    SPMVC_CHECK_LAUNCH();
+}
+
+// Several right-hand sides: a lane group per row (LPR lanes of VEC right-hand
+// sides each; VEC = 2 when the blocks are 16-/8-byte aligned for pairs).
+template <class Real>
+void launch_lanes(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, int64_t ldx, void *Y,
+                  int64_t ldy, hipStream_t s) {
+    const Real *xp = static_cast<const Real *>(X);
+    Real *yp = static_cast<Real *>(Y);
+    const uintptr_t al = 2 * sizeof(Real);
+    const bool pairs = nrhs % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 && reinterpret_cast<uintptr_t>(X) % al == 0 &&
+                       reinterpret_cast<uintptr_t>(Y) % al == 0;
+    const int lanes = pairs ? nrhs / 2 : nrhs;
+    if (pairs) {
+        if (lanes <= 1)
+            launch_lanes_l<Real, 1, 2>(M, a, nrhs, xp, ldx, yp, ldy, s);
+        else if (lanes <= 2)
+            launch_lanes_l<Real, 2, 2>(M, a, nrhs, xp, ldx, yp, ldy, s);
+        else if (lanes <= 4)
+            launch_lanes_l<Real, 4, 2>(M, a, nrhs, xp, ldx, yp, ldy, s);
+        else
+            launch_lanes_l<Real, 8, 2>(M, a, nrhs, xp, ldx, yp, ldy, s);
+    } else {
+        if (lanes <= 2)
+            launch_lanes_l<Real, 2, 1>(M, a, nrhs, xp, ldx, yp, ldy, s);
+        else if (lanes <= 4)
+            launch_lanes_l<Real, 4, 1>(M, a, nrhs, xp, ldx, yp, ldy, s);
+        else if (lanes <= 8)
+            launch_lanes_l<Real, 8, 1>(M, a, nrhs, xp, ldx, yp, ldy, s);
+        else
+            launch_lanes_l<Real, 16, 1>(M, a, nrhs, xp, ldx, yp, ldy, s);
+    }
+}
+
 template <class Real>
 void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ldx, void *Y, int64_t ldy,
                     hipStream_t s, const int *skip, double *dot = nullptr) {
     SpmvArgs a = make_args<Real>(M, skip, dot);
+    if (nrhs > 1 && !dot) {
+        launch_lanes<Real>(M, a, nrhs, X, ldx, Y, ldy, s);
+        return;
+    }
     if (nrhs == 1)
         launch_direct_nr<Real, 1>(M, a, 1, X, ldx, Y, ldy, s);
     else if (nrhs <= 4)

@@ -173,6 +173,34 @@ def test_block_spmv(fmt, nrhs):
         assert max_rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14
 
 
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("nrhs,ld,off", [(8, 11, 0), (6, 8, 1), (2, 2, 0), (5, 5, 0), (4, 6, 0)])
+def test_block_spmv_strided_and_unaligned(fmt, nrhs, ld, off):
+    """Blocks with a leading dimension above nrhs (odd or even) and blocks that
+    start one element into their buffer (not 16-byte aligned): the pair-wise
+    lane loads are taken only when every row's pair is aligned, else single
+    loads; irregular values (raw FP64) for DIT and DT, stencil for ELL."""
+    say("case: block strided", fmt, nrhs, ld, off)
+    torch = torch_mod()
+    A = stencil27(21, 18, 15) if fmt == "ELL" else stencil27_irregular(20, 18, 15, seed=4)
+    X = np.stack([uniform_vector(A.n_cols, seed=30 + r) for r in range(nrhs)], axis=1)
+    M = compress(A, fmt=fmt)
+    xb = torch.zeros(A.n_cols * ld + off, dtype=torch.float64, device="cuda")
+    xv = xb[off:].view(A.n_cols, ld)[:, :nrhs]
+    xv.copy_(torch.from_numpy(X).cuda())
+    yb = torch.full((A.n_rows * ld + off,), 7.0, dtype=torch.float64, device="cuda")
+    yv = yb[off:].view(A.n_rows, ld)[:, :nrhs]
+    M.spmv_block(xv, yv)
+    torch.cuda.synchronize()
+    Y = yv.cpu().numpy()
+    Yref = oracle.spmv_block(A, X)
+    for r in range(nrhs):
+        assert max_rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14
+    # columns past nrhs are untouched
+    if ld > nrhs:
+        assert np.all(yb[off:].view(A.n_rows, ld)[:, nrhs:].cpu().numpy() == 7.0)
+
+
 # ---- encoded arrays equal the reference codec's -----------------------------------------
 
 def _np(t, dtype):
