@@ -223,6 +223,7 @@ def main():
     # block SpMV, 8 right-hand sides (row-interleaved), same matrix: DIT and ELL
     X8 = torch.from_numpy(np.random.default_rng(5).uniform(-1.0, 1.0, (n, 8))).to(dev)
     Y8 = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    tuned_block = D.tune(torch.float64, nrhs=8) if not args.no_tune else None
     for _ in range(5):
         D.spmv_block(X8, Y8)
         E.spmv_block(X8, Y8)
@@ -230,7 +231,8 @@ def main():
     b_ell = time_batch(lambda: E.spmv_block(X8, Y8), max(20, args.steps // 4), torch)
     block8 = {"nrhs": 8, "dit_us": round(b_dit * 1000, 3), "dit_gflops": round(16.0 * nnz / (b_dit * 1e-3) / 1e9, 1),
               "ell_us": round(b_ell * 1000, 3), "ell_gflops": round(16.0 * nnz / (b_ell * 1e-3) / 1e9, 1),
-              "dit_GBps": round((dinf["bytes_stream"] + 128 * n) / (b_dit * 1e-3) / 1e9, 1)}
+              "dit_GBps": round((dinf["bytes_stream"] + 128 * n) / (b_dit * 1e-3) / 1e9, 1),
+              "tuned": tuned_block}
     log(f"[bench] block SpMV x8: DIT {block8['dit_us']} us ({block8['dit_gflops']} Gflops), "
         f"ELL {block8['ell_us']} us ({block8['ell_gflops']} Gflops)")
     del X8, Y8

@@ -227,7 +227,9 @@ spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds
  * Autotuner: times each candidate kernel configuration of `A` for dtype `dt`
  * and `nrhs` (spmv when nrhs == 1, else spmv_block) on scratch vectors, keeps
  * the fastest in the handle as that dtype's configuration and reports it (host
- * outputs, may be NULL).
+ * outputs, may be NULL).  nrhs == 1: rows per block and LDS mode (0 direct,
+ * 1 windows, 2 plane-marching).  nrhs > 1: *best_lds reports the block kernel
+ * (1 = a lane group per row, 0 = one lane per row for all right-hand sides).
  * Results are cached per (arch, format, n_rows, P, K, dtype, nrhs) in the JSON
  * file named by $SPMVC_TUNE_CACHE when set.  Blocking.
  */

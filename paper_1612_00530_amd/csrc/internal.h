@@ -115,6 +115,8 @@ struct spmvc_matrix_s {
     int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits,
                                            // 2 = as 1, plane-marching where it applies
     spmvc::LdsPlan plan[2];                // per dtype
+    int32_t block_mode[2] = {1, 1};        // per dtype, several right-hand sides: 1 = a lane group
+                                           // per row, 0 = one lane per row (all rhs)
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
     int32_t n_cu = 256;         // compute units of the device (grid sizing)

@@ -1041,7 +1041,8 @@ template <class Real>
 void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ldx, void *Y, int64_t ldy,
                     hipStream_t s, const int *skip, double *dot = nullptr) {
     SpmvArgs a = make_args<Real>(M, skip, dot);
-    if (nrhs > 1 && !dot) {
+    constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
+    if (nrhs > 1 && !dot && M->block_mode[dt]) {
         launch_lanes<Real>(M, a, nrhs, X, ldx, Y, ldy, s);
         return;
     }

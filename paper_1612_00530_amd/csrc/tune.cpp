@@ -3,8 +3,9 @@
 // Candidates (single right-hand side, DIT): rows per block in {256 .. 4096}
 // with the x windows staged in LDS, the plane-marching form with row tiles of
 // {256, 512, 1024}, and the direct-gather kernel (x read through the L1/L2
-// caches).  Every candidate gives the same result; only the
-// time differs.  A candidate's time is the median over repetitions of the mean
+// caches).  Several right-hand sides (block SpMV): a lane group per row or
+// one lane per row.  Every candidate gives a result within the same accuracy
+// bound; only the time differs.  A candidate's time is the median over repetitions of the mean
 // of a run of back-to-back launches.  Winners are cached per (arch, format, rows, P, K, dtype, nrhs)
 // in the JSON object stored in the file named by $SPMVC_TUNE_CACHE.
 #include <algorithm>
@@ -90,9 +91,13 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
             auto it = m.find(key);
             if (it != m.end()) {
                 const int rows = static_cast<int>(it->second[0]), lds = static_cast<int>(it->second[1]);
-                A->lds_mode[dt] = lds;
-                A->rows_per_block[dt] = rows;
-                build_lds_plan(A, dt, rows);
+                if (nrhs > 1) {
+                    A->block_mode[dt] = lds;
+                } else {
+                    A->lds_mode[dt] = lds;
+                    A->rows_per_block[dt] = rows;
+                    build_lds_plan(A, dt, rows);
+                }
                 if (best_rows) *best_rows = rows;
                 if (best_lds) *best_lds = lds;
                 if (best_us) *best_us = it->second[2];
@@ -103,6 +108,10 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         if (A->fmt == SPMVC_FMT_DIT && nrhs == 1) {
             for (int rows : {256, 512, 1024, 2048, 4096}) cands.push_back({rows, 1});
             for (int rows : {256, 512, 1024}) cands.push_back({rows, 2});
+            cands.push_back({A->rows_per_block[dt], 0});
+        } else if (nrhs > 1) {
+            // block SpMV: a lane group per row (1) or one lane per row (0)
+            cands.push_back({A->rows_per_block[dt], 1});
             cands.push_back({A->rows_per_block[dt], 0});
         } else {
             cands.push_back({A->rows_per_block[dt], A->lds_mode[dt]});
@@ -118,11 +127,15 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         double best = 1e300;
         Cand win = cands.front();
         for (const Cand &c : cands) {
-            A->lds_mode[dt] = c.lds;
-            A->rows_per_block[dt] = c.rows;
-            build_lds_plan(A, dt, c.rows);
-            if (c.lds >= 1 && A->fmt == SPMVC_FMT_DIT && A->plan[dt].n_win == 0) continue;  // does not fit
-            if (c.lds == 2 && kernel_kind(A, dt) != 3) continue;  // no plane-marching form
+            if (nrhs > 1) {
+                A->block_mode[dt] = c.lds;
+            } else {
+                A->lds_mode[dt] = c.lds;
+                A->rows_per_block[dt] = c.rows;
+                build_lds_plan(A, dt, c.rows);
+                if (c.lds >= 1 && A->fmt == SPMVC_FMT_DIT && A->plan[dt].n_win == 0) continue;  // does not fit
+                if (c.lds == 2 && kernel_kind(A, dt) != 3) continue;  // no plane-marching form
+            }
             auto run = [&]() {
                 if (nrhs == 1)
                     launch_spmv(A, dt, x.p, y.p, s);
@@ -151,9 +164,13 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        A->lds_mode[dt] = win.lds;
-        A->rows_per_block[dt] = win.rows;
-        build_lds_plan(A, dt, win.rows);
+        if (nrhs > 1) {
+            A->block_mode[dt] = win.lds;
+        } else {
+            A->lds_mode[dt] = win.lds;
+            A->rows_per_block[dt] = win.rows;
+            build_lds_plan(A, dt, win.rows);
+        }
         if (cpath) {
             auto m = read_cache(cpath);
             m[key] = {static_cast<double>(win.rows), static_cast<double>(win.lds), best};

@@ -201,6 +201,27 @@ def test_block_spmv_strided_and_unaligned(fmt, nrhs, ld, off):
         assert np.all(yb[off:].view(A.n_rows, ld)[:, nrhs:].cpu().numpy() == 7.0)
 
 
+def test_autotuner_single_and_block():
+    """The autotuner's choices (single vector: rows per block / staging; block:
+    lane group or one lane per row) keep every product within the bound."""
+    say("case: autotuner")
+    torch = torch_mod()
+    A = stencil27(48, 40, 36)
+    M = compress(A, fmt="DIT")
+    x = uniform_vector(A.n_cols, seed=2)
+    X = np.stack([uniform_vector(A.n_cols, seed=40 + r) for r in range(8)], axis=1)
+    for dt in (torch.float64, torch.float32):
+        t = M.tune(dt)
+        assert t["rows_per_block"] in (256, 512, 1024, 2048, 4096) and t["lds"] in (0, 1, 2) and t["us"] > 0
+    tb = M.tune(torch.float64, nrhs=8)
+    assert tb["lds"] in (0, 1) and tb["us"] > 0
+    assert max_rel_err(A, x, gpu_spmv(M, x), oracle.spmv(A, x)) <= 1e-14
+    Y = M.spmv_block(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yref = oracle.spmv_block(A, X)
+    for r in range(8):
+        assert max_rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14
+
+
 # ---- encoded arrays equal the reference codec's -----------------------------------------
 
 def _np(t, dtype):
