@@ -224,12 +224,24 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
 spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds);
 
 /*
+ * Kernel of spmv_block (both dtypes): 2 = x windows of FP64 right-hand-side
+ * pairs in LDS where that applies (DIT, value table of 1 or 2 entries, even
+ * nrhs and leading dimensions, 16-byte aligned blocks), else as 1; 1 = a group
+ * of lanes per row (the default); 0 = one lane per row for all right-hand
+ * sides.  Used by the autotuner; results agree within the accuracy bound.
+ * SPMVC_EINVAL for other values or a null handle.
+ */
+spmvc_status spmv_set_block_mode(spmvc_matrix A, int32_t mode);
+
+/*
  * Autotuner: times each candidate kernel configuration of `A` for dtype `dt`
  * and `nrhs` (spmv when nrhs == 1, else spmv_block) on scratch vectors, keeps
  * the fastest in the handle as that dtype's configuration and reports it (host
  * outputs, may be NULL).  nrhs == 1: rows per block and LDS mode (0 direct,
  * 1 windows, 2 plane-marching).  nrhs > 1: *best_lds reports the block kernel
- * (1 = a lane group per row, 0 = one lane per row for all right-hand sides).
+ * (2 = x windows of FP64 right-hand-side pairs in LDS where that applies, else
+ * as 1; 1 = a lane group per row; 0 = one lane per row for all right-hand
+ * sides).
  * Results are cached per (arch, format, n_rows, P, K, dtype, nrhs) in the JSON
  * file named by $SPMVC_TUNE_CACHE when set.  Blocking.
  */

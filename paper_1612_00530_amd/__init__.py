@@ -31,8 +31,8 @@ ARR = {
 
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
-    "spmv_get_array", "spmv_set_config", "spmv_tune", "spmv_free", "spmvc_status_string",
-    "spmvc_last_error",
+    "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_free",
+    "spmvc_status_string", "spmvc_last_error",
 ]
 
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
     lib.spmv_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.spmv_get_array.argtypes = [P, i32, P, ctypes.POINTER(i64), P]
     lib.spmv_set_config.argtypes = [P, i32, i32]
+    lib.spmv_set_block_mode.argtypes = [P, i32]
     lib.spmv_tune.argtypes = [P, i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                               ctypes.POINTER(ctypes.c_double)]
     lib.spmv_free.argtypes = [P]
@@ -104,7 +105,7 @@ def load(path: str = LIB_PATH):
     lib.spmvc_status_string.restype = ctypes.c_char_p
     lib.spmvc_last_error.restype = ctypes.c_char_p
     for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
-                 "spmv_get_array", "spmv_set_config", "spmv_tune"]:
+                 "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune"]:
         getattr(lib, name).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -239,6 +240,9 @@ class Matrix:
 
     def set_config(self, rows_per_block=0, lds=-1):
         _check(load().spmv_set_config(self._h, rows_per_block, lds))
+
+    def set_block_mode(self, mode):
+        _check(load().spmv_set_block_mode(self._h, mode))
 
     def tune(self, dtype=None, nrhs=1):
         import torch

@@ -78,6 +78,8 @@ struct LdsPlan {
     int32_t zero_base = 0;        // element offset of the zero window (after the x windows)
     bool reg_tab_in_lds = false;
     DevBuf reg_tab64, reg_tab32;  // byte offsets for FP64 and FP32 elements
+    bool reg128 = false;          // the windows also fit as 16-byte elements (block SpMV,
+    DevBuf reg_tab128;            //   pairs of FP64 right-hand sides): offsets for those
     bool v_finite = false;        // every value-table entry finite (v * 0 == 0)
     bool v_same_lo = false;       // value-table entries share their low 32 bits
     // plane-marching form of the register kernel: windows equally spaced by
@@ -115,8 +117,9 @@ struct spmvc_matrix_s {
     int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits,
                                            // 2 = as 1, plane-marching where it applies
     spmvc::LdsPlan plan[2];                // per dtype
-    int32_t block_mode[2] = {1, 1};        // per dtype, several right-hand sides: 1 = a lane group
-                                           // per row, 0 = one lane per row (all rhs)
+    int32_t block_mode[2] = {1, 1};        // per dtype, several right-hand sides: 2 = x windows of
+                                           // right-hand-side pairs in LDS where that applies, else 1;
+                                           // 1 = a lane group per row; 0 = one lane per row (all rhs)
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
     int32_t n_cu = 256;         // compute units of the device (grid sizing)

@@ -748,6 +748,116 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, con
     }
 }
 
+// ---- block SpMV, right-hand sides in pairs, x windows in LDS ------------------------
+// The register kernel with 16-byte elements: a block owns a row tile and one
+// pair (2p, 2p + 1) of FP64 right-hand sides; its x windows hold that pair of
+// every row (16 bytes), copied with direct loads from the row-interleaved
+// block (one row per lane, rows ldx apart).  Every entry is then one 16-byte
+// LDS read and two adds.  Values from a table of K = 1 or 2 entries.
+struct D2 {
+    double x, y;
+};
+__device__ __forceinline__ D2 operator+(D2 a, D2 b) { return D2{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ D2 &operator+=(D2 &a, D2 b) {
+    a.x += b.x;
+    a.y += b.y;
+    return a;
+}
+__device__ __forceinline__ D2 operator*(double v, D2 a) { return D2{v * a.x, v * a.y}; }
+__device__ __forceinline__ D2 fma(double v, D2 a, D2 c) { return D2{::fma(v, a.x, c.x), ::fma(v, a.y, c.y)}; }
+
+template <int KK, int RPT, int MAXW>
+__global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const double *__restrict__ X, int64_t ldx,
+                                                           double *__restrict__ Y, int64_t ldy) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t pr = blockIdx.y;  // right-hand-side pair
+    const double *xp = X + 2 * pr;
+    D2 *xs = reinterpret_cast<D2 *>(smem);
+    const int64_t r0 = xcd_tile(blockIdx.x, gridDim.x, a.n_xcd) * (kBlock * RPT);
+    const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+    uint32_t idv[RPT];
+    int t0v[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int64_t row = r0 + threadIdx.x + j * kBlock;
+        const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
+        idv[j] = load_id(a.ids, a.id_bytes, rc);
+        t0v[j] = static_cast<int>(a.T[rc]);
+    }
+    // windows: element e of window w is the pair of row r0 + lo[w] + e
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < a.n_win; ++w) {
+        const int64_t g0 = r0 + a.win_lo[w];
+        const int n = a.win_len[w];
+        D2 *dst = xs + a.win_base[w];
+        if (a.async_lds && g0 >= 0 && g0 + n <= a.n_cols) {
+            for (int c = wave; c * 64 < n; c += kBlock / 64) {
+                const int e = c * 64 + lane;
+                if (e < n) lds_load16(xp + (g0 + e) * ldx, dst + c * 64);
+            }
+        } else {
+            const int64_t last = a.n_cols - 1;
+            for (int e = threadIdx.x; e < n; e += kBlock) {
+                int64_t g = g0 + e;
+                g = g < 0 ? 0 : (g > last ? last : g);
+                dst[e] = D2{xp[g * ldx], xp[g * ldx + 1]};
+            }
+        }
+    }
+    for (int e = threadIdx.x; e < a.zero_len; e += kBlock) xs[a.zero_base + e] = D2{0.0, 0.0};
+    uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
+    const int n16 = a.P * (kRegTw * 2 / 16);
+    for (int e = threadIdx.x; e < n16; e += kBlock) tab_s[e] = reinterpret_cast<const uint4 *>(a.reg_tab)[e];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const double v0 = a.V[0], v1 = a.V[KK >= 2 ? 1 : 0];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rel = threadIdx.x + j * kBlock;
+        const int64_t row = r0 + rel;
+        const bool active = row < a.n_rows && idv[j] != esc;
+        const uint4 *tp = tab_s + static_cast<int64_t>(active ? idv[j] : 0u) * (kRegTw * 2 / 16);
+        uint32_t wv[16];
+#pragma unroll
+        for (int q = 0; q < (MAXW + 8) / 8; ++q) {
+            const uint4 u = tp[q];
+            wv[4 * q + 0] = u.x;
+            wv[4 * q + 1] = u.y;
+            wv[4 * q + 2] = u.z;
+            wv[4 * q + 3] = u.w;
+        }
+        const int len = static_cast<int>(wv[0] & 0xFFFFu);
+        const int m = KK == 2 ? len - t0v[j] : 0;
+        int ms = 0;
+        bool uni = true;
+        if constexpr (KK == 2) {
+            const uint64_t act = __ballot(active);
+            if (act == 0) continue;
+            ms = __builtin_amdgcn_readlane(m, static_cast<int>(__builtin_ctzll(act)));
+            uni = __ballot(active && m != ms) == 0;
+        }
+        if (!active) continue;
+        const uint32_t relb = static_cast<uint32_t>(rel) * 16u;
+        auto xat = [&](int k) -> D2 {
+            const uint32_t word = wv[(k + 1) >> 1];
+            const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
+            const double2 t = *reinterpret_cast<const double2 *>(smem + relb + off);
+            return D2{t.x, t.y};
+        };
+        D2 acc{0.0, 0.0};
+        if (KK == 1 || (uni && ms == 0)) {
+            acc = v0 * sum_entries<0, MAXW>(xat);
+        } else if (uni && ms == 1) {
+            acc = fma(v0, sum_entries<1, MAXW>(xat), v1 * xat(0));
+        } else {
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) acc = fma(k < m ? v1 : v0, xat(k), acc);
+        }
+        double *yr = Y + row * ldy + 2 * pr;
+        *reinterpret_cast<double2 *>(yr) = double2{acc.x, acc.y};
+    }
+}
+
 template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *skip, double *dot) {
     SpmvArgs a{};
     a.skip = skip;
@@ -978,6 +1088,66 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
     return grid;
 }
 
+// Block SpMV of FP64 right-hand-side pairs with LDS windows (k_dit_reg_pairs);
+// false when it does not apply (format, value table, alignment, LDS size).
+bool launch_pairs(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                  hipStream_t s) {
+    const LdsPlan &p = M->plan[SPMVC_F64];
+    if (M->fmt != SPMVC_FMT_DIT || !p.reg128 || p.n_win == 0 || M->P == 0 || M->lds_mode[SPMVC_F64] == 0) return false;
+    if (!(M->K == 1 || M->K == 2) || M->raw_elems > 0 || !p.v_finite) return false;
+    if (nrhs % 2 || ldx % 2 || ldy % 2 || reinterpret_cast<uintptr_t>(X) % 16 || reinterpret_cast<uintptr_t>(Y) % 16)
+        return false;
+    const int rpt = p.rows / kBlock;
+    if (rpt > 4) return false;
+    a.rows = p.rows;
+    a.n_win = p.n_win;
+    for (int w = 0; w < p.n_win; ++w) {
+        a.win_lo[w] = p.lo[w];
+        a.win_len[w] = p.len[w];
+        a.win_base[w] = p.base[w];
+    }
+    a.async_lds = 1;
+    a.zero_base = p.zero_base;
+    a.zero_len = p.rows;
+    a.reg_tab = p.reg_tab128.as<uint16_t>();
+    a.lds_x_bytes = 16 * (p.zero_base + p.rows);
+    const size_t shmem = a.lds_x_bytes + static_cast<size_t>(M->P) * kRegTw * 2;
+    const unsigned tiles = static_cast<unsigned>((M->n_rows + p.rows - 1) / p.rows);
+    const dim3 grid(tiles, static_cast<unsigned>(nrhs / 2));
+    const double *xp = static_cast<const double *>(X);
+    double *yp = static_cast<double *>(Y);
+    const bool w27 = M->width <= 27;
+#define SPMVC_PAIRS_W(KK, R)                                                                         \
+    if (w27)                                                                                         \
+        k_dit_reg_pairs<KK, R, 27><<<grid, kBlock, shmem, s>>>(a, xp, ldx, yp, ldy);                 \
+    else                                                                                             \
+        k_dit_reg_pairs<KK, R, kRegW><<<grid, kBlock, shmem, s>>>(a, xp, ldx, yp, ldy);
+#define SPMVC_PAIRS_R(KK)        \
+    if (rpt == 1) {              \
+        SPMVC_PAIRS_W(KK, 1)     \
+    } else if (rpt == 2) {       \
+        SPMVC_PAIRS_W(KK, 2)     \
+    } else {                     \
+        SPMVC_PAIRS_W(KK, 4)     \
+    }
+    if (M->K == 1) {
+        SPMVC_PAIRS_R(1)
+    } else {
+        SPMVC_PAIRS_R(2)
+    }
+#undef SPMVC_PAIRS_R
+#undef SPMVC_PAIRS_W
+    SPMVC_CHECK_LAUNCH();
+    // escape rows: one lane per row, all right-hand sides
+    const unsigned eb = escape_blocks(M);
+    if (eb) {
+        a.n_main_blocks = 0;
+        k_spmv_lanes<SPMVC_FMT_DIT, double, uint8_t, false, 1, 1><<<eb, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+        SPMVC_CHECK_LAUNCH();
+    }
+    return true;
+}
+
 template <class Real, int LPR, int VEC>
 void launch_lanes_l(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const Real *xp, int64_t ldx, Real *yp,
                     int64_t ldy, hipStream_t s) {
@@ -1042,6 +1212,9 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
                     hipStream_t s, const int *skip, double *dot = nullptr) {
     SpmvArgs a = make_args<Real>(M, skip, dot);
     constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
+    if constexpr (dt == SPMVC_F64) {
+        if (nrhs > 1 && !dot && M->block_mode[dt] == 2 && launch_pairs(M, a, nrhs, X, ldx, Y, ldy, s)) return;
+    }
     if (nrhs > 1 && !dot && M->block_mode[dt]) {
         launch_lanes<Real>(M, a, nrhs, X, ldx, Y, ldy, s);
         return;
@@ -1155,6 +1328,8 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     p.tab_in_lds = false;
     p.reg = false;
     p.reg_tab_in_lds = false;
+    p.reg128 = false;
+    p.reg_tab128.release();
     p.march = false;
     p.m_tab64.release();
     p.m_tab32.release();
@@ -1247,6 +1422,23 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         }
         p.reg_tab_in_lds = reg_tab_bytes <= 16 * 1024 && x_bytes64 + reg_tab_bytes <= kLdsBudgetBytes;
         p.reg = true;
+        // the same windows as 16-byte elements (pairs of FP64 right-hand sides)
+        const int64_t x_bytes128 = x_elems * 16;
+        if (x_bytes128 + reg_tab_bytes <= kLdsBudgetBytes && x_elems * 16 <= 65535 && M->K >= 1) {
+            std::vector<uint16_t> rt(static_cast<size_t>(M->P) * kRegTw, 0);
+            for (int q = 0; q < M->P; ++q) {
+                const int L = M->h_pat_len[q];
+                uint16_t *r = rt.data() + static_cast<size_t>(q) * kRegTw;
+                r[0] = static_cast<uint16_t>(L);
+                for (int k = 0; k < kRegW; ++k) {
+                    const int64_t e = k < L ? lds_index(M->h_pat_off[static_cast<size_t>(q) * W + (L - 1 - k)]) : total;
+                    r[1 + k] = static_cast<uint16_t>(e * 16);
+                }
+            }
+            p.reg_tab128.alloc(sizeof(uint16_t) * rt.size());
+            SPMVC_HIP(hipMemcpy(p.reg_tab128.p, rt.data(), p.reg_tab128.bytes, hipMemcpyHostToDevice));
+            p.reg128 = true;
+        }
     }
     build_march_plan(M, p, win, lo, len, rows);
 }

@@ -61,6 +61,10 @@ def test_null_arguments_rejected_on_host():
     assert lib.spmv_compress(-1, 4, 0, None, None, None, None, None, ctypes.byref(out)) == -1
     lib.spmvc_last_error.restype = ctypes.c_char_p
     assert b"negative" in lib.spmvc_last_error()
+    lib.spmv_set_block_mode.argtypes = [P, ctypes.c_int32]
+    assert lib.spmv_set_block_mode(None, 1) == -1
+    lib.spmv_set_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    assert lib.spmv_set_config(None, 512, 1) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
