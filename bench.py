@@ -209,9 +209,20 @@ def main():
             oracle.spmv(A, xh)
             reps += 1
         t_cpu = (time.perf_counter() - t0) / reps
-        out["cpu_baseline"] = {"value": 2.0 * nnz / t_cpu / 1e9, "unit": "Gflops", "cores": oracle.threads(),
+        # and on one thread (a few repetitions)
+        nthr = oracle.threads()
+        oracle.set_threads(1)
+        reps1, t1 = 0, time.perf_counter()
+        while reps1 < 2 or (time.perf_counter() - t1) < min(3.0, args.cpu_seconds):
+            oracle.spmv(A, xh)
+            reps1 += 1
+        t_cpu1 = (time.perf_counter() - t1) / reps1
+        oracle.set_threads(nthr)
+        out["cpu_baseline"] = {"value": 2.0 * nnz / t_cpu / 1e9, "unit": "Gflops", "cores": nthr,
                                "kind": "oracle",
-                               "sample": f"{reps} full CSR SpMVs of the {g}^3 stencil matrix (FP64, OpenMP rows)"}
+                               "sample": f"{reps} full CSR SpMVs of the {g}^3 stencil matrix (FP64, OpenMP rows)",
+                               "value_1thread": round(2.0 * nnz / t_cpu1 / 1e9, 3),
+                               "sample_1thread": f"{reps1} full CSR SpMVs on one thread"}
         log(f"[bench] CPU oracle: {out['cpu_baseline']['value']:.2f} Gflops on {oracle.threads()} threads")
 
     # FP32 DIT SpMV of the same matrix (the inner kernel of the mixed-precision CG)

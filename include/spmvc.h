@@ -224,11 +224,16 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
 spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds);
 
 /*
- * Kernel of spmv_block (both dtypes): 2 = x windows of FP64 right-hand-side
- * pairs in LDS where that applies (DIT, value table of 1 or 2 entries, even
- * nrhs and leading dimensions, 16-byte aligned blocks), else as 1; 1 = a group
- * of lanes per row (the default); 0 = one lane per row for all right-hand
- * sides.  Used by the autotuner; results agree within the accuracy bound.
+ * Kernel of spmv_block (both dtypes).  Modes 3 and 2 apply to FP64 DIT
+ * matrices with a value table of 1 or 2 entries (no raw values) and fall back
+ * to mode 1 otherwise:
+ *   3 = whole rows of the block in LDS, one x window at a time (nrhs 2, 4 or
+ *       8, unpadded blocks: ldx == ldy == nrhs; 16-byte aligned; the default);
+ *   2 = x windows of right-hand-side pairs in LDS (even nrhs and leading
+ *       dimensions, 16-byte aligned blocks);
+ *   1 = a group of lanes per row;
+ *   0 = one lane per row for all right-hand sides.
+ * Used by the autotuner; results agree within the accuracy bound.
  * SPMVC_EINVAL for other values or a null handle.
  */
 spmvc_status spmv_set_block_mode(spmvc_matrix A, int32_t mode);
@@ -239,9 +244,7 @@ spmvc_status spmv_set_block_mode(spmvc_matrix A, int32_t mode);
  * the fastest in the handle as that dtype's configuration and reports it (host
  * outputs, may be NULL).  nrhs == 1: rows per block and LDS mode (0 direct,
  * 1 windows, 2 plane-marching).  nrhs > 1: *best_lds reports the block kernel
- * (2 = x windows of FP64 right-hand-side pairs in LDS where that applies, else
- * as 1; 1 = a lane group per row; 0 = one lane per row for all right-hand
- * sides).
+ * (the mode of spmv_set_block_mode).
  * Results are cached per (arch, format, n_rows, P, K, dtype, nrhs) in the JSON
  * file named by $SPMVC_TUNE_CACHE when set.  Blocking.
  */

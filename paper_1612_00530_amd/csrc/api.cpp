@@ -278,7 +278,7 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
 spmvc_status spmv_set_block_mode(spmvc_matrix A, int32_t mode) {
     return guarded([&]() -> spmvc_status {
         if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
-        if (mode < 0 || mode > 2) return fail(SPMVC_EINVAL, "block mode must be 0, 1 or 2");
+        if (mode < 0 || mode > 3) return fail(SPMVC_EINVAL, "block mode must be 0, 1, 2 or 3");
         A->block_mode[SPMVC_F64] = mode;
         A->block_mode[SPMVC_F32] = mode;
         return SPMVC_OK;

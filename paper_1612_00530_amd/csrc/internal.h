@@ -80,6 +80,14 @@ struct LdsPlan {
     DevBuf reg_tab64, reg_tab32;  // byte offsets for FP64 and FP32 elements
     bool reg128 = false;          // the windows also fit as 16-byte elements (block SpMV,
     DevBuf reg_tab128;            //   pairs of FP64 right-hand sides): offsets for those
+    // window-phased block SpMV (whole right-hand-side rows in LDS, one window
+    // at a time, row tiles of kWinRows): windows, and per pattern and window
+    // the count and the entries ((canonical index << 16) | element in window)
+    bool bw = false;
+    int32_t bw_nw = 0, bw_maxlen = 0;
+    int64_t bw_lo[kMaxWindows] = {};
+    int32_t bw_len[kMaxWindows] = {};
+    DevBuf bw_tab;
     bool v_finite = false;        // every value-table entry finite (v * 0 == 0)
     bool v_same_lo = false;       // value-table entries share their low 32 bits
     // plane-marching form of the register kernel: windows equally spaced by
@@ -93,6 +101,8 @@ struct LdsPlan {
 };
 
 constexpr int kRegW = 31;   // longest pattern the register kernel takes
+constexpr int kWinRows = 256;   // row tile of the window-phased block SpMV
+constexpr int kWinMaxPw = 12;   // most entries of one pattern in one window (window-phased)
 constexpr int kRegTw = 32;  // uint16 per register-table row (64 bytes, 16-byte aligned)
 
 }  // namespace spmvc
@@ -117,9 +127,11 @@ struct spmvc_matrix_s {
     int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits,
                                            // 2 = as 1, plane-marching where it applies
     spmvc::LdsPlan plan[2];                // per dtype
-    int32_t block_mode[2] = {1, 1};        // per dtype, several right-hand sides: 2 = x windows of
-                                           // right-hand-side pairs in LDS where that applies, else 1;
-                                           // 1 = a lane group per row; 0 = one lane per row (all rhs)
+    int32_t block_mode[2] = {3, 3};        // per dtype, several right-hand sides: 3 = whole rows
+                                           // of the block in LDS one window at a time, 2 = x windows
+                                           // of right-hand-side pairs in LDS (3 and 2 where they
+                                           // apply, else 1); 1 = a lane group per row; 0 = one lane
+                                           // per row (all rhs)
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
     int32_t n_cu = 256;         // compute units of the device (grid sizing)

@@ -858,6 +858,107 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
     }
 }
 
+// ---- block SpMV, whole right-hand-side rows in LDS, one window at a time ----------
+// nrhs = 2 * LPR FP64 right-hand sides, row-interleaved and unpadded.  A block
+// owns kWinRows rows; for each x window in turn it copies the window's rows
+// of the block (all nrhs values of a row: 16 * LPR bytes, a contiguous range
+// of memory) into LDS, then every row adds the products of its entries that
+// fall in that window.  Only one window is held at a time, so whole rows fit.
+// A group of LPR lanes serves a row, each lane a pair of right-hand sides
+// (16-byte LDS reads); per pair two sums are kept, one per value-table entry,
+// and scaled once at the end.
+template <int LPR>
+__global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const double *__restrict__ X,
+                                                           double *__restrict__ Y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NR = 2 * LPR;          // right-hand sides
+    constexpr int PASSES = kWinRows / (kBlock / LPR);
+    constexpr int ST = kWinMaxPw + 1;    // table words per (pattern, window)
+    const int NW = a.n_win;
+    double *xs = reinterpret_cast<double *>(smem);
+    uint32_t *tab_s = reinterpret_cast<uint32_t *>(smem + a.lds_x_bytes);
+    const int64_t r0 = xcd_tile(blockIdx.x, gridDim.x, a.n_xcd) * kWinRows;
+    const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+    const int lr = threadIdx.x / LPR;           // row within a pass
+    const int rp = (threadIdx.x % LPR) * 2;     // this lane's right-hand-side pair
+    uint32_t idv[PASSES];
+    int t0v[PASSES];
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+        const int64_t row = r0 + ps * (kBlock / LPR) + lr;
+        const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
+        idv[ps] = load_id(a.ids, a.id_bytes, rc);
+        t0v[ps] = a.K >= 2 ? static_cast<int>(a.T[rc]) : 255;
+    }
+    {
+        const int nt = a.P * NW * ST;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.reg_tab);
+        for (int e = threadIdx.x; e < nt; e += kBlock) tab_s[e] = src[e];
+    }
+    double s0[PASSES][2], s1[PASSES][2];
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            s0[ps][v] = 0.0;
+            s1[ps][v] = 0.0;
+        }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < NW; ++w) {
+        if (w > 0) __syncthreads();  // every row is done with the previous window
+        const int64_t g0 = r0 + a.win_lo[w];
+        const int n = a.win_len[w];
+        if (a.async_lds && g0 >= 0 && g0 + n <= a.n_cols) {
+            // rows g0 .. g0 + n: n * NR doubles, contiguous; 16 bytes per lane
+            const double *src = X + g0 * NR;
+            const int nchunk = n * NR / 2;
+            for (int c = wave * 64; c < nchunk; c += kBlock) {
+                const int e = c + lane;
+                if (e < nchunk) lds_load16(src + 2 * e, xs + 2 * c);
+            }
+        } else {
+            const int64_t last = a.n_cols - 1;
+            for (int e = threadIdx.x; e < n * NR; e += kBlock) {
+                int64_t g = g0 + e / NR;
+                g = g < 0 ? 0 : (g > last ? last : g);
+                xs[e] = X[g * NR + e % NR];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int rel = ps * (kBlock / LPR) + lr;
+            const int64_t row = r0 + rel;
+            if (row >= a.n_rows || idv[ps] == esc) continue;
+            const uint32_t *t = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * ST;
+            const int cnt = static_cast<int>(t[0]);
+            for (int k = 0; k < cnt; ++k) {
+                const uint32_t ent = t[1 + k];
+                const int off = static_cast<int>(ent & 0xFFFFu);
+                const int kc = static_cast<int>(ent >> 16);
+                const double2 xv = *reinterpret_cast<const double2 *>(xs + (rel + off) * NR + rp);
+                if (kc < t0v[ps]) {
+                    s0[ps][0] += xv.x;
+                    s0[ps][1] += xv.y;
+                } else {
+                    s1[ps][0] += xv.x;
+                    s1[ps][1] += xv.y;
+                }
+            }
+        }
+    }
+    const double v0 = a.V[0], v1 = a.V[a.K >= 2 ? 1 : 0];
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+        const int64_t row = r0 + ps * (kBlock / LPR) + lr;
+        if (row >= a.n_rows || idv[ps] == esc) continue;
+        const double y0 = ::fma(v1, s1[ps][0], v0 * s0[ps][0]);
+        const double y1 = ::fma(v1, s1[ps][1], v0 * s0[ps][1]);
+        *reinterpret_cast<double2 *>(Y + row * NR + rp) = double2{y0, y1};
+    }
+}
+
 template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *skip, double *dot) {
     SpmvArgs a{};
     a.skip = skip;
@@ -1088,6 +1189,45 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
     return grid;
 }
 
+// Window-phased block SpMV (k_dit_block_win): FP64, 2, 4 or 8 right-hand
+// sides, unpadded row-interleaved blocks; false when it does not apply.
+bool launch_block_win(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, int64_t ldx, void *Y,
+                      int64_t ldy, hipStream_t s) {
+    const LdsPlan &p = M->plan[SPMVC_F64];
+    if (M->fmt != SPMVC_FMT_DIT || !p.bw || M->P == 0) return false;
+    if (!(nrhs == 2 || nrhs == 4 || nrhs == 8) || ldx != nrhs || ldy != nrhs) return false;
+    if (reinterpret_cast<uintptr_t>(X) % 16 || reinterpret_cast<uintptr_t>(Y) % 16) return false;
+    const int64_t xb = static_cast<int64_t>(p.bw_maxlen) * nrhs * 8;
+    const int64_t tb = static_cast<int64_t>(M->P) * p.bw_nw * (kWinMaxPw + 1) * 4;
+    if (xb + tb > kLdsBudgetBytes) return false;
+    a.n_win = p.bw_nw;
+    for (int w = 0; w < p.bw_nw; ++w) {
+        a.win_lo[w] = p.bw_lo[w];
+        a.win_len[w] = p.bw_len[w];
+    }
+    a.async_lds = 1;
+    a.lds_x_bytes = static_cast<int32_t>(xb);
+    a.reg_tab = reinterpret_cast<const uint16_t *>(p.bw_tab.p);
+    const size_t shmem = static_cast<size_t>(xb + tb);
+    const unsigned grid = static_cast<unsigned>((M->n_rows + kWinRows - 1) / kWinRows);
+    const double *xp = static_cast<const double *>(X);
+    double *yp = static_cast<double *>(Y);
+    if (nrhs == 2)
+        k_dit_block_win<1><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+    else if (nrhs == 4)
+        k_dit_block_win<2><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+    else
+        k_dit_block_win<4><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+    SPMVC_CHECK_LAUNCH();
+    const unsigned eb = escape_blocks(M);
+    if (eb) {
+        a.n_main_blocks = 0;
+        k_spmv_lanes<SPMVC_FMT_DIT, double, uint8_t, false, 1, 1><<<eb, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+        SPMVC_CHECK_LAUNCH();
+    }
+    return true;
+}
+
 // Block SpMV of FP64 right-hand-side pairs with LDS windows (k_dit_reg_pairs);
 // false when it does not apply (format, value table, alignment, LDS size).
 bool launch_pairs(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, int64_t ldx, void *Y, int64_t ldy,
@@ -1213,6 +1353,7 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
     SpmvArgs a = make_args<Real>(M, skip, dot);
     constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
     if constexpr (dt == SPMVC_F64) {
+        if (nrhs > 1 && !dot && M->block_mode[dt] == 3 && launch_block_win(M, a, nrhs, X, ldx, Y, ldy, s)) return;
         if (nrhs > 1 && !dot && M->block_mode[dt] == 2 && launch_pairs(M, a, nrhs, X, ldx, Y, ldy, s)) return;
     }
     if (nrhs > 1 && !dot && M->block_mode[dt]) {
@@ -1313,6 +1454,50 @@ static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<st
     p.march = true;
 }
 
+// Window-phased block SpMV plan: the same displacement windows, laid out for
+// row tiles of kWinRows; per pattern and window the entry count and entries
+// (canonical index << 16 | element offset in the window).  Applies to DIT
+// matrices with a value table of 1 or 2 entries and no raw values, when no
+// pattern has more than kWinMaxPw entries in one window.
+static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p,
+                                    const std::vector<std::pair<int64_t, int64_t>> &win) {
+    if (!(M->K == 1 || M->K == 2) || M->raw_elems > 0 || win.empty() || static_cast<int>(win.size()) > kMaxWindows)
+        return;
+    const int NW = static_cast<int>(win.size());
+    int64_t lo[kMaxWindows], len[kMaxWindows];
+    int64_t maxlen = 0;
+    for (int w = 0; w < NW; ++w) {
+        lo[w] = win[w].first - (((win[w].first % 4) + 4) % 4);
+        len[w] = (kWinRows + win[w].second - lo[w] + 3) / 4 * 4;
+        if (len[w] > 65535) return;
+        maxlen = std::max(maxlen, len[w]);
+    }
+    const int W = M->width;
+    const int stride = kWinMaxPw + 1;
+    std::vector<uint32_t> tab(static_cast<size_t>(M->P) * NW * stride, 0);
+    for (int q = 0; q < M->P; ++q) {
+        const int L = M->h_pat_len[q];
+        for (int k = 0; k < L; ++k) {
+            const int64_t d = M->h_pat_off[static_cast<size_t>(q) * W + k];
+            int w = 0;
+            while (!(d >= win[w].first && d <= win[w].second)) ++w;
+            uint32_t *t = tab.data() + (static_cast<size_t>(q) * NW + w) * stride;
+            if (t[0] >= static_cast<uint32_t>(kWinMaxPw)) return;  // too many entries in one window
+            t[1 + t[0]] = (static_cast<uint32_t>(k) << 16) | static_cast<uint32_t>(d - lo[w]);
+            ++t[0];
+        }
+    }
+    p.bw_tab.alloc(sizeof(uint32_t) * tab.size());
+    SPMVC_HIP(hipMemcpy(p.bw_tab.p, tab.data(), p.bw_tab.bytes, hipMemcpyHostToDevice));
+    p.bw_nw = NW;
+    p.bw_maxlen = static_cast<int32_t>(maxlen);
+    for (int w = 0; w < NW; ++w) {
+        p.bw_lo[w] = lo[w];
+        p.bw_len[w] = static_cast<int32_t>(len[w]);
+    }
+    p.bw = true;
+}
+
 // Cut the displacement set into dense windows for `rows` rows per block and
 // express the pattern table in LDS offsets (the plan of dtype dt).  All LDS
 // use stays within kLdsBudgetBytes for FP64 elements (FP32 uses half of the x
@@ -1330,6 +1515,8 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     p.reg_tab_in_lds = false;
     p.reg128 = false;
     p.reg_tab128.release();
+    p.bw = false;
+    p.bw_tab.release();
     p.march = false;
     p.m_tab64.release();
     p.m_tab32.release();
@@ -1441,6 +1628,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         }
     }
     build_march_plan(M, p, win, lo, len, rows);
+    build_block_window_plan(M, p, win);
 }
 
 int kernel_kind(const spmvc_matrix_s *M, int dt) {

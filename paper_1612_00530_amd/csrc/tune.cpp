@@ -3,8 +3,9 @@
 // Candidates (single right-hand side, DIT): rows per block in {256 .. 4096}
 // with the x windows staged in LDS, the plane-marching form with row tiles of
 // {256, 512, 1024}, and the direct-gather kernel (x read through the L1/L2
-// caches).  Several right-hand sides (block SpMV): LDS windows of
-// right-hand-side pairs, a lane group per row, or one lane per row.  Every candidate gives a result within the same accuracy
+// caches).  Several right-hand sides (block SpMV): whole rows in LDS one
+// window at a time, LDS windows of right-hand-side pairs, a lane group per
+// row, or one lane per row.  Every candidate gives a result within the same accuracy
 // bound; only the time differs.  A candidate's time is the median over repetitions of the mean
 // of a run of back-to-back launches.  Winners are cached per (arch, format, rows, P, K, dtype, nrhs)
 // in the JSON object stored in the file named by $SPMVC_TUNE_CACHE.
@@ -110,8 +111,10 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
             for (int rows : {256, 512, 1024}) cands.push_back({rows, 2});
             cands.push_back({A->rows_per_block[dt], 0});
         } else if (nrhs > 1) {
-            // block SpMV: LDS windows of right-hand-side pairs (2, where it
-            // applies), a lane group per row (1) or one lane per row (0)
+            // block SpMV: whole rows in LDS one window at a time (3) or LDS
+            // windows of right-hand-side pairs (2), where they apply; a lane
+            // group per row (1) or one lane per row (0)
+            cands.push_back({A->rows_per_block[dt], 3});
             cands.push_back({A->rows_per_block[dt], 2});
             cands.push_back({A->rows_per_block[dt], 1});
             cands.push_back({A->rows_per_block[dt], 0});
