@@ -47,6 +47,12 @@ struct SysDesc {
     const double *esc_val;
     int64_t n_esc;
     double V[2];
+    // window-phased SpMV: the system's x windows for 256-row tiles and its
+    // per-(pattern, window) entry lists (see the FP64 plan of the handle)
+    int32_t bw_nw;
+    int64_t bw_lo[kMaxWindows];
+    int32_t bw_len[kMaxWindows];
+    const uint32_t *bw_tab;
 };
 
 struct Batch {
@@ -71,6 +77,8 @@ struct Batch {
     int32_t max_width;  // longest pattern of any system
     int32_t tab_lds;    // every system's pattern table fits the LDS copy of the SpMV
     int32_t tab_ints;   // largest pattern table (P * width entries)
+    int32_t win_x_bytes;  // window-phased SpMV: LDS bytes of the largest window (0: not used)
+    int32_t win_tab_bytes; // ... and of the largest entry-list table
     int32_t n_xcd;      // XCDs the blocks are dispatched over (tile mapping of the SpMV)
 };
 
@@ -281,6 +289,153 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
         const double t = rhs_sum<LPR>(dotc[v]);
         const int rr = static_cast<int>(threadIdx.x) * VEC + v;
         if (threadIdx.x < LPR && rr < nr) part[static_cast<int64_t>(tile) * nr + rr] = t;
+    }
+}
+
+// One 16-byte direct global-to-LDS load per lane: the wavefront's 64 chunks
+// land contiguously at lds (a wavefront-uniform address).  The builtin exists
+// only for the GPU target; the host compilation pass sees an empty body.
+__device__ __forceinline__ void lds_load16(const void *g, void *lds) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+#else
+    (void)g;
+    (void)lds;
+#endif
+}
+
+// Window-phased form of k_bspmv for nrhs = 2 * LPR (2, 4 or 8): the tile's
+// rows of one x window at a time -- whole rows of the row-interleaved block,
+// a contiguous range -- are copied into LDS, and every row adds the products
+// of its entries that fall in that window (entry lists per pattern and
+// window).  One lane per right-hand-side pair, LPR lanes per row; two sums per
+// pair (one per value-table entry), scaled once.
+template <int LPR>
+__global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restrict__ Pin,
+                                                  double *__restrict__ Qout, double *part, int with_dot) {
+    extern __shared__ __align__(16) unsigned char wsm[];
+    constexpr int NR = 2 * LPR;
+    constexpr int PASSES = kT / (kT / LPR);  // = LPR
+    constexpr int ST = kWinMaxPw + 1;
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd);
+    const int s = b.tile_sys[tile];
+    if (!b.sys_active[s]) return;  // uniform per block
+    const SysDesc &d = b.sys[s];
+    double *xs = reinterpret_cast<double *>(wsm);
+    uint32_t *tab_s = reinterpret_cast<uint32_t *>(wsm + b.win_x_bytes);
+    const int NW = d.bw_nw;
+    const int64_t r0 = static_cast<int64_t>(tile - d.tile0) * kT;  // system-local first row
+    const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+    const int lr = threadIdx.x / LPR;
+    const int rp = (threadIdx.x % LPR) * 2;
+    const bool lane_on = rp < b.nrhs;
+    uint32_t idv[PASSES];
+    int t0v[PASSES];
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+        int64_t lrow = r0 + ps * (kT / LPR) + lr;
+        lrow = lrow < d.n ? lrow : d.n - 1;
+        idv[ps] = load_id(d.ids, d.id_bytes, lrow);
+        t0v[ps] = d.K >= 2 ? static_cast<int>(d.T[lrow]) : 255;
+    }
+    {
+        const int nt = d.P * NW * ST;
+        for (int e = threadIdx.x; e < nt; e += kT) tab_s[e] = d.bw_tab[e];
+    }
+    double s0[PASSES][2], s1[PASSES][2];
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            s0[ps][v] = 0.0;
+            s1[ps][v] = 0.0;
+        }
+    const double *sysP = Pin + d.row0 * NR;  // the system's rows
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < NW; ++w) {
+        if (w > 0) __syncthreads();  // every row is done with the previous window
+        const int64_t g0 = r0 + d.bw_lo[w];
+        const int n = d.bw_len[w];
+        if (g0 >= 0 && g0 + n <= d.n) {
+            const double *src = sysP + g0 * NR;
+            const int nchunk = n * NR / 2;
+            for (int c = wave * 64; c < nchunk; c += kT) {
+                const int e = c + lane;
+                if (e < nchunk) lds_load16(src + 2 * e, xs + 2 * c);
+            }
+        } else {
+            const int64_t last = d.n - 1;
+            for (int e = threadIdx.x; e < n * NR; e += kT) {
+                int64_t g = g0 + e / NR;
+                g = g < 0 ? 0 : (g > last ? last : g);
+                xs[e] = sysP[g * NR + e % NR];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int rel = ps * (kT / LPR) + lr;
+            if (r0 + rel >= d.n || idv[ps] == esc) continue;
+            const uint32_t *t = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * ST;
+            const int cnt = static_cast<int>(t[0]);
+            for (int k = 0; k < cnt; ++k) {
+                const uint32_t ent = t[1 + k];
+                const int off = static_cast<int>(ent & 0xFFFFu);
+                const int kc = static_cast<int>(ent >> 16);
+                const double2 xv = *reinterpret_cast<const double2 *>(xs + (rel + off) * NR + rp);
+                if (kc < t0v[ps]) {
+                    s0[ps][0] += xv.x;
+                    s0[ps][1] += xv.y;
+                } else {
+                    s1[ps][0] += xv.x;
+                    s1[ps][1] += xv.y;
+                }
+            }
+        }
+    }
+    double dotc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+        const int64_t lrow = r0 + ps * (kT / LPR) + lr;
+        if (lrow >= d.n) continue;
+        double q0, q1;
+        if (idv[ps] != esc) {
+            // with one table entry every entry went to s0 (s1 stays 0)
+            const double v1 = d.K >= 2 ? d.V[1] : 0.0;
+            q0 = fma(v1, s1[ps][0], d.V[0] * s0[ps][0]);
+            q1 = fma(v1, s1[ps][1], d.V[0] * s0[ps][1]);
+        } else {
+            // escape row: plain CSR gathers from global memory
+            int64_t lo = 0, hi = d.n_esc;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) / 2;
+                if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
+            }
+            q0 = 0.0;
+            q1 = 0.0;
+            for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) {
+                const double2 xv = *reinterpret_cast<const double2 *>(sysP + static_cast<int64_t>(d.esc_col[e]) * NR + rp);
+                q0 = fma(d.esc_val[e], xv.x, q0);
+                q1 = fma(d.esc_val[e], xv.y, q1);
+            }
+        }
+        if (lane_on) {
+            const int64_t gi = (d.row0 + lrow) * NR + rp;
+            *reinterpret_cast<double2 *>(Qout + gi) = double2{q0, q1};
+            if (with_dot) {
+                const double2 pv = *reinterpret_cast<const double2 *>(Pin + gi);
+                dotc[0] += pv.x * q0;
+                dotc[1] += pv.y * q1;
+            }
+        }
+    }
+    if (!with_dot) return;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        const double t = rhs_sum<LPR>(dotc[v]);
+        const int rr = static_cast<int>(threadIdx.x) * 2 + v;
+        if (threadIdx.x < LPR && rr < b.nrhs) part[static_cast<int64_t>(tile) * b.nrhs + rr] = t;
     }
 }
 
@@ -547,6 +702,16 @@ constexpr int kTabLdsInts = 4096;  // pattern tables up to 16 KB are copied to L
 
 void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles);
+    if (b.win_x_bytes > 0) {
+        const size_t wsh = static_cast<size_t>(b.win_x_bytes) + static_cast<size_t>(b.win_tab_bytes);
+        if (b.nrhs == 2)
+            k_bspmv_win<1><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
+        else if (b.nrhs == 4)
+            k_bspmv_win<2><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
+        else
+            k_bspmv_win<4><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
+        return;
+    }
     const size_t sh = b.tab_lds ? sizeof(int32_t) * static_cast<size_t>(b.tab_ints) : 0;
     // two right-hand sides per lane when every row's block starts 16-byte aligned
     const bool pairs = b.nrhs % 2 == 0;
@@ -613,6 +778,13 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         d.n_esc = M->n_esc;
         d.V[0] = M->V[0];
         d.V[1] = M->V[1];
+        const LdsPlan &pl = M->plan[SPMVC_F64];
+        d.bw_nw = pl.bw ? pl.bw_nw : 0;
+        for (int w = 0; w < kMaxWindows; ++w) {
+            d.bw_lo[w] = pl.bw_lo[w];
+            d.bw_len[w] = pl.bw_len[w];
+        }
+        d.bw_tab = pl.bw ? pl.bw_tab.as<uint32_t>() : nullptr;
         for (int t = 0; t < d.ntiles; ++t) tile_sys.push_back(s);
         row0 += M->n_rows;
         tile0 += d.ntiles;
@@ -666,6 +838,21 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         b.tab_ints = std::max(b.tab_ints, sd[q].P * sd[q].width);
     }
     b.tab_lds = b.tab_ints > 0 && b.tab_ints <= kTabLdsInts;
+    // window-phased SpMV when every system has its window plan, nrhs is 2, 4
+    // or 8 and the largest window and table fit the LDS budget
+    b.win_x_bytes = 0;
+    b.win_tab_bytes = 0;
+    bool win_ok = nrhs == 2 || nrhs == 4 || nrhs == 8;
+    for (int q = 0; q < n_sys && win_ok; ++q) {
+        const LdsPlan &pl = A[q]->plan[SPMVC_F64];
+        if (!pl.bw) {
+            win_ok = false;
+            break;
+        }
+        b.win_x_bytes = std::max<int32_t>(b.win_x_bytes, pl.bw_maxlen * nrhs * 8);
+        b.win_tab_bytes = std::max<int32_t>(b.win_tab_bytes, A[q]->P * pl.bw_nw * (kWinMaxPw + 1) * 4);
+    }
+    if (!win_ok || b.win_x_bytes + b.win_tab_bytes > kLdsBudgetBytes) b.win_x_bytes = 0;
     b.B = B.as<double>();
     b.X = X.as<double>();
     b.R = R.as<double>();

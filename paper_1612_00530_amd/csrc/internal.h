@@ -102,7 +102,7 @@ struct LdsPlan {
 
 constexpr int kRegW = 31;   // longest pattern the register kernel takes
 constexpr int kWinRows = 256;   // row tile of the window-phased block SpMV
-constexpr int kWinMaxPw = 12;   // most entries of one pattern in one window (window-phased)
+constexpr int kWinMaxPw = 32;   // most entries of one pattern in one window (window-phased)
 constexpr int kRegTw = 32;  // uint16 per register-table row (64 bytes, 16-byte aligned)
 
 }  // namespace spmvc

@@ -1454,15 +1454,22 @@ static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<st
     p.march = true;
 }
 
-// Window-phased block SpMV plan: the same displacement windows, laid out for
-// row tiles of kWinRows; per pattern and window the entry count and entries
+// Window-phased block SpMV plan: displacement windows for row tiles of
+// kWinRows; per pattern and window the entry count and entries
 // (canonical index << 16 | element offset in the window).  Applies to DIT
 // matrices with a value table of 1 or 2 entries and no raw values, when no
 // pattern has more than kWinMaxPw entries in one window.
-static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p,
-                                    const std::vector<std::pair<int64_t, int64_t>> &win) {
-    if (!(M->K == 1 || M->K == 2) || M->raw_elems > 0 || win.empty() || static_cast<int>(win.size()) > kMaxWindows)
-        return;
+static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p, const std::set<int64_t> &ds) {
+    if (!(M->K == 1 || M->K == 2) || M->raw_elems > 0 || ds.empty()) return;
+    // windows for kWinRows-row tiles: clusters closer than a tile merge
+    std::vector<std::pair<int64_t, int64_t>> win;
+    for (int64_t d : ds) {
+        if (!win.empty() && d - win.back().second <= kWinRows)
+            win.back().second = d;
+        else
+            win.push_back({d, d});
+    }
+    if (static_cast<int>(win.size()) > kMaxWindows) return;
     const int NW = static_cast<int>(win.size());
     int64_t lo[kMaxWindows], len[kMaxWindows];
     int64_t maxlen = 0;
@@ -1526,6 +1533,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     for (int q = 0; q < M->P; ++q)
         for (int k = 0; k < M->h_pat_len[q]; ++k) ds.insert(M->h_pat_off[static_cast<size_t>(q) * W + k]);
     if (ds.empty()) return;
+    build_block_window_plan(M, p, ds);  // independent of `rows`
     // Two windows merge when the gap between them is below `rows`: a separate
     // window costs `rows` more LDS elements than the gap it skips.
     std::vector<std::pair<int64_t, int64_t>> win;
@@ -1628,7 +1636,6 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         }
     }
     build_march_plan(M, p, win, lo, len, rows);
-    build_block_window_plan(M, p, win);
 }
 
 int kernel_kind(const spmvc_matrix_s *M, int dt) {
