@@ -9,10 +9,11 @@
 // finished drops out of the tile loops.
 //
 // One iteration is five launches:
-//   bspmv      Q = A_s P for the active systems (a group of lanes per row,
-//              one lane per right-hand side of the row-interleaved block, so
-//              every gather is a contiguous run) and per-tile partials of p.q
-//              for every rhs;
+//   bspmv      Q = A_s P for the active systems and per-tile partials of p.q
+//              for every rhs: for 2, 4 or 8 right-hand sides whole rows of each
+//              x window in turn are staged in LDS (k_bspmv_win); otherwise a
+//              group of lanes per row gathers through the caches, one lane per
+//              right-hand side (or pair) of the row-interleaved block (k_bspmv);
 //   fin_alpha  one block per system: sigma = sum of its tiles' partials (fixed
 //              order), alpha = rho / sigma, breakdown test;
 //   update     R -= alpha Q for the pairs taking a step; partials of r.r;

@@ -5,9 +5,9 @@
 //   ELL  col/val [width][n_pad]            (Section IV-B baseline, 12 B per slot)
 //   DT   S [width][n_pad], T u8 [K][n_pad]  (value table + sorted columns, Fig. 1)
 //   DIT  ID [n_pad], T u8 [K][n_pad]        (pattern ID + terminal indices)
-// One lane owns one row.  A row's entries are consumed in the canonical order
-// of Section V: first all entries of V[0] (positions < T[0]), then V[1], ...,
-// then the raw FP64 entries.
+// In the single-vector kernels one lane owns one row.  A row's entries are
+// consumed in the canonical order of Section V: first all entries of V[0]
+// (positions < T[0]), then V[1], ..., then the raw FP64 entries.
 //
 // DIT with LDS staging: for a block of R consecutive rows [r0, r0+R) every
 // displacement d of the pattern table reads x[r0+d .. r0+R-1+d].  The sorted
@@ -22,11 +22,19 @@
 // independent and issue back to back.  Per entry it costs one add (offset +
 // row), one LDS read and one add (one FMA where the value must be selected per
 // lane).  Rows shorter than the table width read a zero window in LDS for the
-// missing entries (exact when every table value is finite); patterns with raw
-// values use a per-entry predicate.
+// missing entries (exact when every table value is finite); with every value
+// raw, a row's values are read up to its 64-row slice's width (zero padding).
+// k_dit_march is its plane-marching form: a block walks one row tile through
+// consecutive planes and stages one new window per step.
 //
-// Escape rows (plain CSR) are served by extra blocks appended to the same grid;
-// the main blocks skip them (ID == all-ones, or column -2 in slot 0).
+// Several right-hand sides (row-interleaved blocks): k_dit_block_win holds
+// whole rows of one window at a time in LDS; k_dit_reg_pairs the windows of
+// one right-hand-side pair; k_spmv_lanes gathers through the caches with a
+// group of lanes per row.
+//
+// Escape rows (plain CSR) are served by extra blocks appended to the same grid
+// (or a launch of their own); the main blocks skip them (ID == all-ones, or
+// column -2 in slot 0).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
