@@ -52,12 +52,11 @@ def traffic_from_profile(kernel, rows_per_block):
 
     if field("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if field("kernel") != kernel or field("rows_per_block") != str(rows_per_block):
+    m = re.search(r"^traffic:\s+" + re.escape(kernel) + r"\s+" + str(int(rows_per_block)) + r"\s+(\d+)\s+(\d+)\s*$",
+                  txt, re.M)
+    if m is None:
         return None
-    f, w = field("fetch_bytes_per_launch"), field("write_bytes_per_launch")
-    if f is None or w is None:
-        return None
-    return float(f) + float(w)
+    return float(m.group(1)) + float(m.group(2))
 
 
 def time_launches(fn, reps, torch):
@@ -113,6 +112,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 512 MiB read+write elementwise kernel (counter calibration)")
+    ap.add_argument("--pmc-configs", action="store_true",
+                    help="after the timed region, also launch the FP64 DIT kernel in each tuner candidate "
+                         "configuration (register and plane-marching kernels, 256/512/1024 rows per block) "
+                         "so that one counter run covers whichever the tuner picks")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -181,6 +184,14 @@ def main():
     alg_dit = dinf["bytes_stream"] + 8 * n + 8 * n
     achieved = alg_dit / (k_mean * 1e-3) / 1e9
     traffic = traffic_from_profile(dinf["kernel_name"], dinf["rows_per_block"])
+    if args.pmc_configs:
+        for lds in (1, 2):
+            for rows in (256, 512, 1024):
+                D.set_config(rows, lds)
+                for _ in range(args.steps):
+                    D.spmv(x, y)
+        torch.cuda.synchronize()
+        D.set_config(dinf["rows_per_block"], {0: 0, 1: 1, 2: 1, 3: 2}[dinf["kernel"]])
 
     # ELL baseline, same matrix and vectors
     for _ in range(args.warmup):

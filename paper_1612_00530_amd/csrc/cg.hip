@@ -27,6 +27,7 @@
 // block scheduling, so iteration counts repeat exactly from run to run.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 #include "internal.h"
 
@@ -73,20 +74,43 @@ template <int NT> __device__ __forceinline__ double sum_partials(const double *p
 
 template <class Real> __device__ __forceinline__ double dd(Real v) { return static_cast<double>(v); }
 
-// Grid-stride loop over [0, n) that handles four elements per step, each a
+// Grid-stride loop over [0, N) that handles four items per step, each a
 // stride apart, so every thread has four independent loads of each stream in
-// flight; the tail is handled one element at a time.
-#define SPMVC_STREAM4(BODY4, BODY1)                                                              \
+// flight; the tail is handled one item at a time.
+#define SPMVC_STREAM4N(N, BODY4, BODY1)                                                          \
     {                                                                                            \
         const int64_t stride_ = static_cast<int64_t>(gridDim.x) * kRT;                           \
         int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x;                        \
-        for (; i + 3 * stride_ < n; i += 4 * stride_) {                                          \
+        for (; i + 3 * stride_ < (N); i += 4 * stride_) {                                        \
             BODY4                                                                                \
         }                                                                                        \
-        for (; i < n; i += stride_) {                                                            \
+        for (; i < (N); i += stride_) {                                                          \
             BODY1                                                                                \
         }                                                                                        \
     }
+#define SPMVC_STREAM4(BODY4, BODY1) SPMVC_STREAM4N(n, BODY4, BODY1)
+
+// W consecutive elements moved as one access: 16-byte loads and stores double
+// the bytes each wave has in flight over 8-byte (FP64) ones and quadruple them
+// over 4-byte (FP32) ones, which is what the two CG update kernels need to
+// approach the HBM rate with one 8-wave block per CU.
+template <class Real, int W> struct Pack;
+template <class Real> struct Pack<Real, 1> { using T = Real; };
+template <> struct Pack<double, 2> { using T = double __attribute__((ext_vector_type(2))); };
+template <> struct Pack<float, 4> { using T = float __attribute__((ext_vector_type(4))); };
+
+__device__ __forceinline__ double sumsq(double v) { return v * v; }
+__device__ __forceinline__ double sumsq(float v) { return static_cast<double>(v) * static_cast<double>(v); }
+__device__ __forceinline__ double sumsq(Pack<double, 2>::T v) { return v.x * v.x + v.y * v.y; }
+__device__ __forceinline__ double sumsq(Pack<float, 4>::T v) {
+    return sumsq(v.x) + sumsq(v.y) + sumsq(v.z) + sumsq(v.w);
+}
+
+template <class Real> constexpr int pack_width() { return 16 / static_cast<int>(sizeof(Real)); }
+
+inline bool aligned16(const void *a, const void *b, const void *c = nullptr) {
+    return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) & 15) == 0;
+}
 
 // x = 0, r = rhs, p = rhs; partials of r.r
 template <class Real, class RhsT>
@@ -134,7 +158,7 @@ __global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, in
 // r -= alpha q; partials of r.r.  A breakdown (sigma <= 0 or not finite) stops
 // the solve.  Block 0 records sigma and whether the step ran (go), which the
 // p-update reads: it must not read `done`, which its own block 0 may set.
-template <class Real>
+template <class Real, int W>
 __global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__ r, const Real *__restrict__ q,
                                                    const double *sig_part, int n_sig, double *rr_part, CgScal *st,
                                                    int par, int it) {
@@ -160,19 +184,31 @@ __global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__
     }
     const Real alpha = static_cast<Real>(st->rho[par] / sigma);
     double acc = 0.0;
-    SPMVC_STREAM4(
-        Real rv[4]; Real qv[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = r[i + u * stride_]; qv[u] = q[i + u * stride_]; }
+    using T = typename Pack<Real, W>::T;
+    T *__restrict__ rw = reinterpret_cast<T *>(r);
+    const T *__restrict__ qw = reinterpret_cast<const T *>(q);
+    const int64_t nw = n / W;
+    SPMVC_STREAM4N(nw,
+        T rv[4]; T qv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = rw[i + u * stride_]; qv[u] = qw[i + u * stride_]; }
 _Pragma("unroll") for (int u = 0; u < 4; ++u) {
-            const Real ri = rv[u] - alpha * qv[u];
-            r[i + u * stride_] = ri;
-            acc += dd(ri) * dd(ri);
+            const T ri = rv[u] - alpha * qv[u];
+            rw[i + u * stride_] = ri;
+            acc += sumsq(ri);
         }
         ,
-        const Real ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        acc += dd(ri) * dd(ri);
+        const T ri = rw[i] - alpha * qw[i];
+        rw[i] = ri;
+        acc += sumsq(ri);
     )
+    if (W > 1 && blockIdx.x == 0) {  // the last n mod W elements
+        const int64_t i = nw * W + threadIdx.x;
+        if (i < n) {
+            const Real ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            acc += sumsq(ri);
+        }
+    }
     const double b = block_sum<kRT>(acc);
     if (threadIdx.x == 0) rr_part[blockIdx.x] = b;
 }
@@ -180,7 +216,7 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
 // rho' = sum of the r.r partials; convergence test; x += alpha p (with the
 // update step's alpha); unless the solve stops here, beta = rho'/rho and
 // p = r + beta p.  x is updated here, not in k_cg_update, so p is read once.
-template <class Real>
+template <class Real, int W>
 __global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, Real *__restrict__ x, const Real *__restrict__ r,
                                                     Real *__restrict__ p, const double *rr_part, int n_rr,
                                                     CgScal *st, int par, int it) {
@@ -205,30 +241,41 @@ __global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, Real *__restrict_
         }
     }
     const Real alpha = static_cast<Real>(rho / st->sigma);
+    using T = typename Pack<Real, W>::T;
+    T *__restrict__ xw = reinterpret_cast<T *>(x);
+    const T *__restrict__ rw = reinterpret_cast<const T *>(r);
+    T *__restrict__ pw = reinterpret_cast<T *>(p);
+    const int64_t nw = n / W;
+    const int64_t tail = (W > 1 && blockIdx.x == 0) ? nw * W + threadIdx.x : n;  // the last n mod W elements
     if (stop) {
-        SPMVC_STREAM4(
-            Real xv[4]; Real pv[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) { xv[u] = x[i + u * stride_]; pv[u] = p[i + u * stride_]; }
-_Pragma("unroll") for (int u = 0; u < 4; ++u) x[i + u * stride_] = xv[u] + alpha * pv[u];
+        SPMVC_STREAM4N(nw,
+            T xv[4]; T pv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { xv[u] = xw[i + u * stride_]; pv[u] = pw[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) xw[i + u * stride_] = xv[u] + alpha * pv[u];
             ,
-            x[i] = x[i] + alpha * p[i];
+            xw[i] = xw[i] + alpha * pw[i];
         )
+        if (tail < n) x[tail] = x[tail] + alpha * p[tail];
         return;
     }
     const Real beta = static_cast<Real>(rho_new / rho);
-    SPMVC_STREAM4(
-        Real xv[4]; Real rv[4]; Real pv[4];
+    SPMVC_STREAM4N(nw,
+        T xv[4]; T rv[4]; T pv[4];
 _Pragma("unroll") for (int u = 0; u < 4; ++u) {
-            xv[u] = x[i + u * stride_]; rv[u] = r[i + u * stride_]; pv[u] = p[i + u * stride_];
+            xv[u] = xw[i + u * stride_]; rv[u] = rw[i + u * stride_]; pv[u] = pw[i + u * stride_];
         }
 _Pragma("unroll") for (int u = 0; u < 4; ++u) {
-            x[i + u * stride_] = xv[u] + alpha * pv[u];
-            p[i + u * stride_] = rv[u] + beta * pv[u];
+            xw[i + u * stride_] = xv[u] + alpha * pv[u];
+            pw[i + u * stride_] = rv[u] + beta * pv[u];
         }
         ,
-        x[i] = x[i] + alpha * p[i];
-        p[i] = r[i] + beta * p[i];
+        xw[i] = xw[i] + alpha * pw[i];
+        pw[i] = rw[i] + beta * pw[i];
     )
+    if (tail < n) {
+        x[tail] = x[tail] + alpha * p[tail];
+        p[tail] = r[tail] + beta * p[tail];
+    }
 }
 
 // partials of (b - ax).(b - ax), optionally storing r = b - ax; partials of b.b
@@ -329,6 +376,8 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Rea
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     const int dt = std::is_same<Real, double>::value ? SPMVC_F64 : SPMVC_F32;
+    constexpr int VW = pack_width<Real>();
+    const bool vec_u = aligned16(r, q), vec_p = aligned16(z, r, p);
     k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, z, r, p, sv.part_a.as<double>());
     k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), rtol, max_iter);
     SPMVC_CHECK_LAUNCH();
@@ -339,10 +388,18 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Rea
         for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
             const int par = it & 1;
             const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.part_sig.as<double>());
-            k_cg_update<Real><<<g, kRT, 0, sv.s>>>(n, r, q, sv.part_sig.as<double>(), static_cast<int>(ns),
-                                                   sv.part_b.as<double>(), sv.st(), par, it);
-            k_cg_pupdate<Real><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.part_b.as<double>(), static_cast<int>(g), sv.st(),
-                                                    par, it);
+            if (vec_u)
+                k_cg_update<Real, VW><<<g, kRT, 0, sv.s>>>(n, r, q, sv.part_sig.as<double>(), static_cast<int>(ns),
+                                                           sv.part_b.as<double>(), sv.st(), par, it);
+            else
+                k_cg_update<Real, 1><<<g, kRT, 0, sv.s>>>(n, r, q, sv.part_sig.as<double>(), static_cast<int>(ns),
+                                                          sv.part_b.as<double>(), sv.st(), par, it);
+            if (vec_p)
+                k_cg_pupdate<Real, VW><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.part_b.as<double>(), static_cast<int>(g),
+                                                            sv.st(), par, it);
+            else
+                k_cg_pupdate<Real, 1><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.part_b.as<double>(), static_cast<int>(g),
+                                                           sv.st(), par, it);
         }
         SPMVC_CHECK_LAUNCH();
     }

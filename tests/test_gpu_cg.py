@@ -74,6 +74,38 @@ def test_cg_under_each_spmv_configuration(rows, lds):
         assert np.abs(x - 1).max() < 1e-7
 
 
+@pytest.mark.parametrize("offset", [0, 1])
+def test_cg_odd_size_and_unaligned_vectors(offset):
+    """The CG update kernels move 16-byte packs when every vector they touch is
+    16-byte aligned and handle the last n mod 2 (FP64) or n mod 4 (FP32)
+    elements one at a time; with x and b one element into their buffers the
+    x/p update falls back to 8-byte accesses.  Both must give the oracle's
+    solve, in FP64 and mixed precision, on a grid whose n = 7*9*11 is odd."""
+    say("case: cg odd/unaligned", offset)
+    torch = torch_mod()
+    P = lib()
+    A = stencil27(7, 9, 11)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    M = compress(A, fmt="DIT")
+    _, _, it_ref, _ = oracle.cg(A, b)
+    bbuf = torch.zeros(A.n_rows + 1, dtype=torch.float64, device="cuda")
+    bbuf[offset:offset + A.n_rows] = torch.from_numpy(b).cuda()
+    bt = bbuf[offset:offset + A.n_rows]
+    for mode in (0, 1):
+        xbuf = torch.full((A.n_rows + 1,), 7.0, dtype=torch.float64, device="cuda")
+        xt = xbuf[offset:offset + A.n_rows]
+        st, _, stats = P.cg_solve(M, bt, xs=xt, mode=mode)
+        torch.cuda.synchronize()
+        x = xt.cpu().numpy()
+        assert st == 0 and stats[0]["status"] == 0
+        if mode == 0:
+            assert abs(stats[0]["iters"] - it_ref) <= 2
+        assert oracle.relres(A, b, x) <= 1.5e-10
+        assert np.abs(x - 1).max() < 1e-7
+        rest = xbuf.cpu().numpy()
+        assert rest[0 if offset else A.n_rows] == 7.0  # the element outside the view is untouched
+
+
 def test_fp64_cg_random_rhs_irregular():
     say("case: cg irregular")
     A = stencil27_irregular(30, 28, 26, seed=0)
