@@ -305,25 +305,45 @@ __device__ __forceinline__ void lds_load16(const void *g, void *lds) {
 #endif
 }
 
+// Four entries of a row's (pattern, window) record against the x window: four
+// 16-byte x reads in flight, then four weighted FMAs (value V[0] for
+// canonical index < t0, else V[1]).  In the last group (TAIL) the entries
+// past `rem` are padding: they read window row 0 and take weight 0.
+template <int NRB, bool TAIL>
+__device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, int t0, int rem, double v0, double v1,
+                                           double &a0, double &a1) {
+    const uint32_t ent[4] = {e.x, e.y, e.z, e.w};
+    double2 xv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const double2 *>(xrow + (ent[j] & 0xFFFFu) * NRB);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
+        if (TAIL && j > 0) wgt = j < rem ? wgt : 0.0;
+        a0 = fma(wgt, xv[j].x, a0);
+        a1 = fma(wgt, xv[j].y, a1);
+    }
+}
+
 // Window-phased form of k_bspmv for nrhs = 2 * LPR (2, 4 or 8): the tile's
 // rows of one x window at a time -- whole rows of the row-interleaved block,
 // a contiguous range -- are copied into LDS, and every row adds the products
-// of its entries that fall in that window (entry lists per pattern and
-// window).  One lane per right-hand-side pair, LPR lanes per row; two sums per
-// pair (one per value-table entry), scaled once.
+// of its entries that fall in that window (per pattern and window a record of
+// the count and the zero-padded entries, read four entries at a time).  One
+// lane per right-hand-side pair, LPR lanes per row; each product is weighted
+// by its value-table entry as it is added.
 template <int LPR>
 __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restrict__ Pin,
                                                   double *__restrict__ Qout, double *part, int with_dot) {
     extern __shared__ __align__(16) unsigned char wsm[];
     constexpr int NR = 2 * LPR;
     constexpr int PASSES = kT / (kT / LPR);  // = LPR
-    constexpr int ST = kWinMaxPw + 1;
     const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd);
     const int s = b.tile_sys[tile];
     if (!b.sys_active[s]) return;  // uniform per block
     const SysDesc &d = b.sys[s];
     double *xs = reinterpret_cast<double *>(wsm);
-    uint32_t *tab_s = reinterpret_cast<uint32_t *>(wsm + b.win_x_bytes);
+    const uint4 *tab_s = reinterpret_cast<const uint4 *>(wsm + b.win_x_bytes);
     const int NW = d.bw_nw;
     const int64_t r0 = static_cast<int64_t>(tile - d.tile0) * kT;  // system-local first row
     const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
@@ -340,17 +360,15 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
         t0v[ps] = d.K >= 2 ? static_cast<int>(d.T[lrow]) : 255;
     }
     {
-        const int nt = d.P * NW * ST;
-        for (int e = threadIdx.x; e < nt; e += kT) tab_s[e] = d.bw_tab[e];
+        const int n16 = d.P * NW * (kWinSt / 4);
+        const uint4 *src = reinterpret_cast<const uint4 *>(d.bw_tab);
+        uint4 *dst = reinterpret_cast<uint4 *>(wsm + b.win_x_bytes);
+        for (int e = threadIdx.x; e < n16; e += kT) dst[e] = src[e];
     }
-    double s0[PASSES][2], s1[PASSES][2];
+    const double v0 = d.V[0], v1 = d.K >= 2 ? d.V[1] : d.V[0];
+    double acc[PASSES][2];
 #pragma unroll
-    for (int ps = 0; ps < PASSES; ++ps)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            s0[ps][v] = 0.0;
-            s1[ps][v] = 0.0;
-        }
+    for (int ps = 0; ps < PASSES; ++ps) acc[ps][0] = acc[ps][1] = 0.0;
     const double *sysP = Pin + d.row0 * NR;  // the system's rows
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int w = 0; w < NW; ++w) {
@@ -378,21 +396,15 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
         for (int ps = 0; ps < PASSES; ++ps) {
             const int rel = ps * (kT / LPR) + lr;
             if (r0 + rel >= d.n || idv[ps] == esc) continue;
-            const uint32_t *t = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * ST;
-            const int cnt = static_cast<int>(t[0]);
-            for (int k = 0; k < cnt; ++k) {
-                const uint32_t ent = t[1 + k];
-                const int off = static_cast<int>(ent & 0xFFFFu);
-                const int kc = static_cast<int>(ent >> 16);
-                const double2 xv = *reinterpret_cast<const double2 *>(xs + (rel + off) * NR + rp);
-                if (kc < t0v[ps]) {
-                    s0[ps][0] += xv.x;
-                    s0[ps][1] += xv.y;
-                } else {
-                    s1[ps][0] += xv.x;
-                    s1[ps][1] += xv.y;
-                }
-            }
+            const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
+            const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
+            const int cnt = static_cast<int>(rec[0].x);
+            int k0 = 0;
+            for (; k0 + 4 <= cnt; k0 += 4)
+                bwin_group<NR * 8, false>(rec[1 + (k0 >> 2)], xrow, t0v[ps], 4, v0, v1, acc[ps][0], acc[ps][1]);
+            if (k0 < cnt)
+                bwin_group<NR * 8, true>(rec[1 + (k0 >> 2)], xrow, t0v[ps], cnt - k0, v0, v1, acc[ps][0],
+                                         acc[ps][1]);
         }
     }
     double dotc[2] = {0.0, 0.0};
@@ -402,10 +414,8 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
         if (lrow >= d.n) continue;
         double q0, q1;
         if (idv[ps] != esc) {
-            // with one table entry every entry went to s0 (s1 stays 0)
-            const double v1 = d.K >= 2 ? d.V[1] : 0.0;
-            q0 = fma(v1, s1[ps][0], d.V[0] * s0[ps][0]);
-            q1 = fma(v1, s1[ps][1], d.V[0] * s0[ps][1]);
+            q0 = acc[ps][0];
+            q1 = acc[ps][1];
         } else {
             // escape row: plain CSR gathers from global memory
             int64_t lo = 0, hi = d.n_esc;
@@ -851,7 +861,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
             break;
         }
         b.win_x_bytes = std::max<int32_t>(b.win_x_bytes, pl.bw_maxlen * nrhs * 8);
-        b.win_tab_bytes = std::max<int32_t>(b.win_tab_bytes, A[q]->P * pl.bw_nw * (kWinMaxPw + 1) * 4);
+        b.win_tab_bytes = std::max<int32_t>(b.win_tab_bytes, A[q]->P * pl.bw_nw * kWinSt * 4);
     }
     if (!win_ok || b.win_x_bytes + b.win_tab_bytes > kLdsBudgetBytes) b.win_x_bytes = 0;
     b.B = B.as<double>();

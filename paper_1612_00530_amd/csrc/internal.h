@@ -82,7 +82,8 @@ struct LdsPlan {
     DevBuf reg_tab128;            //   pairs of FP64 right-hand sides): offsets for those
     // window-phased block SpMV (whole right-hand-side rows in LDS, one window
     // at a time, row tiles of kWinRows): windows, and per pattern and window
-    // the count and the entries ((canonical index << 16) | element in window)
+    // a kWinSt-word record: the count and the entries
+    // ((canonical index << 16) | element in window)
     bool bw = false;
     int32_t bw_nw = 0, bw_maxlen = 0;
     int64_t bw_lo[kMaxWindows] = {};
@@ -103,6 +104,10 @@ struct LdsPlan {
 constexpr int kRegW = 31;   // longest pattern the register kernel takes
 constexpr int kWinRows = 256;   // row tile of the window-phased block SpMV
 constexpr int kWinMaxPw = 32;   // most entries of one pattern in one window (window-phased)
+// uint32 words per (pattern, window) record of the window-phased table: the
+// count, three unused words, then up to kWinMaxPw entries, zero-padded, so
+// the entries can be read four at a time with 16-byte loads
+constexpr int kWinSt = 4 + kWinMaxPw;
 constexpr int kRegTw = 32;  // uint16 per register-table row (64 bytes, 16-byte aligned)
 
 }  // namespace spmvc

@@ -867,24 +867,56 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
 }
 
 // ---- block SpMV, whole right-hand-side rows in LDS, one window at a time ----------
+// Four entries of a row's (pattern, window) record against the x window: four
+// 16-byte x reads in flight, then four weighted FMAs (value V[0] for
+// canonical index < t0, else V[1]).  In the last group (TAIL) the entries
+// past `rem` are padding: they read window row 0 and take weight 0.
+template <int NRB, bool TAIL>
+__device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, int t0, int rem, double v0, double v1,
+                                          double &a0, double &a1) {
+    const uint32_t ent[4] = {e.x, e.y, e.z, e.w};
+    double2 xv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const double2 *>(xrow + (ent[j] & 0xFFFFu) * NRB);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
+        if (TAIL && j > 0) wgt = j < rem ? wgt : 0.0;
+        a0 = ::fma(wgt, xv[j].x, a0);
+        a1 = ::fma(wgt, xv[j].y, a1);
+    }
+}
+
+// The products of one row's entries that fall in the current x window, for
+// this lane's pair of right-hand sides: `rec` is the row's (pattern, window)
+// record (count, then the zero-padded entries from word 4), `xrow` the lane's
+// element pair in window row 0, NRB the bytes of a window row.  One 16-byte
+// table read per four entries.
+template <int NRB>
+__device__ __forceinline__ void win_row(const uint4 *rec, const unsigned char *xrow, int t0, double v0, double v1,
+                                        double &a0, double &a1) {
+    const int cnt = static_cast<int>(rec[0].x);
+    int k0 = 0;
+    for (; k0 + 4 <= cnt; k0 += 4) win_group<NRB, false>(rec[1 + (k0 >> 2)], xrow, t0, 4, v0, v1, a0, a1);
+    if (k0 < cnt) win_group<NRB, true>(rec[1 + (k0 >> 2)], xrow, t0, cnt - k0, v0, v1, a0, a1);
+}
+
 // nrhs = 2 * LPR FP64 right-hand sides, row-interleaved and unpadded.  A block
 // owns kWinRows rows; for each x window in turn it copies the window's rows
 // of the block (all nrhs values of a row: 16 * LPR bytes, a contiguous range
 // of memory) into LDS, then every row adds the products of its entries that
-// fall in that window.  Only one window is held at a time, so whole rows fit.
-// A group of LPR lanes serves a row, each lane a pair of right-hand sides
-// (16-byte LDS reads); per pair two sums are kept, one per value-table entry,
-// and scaled once at the end.
+// fall in that window (win_row).  Only one window is held at a time, so whole
+// rows fit.  A group of LPR lanes serves a row, each lane a pair of
+// right-hand sides (16-byte LDS reads).
 template <int LPR>
 __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const double *__restrict__ X,
                                                            double *__restrict__ Y) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NR = 2 * LPR;          // right-hand sides
     constexpr int PASSES = kWinRows / (kBlock / LPR);
-    constexpr int ST = kWinMaxPw + 1;    // table words per (pattern, window)
     const int NW = a.n_win;
     double *xs = reinterpret_cast<double *>(smem);
-    uint32_t *tab_s = reinterpret_cast<uint32_t *>(smem + a.lds_x_bytes);
+    const uint4 *tab_s = reinterpret_cast<const uint4 *>(smem + a.lds_x_bytes);
     const int64_t r0 = xcd_tile(blockIdx.x, gridDim.x, a.n_xcd) * kWinRows;
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     const int lr = threadIdx.x / LPR;           // row within a pass
@@ -899,18 +931,15 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
         t0v[ps] = a.K >= 2 ? static_cast<int>(a.T[rc]) : 255;
     }
     {
-        const int nt = a.P * NW * ST;
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.reg_tab);
-        for (int e = threadIdx.x; e < nt; e += kBlock) tab_s[e] = src[e];
+        const int n16 = a.P * NW * (kWinSt / 4);
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.reg_tab);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
+        for (int e = threadIdx.x; e < n16; e += kBlock) dst[e] = src[e];
     }
-    double s0[PASSES][2], s1[PASSES][2];
+    const double v0 = a.V[0], v1 = a.V[a.K >= 2 ? 1 : 0];
+    double acc[PASSES][2];
 #pragma unroll
-    for (int ps = 0; ps < PASSES; ++ps)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            s0[ps][v] = 0.0;
-            s1[ps][v] = 0.0;
-        }
+    for (int ps = 0; ps < PASSES; ++ps) acc[ps][0] = acc[ps][1] = 0.0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int w = 0; w < NW; ++w) {
         if (w > 0) __syncthreads();  // every row is done with the previous window
@@ -939,31 +968,16 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
             const int rel = ps * (kBlock / LPR) + lr;
             const int64_t row = r0 + rel;
             if (row >= a.n_rows || idv[ps] == esc) continue;
-            const uint32_t *t = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * ST;
-            const int cnt = static_cast<int>(t[0]);
-            for (int k = 0; k < cnt; ++k) {
-                const uint32_t ent = t[1 + k];
-                const int off = static_cast<int>(ent & 0xFFFFu);
-                const int kc = static_cast<int>(ent >> 16);
-                const double2 xv = *reinterpret_cast<const double2 *>(xs + (rel + off) * NR + rp);
-                if (kc < t0v[ps]) {
-                    s0[ps][0] += xv.x;
-                    s0[ps][1] += xv.y;
-                } else {
-                    s1[ps][0] += xv.x;
-                    s1[ps][1] += xv.y;
-                }
-            }
+            const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
+            win_row<NR * 8>(rec, reinterpret_cast<const unsigned char *>(xs + rel * NR + rp), t0v[ps], v0, v1,
+                            acc[ps][0], acc[ps][1]);
         }
     }
-    const double v0 = a.V[0], v1 = a.V[a.K >= 2 ? 1 : 0];
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
         const int64_t row = r0 + ps * (kBlock / LPR) + lr;
         if (row >= a.n_rows || idv[ps] == esc) continue;
-        const double y0 = ::fma(v1, s1[ps][0], v0 * s0[ps][0]);
-        const double y1 = ::fma(v1, s1[ps][1], v0 * s0[ps][1]);
-        *reinterpret_cast<double2 *>(Y + row * NR + rp) = double2{y0, y1};
+        *reinterpret_cast<double2 *>(Y + row * NR + rp) = double2{acc[ps][0], acc[ps][1]};
     }
 }
 
@@ -1206,7 +1220,7 @@ bool launch_block_win(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     if (!(nrhs == 2 || nrhs == 4 || nrhs == 8) || ldx != nrhs || ldy != nrhs) return false;
     if (reinterpret_cast<uintptr_t>(X) % 16 || reinterpret_cast<uintptr_t>(Y) % 16) return false;
     const int64_t xb = static_cast<int64_t>(p.bw_maxlen) * nrhs * 8;
-    const int64_t tb = static_cast<int64_t>(M->P) * p.bw_nw * (kWinMaxPw + 1) * 4;
+    const int64_t tb = static_cast<int64_t>(M->P) * p.bw_nw * kWinSt * 4;
     if (xb + tb > kLdsBudgetBytes) return false;
     a.n_win = p.bw_nw;
     for (int w = 0; w < p.bw_nw; ++w) {
@@ -1488,7 +1502,7 @@ static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p, const std::se
         maxlen = std::max(maxlen, len[w]);
     }
     const int W = M->width;
-    const int stride = kWinMaxPw + 1;
+    const int stride = kWinSt;
     std::vector<uint32_t> tab(static_cast<size_t>(M->P) * NW * stride, 0);
     for (int q = 0; q < M->P; ++q) {
         const int L = M->h_pat_len[q];
@@ -1498,7 +1512,7 @@ static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p, const std::se
             while (!(d >= win[w].first && d <= win[w].second)) ++w;
             uint32_t *t = tab.data() + (static_cast<size_t>(q) * NW + w) * stride;
             if (t[0] >= static_cast<uint32_t>(kWinMaxPw)) return;  // too many entries in one window
-            t[1 + t[0]] = (static_cast<uint32_t>(k) << 16) | static_cast<uint32_t>(d - lo[w]);
+            t[4 + t[0]] = (static_cast<uint32_t>(k) << 16) | static_cast<uint32_t>(d - lo[w]);
             ++t[0];
         }
     }

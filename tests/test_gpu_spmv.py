@@ -231,6 +231,31 @@ def test_block_lds_kernels(mode, grid, nrhs, ld):
         assert np.all(yb[:, nrhs:].cpu().numpy() == 5.0)
 
 
+@pytest.mark.parametrize("mode", [3, 2, 1, 0])
+def test_block_spmv_scattered_two_value_dictionary(mode):
+    """A 27-point structure whose values are drawn per entry from {-1, 3.5}
+    (seeded): K = 2 with the V[1] entries anywhere in a row, so within one
+    pattern the split point T changes from row to row and the V[1] entries of
+    a window are not the same ones from row to row.  Every block kernel (and
+    the single-vector kernels) must weight each product by its own entry."""
+    say("case: block scattered dictionary", mode)
+    torch = torch_mod()
+    A = stencil27(33, 29, 17)
+    rng = np.random.default_rng(11)
+    A.val[:] = np.where(rng.random(A.nnz) < 0.3, 3.5, -1.0)
+    M = compress(A, fmt="DIT")
+    assert M.info()["K"] == 2
+    M.set_block_mode(mode)
+    for nrhs in (2, 8):
+        X = np.stack([uniform_vector(A.n_cols, seed=80 + r) for r in range(nrhs)], axis=1)
+        Y = M.spmv_block(torch.from_numpy(X).cuda()).cpu().numpy()
+        Yref = oracle.spmv_block(A, X)
+        for r in range(nrhs):
+            assert max_rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14
+    x = uniform_vector(A.n_cols, seed=90)
+    assert max_rel_err(A, x, gpu_spmv(M, x), oracle.spmv(A, x)) <= 1e-14
+
+
 def test_autotuner_single_and_block():
     """The autotuner's choices (single vector: rows per block / staging; block:
     lane group or one lane per row) keep every product within the bound."""
