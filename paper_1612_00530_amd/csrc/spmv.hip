@@ -517,8 +517,13 @@ template <class Real, int KK> __device__ __forceinline__ void value_pair(const S
     }
 }
 
+// With one or two rows per thread a block of the 27-point stencil takes about
+// 23 KB of LDS (three plane windows, the zero window, the table), so seven
+// blocks fit a CU; asking for seven waves per SIMD keeps registers from being
+// the tighter limit (at most 72 VGPRs instead of 80, no spills).
 template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
-__global__ __launch_bounds__(kBlock) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
+__global__ __launch_bounds__(kBlock, RPT <= 2 ? 7 : 1) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x,
+                                                                      Real *__restrict__ y) {
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
         emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
