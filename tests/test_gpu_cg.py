@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synthetic import stencil27, stencil27_irregular, uniform_vector
+from synthetic import batched_grids, stencil27, stencil27_irregular, uniform_vector
 
 from gpu_util import compress, lib, torch_mod
 
@@ -104,6 +104,35 @@ def test_cg_odd_size_and_unaligned_vectors(offset):
         assert np.abs(x - 1).max() < 1e-7
         rest = xbuf.cpu().numpy()
         assert rest[0 if offset else A.n_rows] == 7.0  # the element outside the view is untouched
+
+
+def test_cg_full_size_192():
+    """The 192^3 stencil (7.08 M rows, 189 M nnz) with b = A*1, in the launch
+    configuration the benchmark times (FP64 and FP32 SpMV tuned): the FP64
+    solve takes the oracle's iteration count within 2, and FP64 and mixed
+    precision both reach 1e-10 in the oracle's own residual with x close to 1."""
+    say("case: cg full size 192^3")
+    torch = torch_mod()
+    P = lib()
+    A = stencil27(192, 192, 192)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    M = compress(A, fmt="DIT")
+    M.tune(torch.float64)
+    M.tune(torch.float32)
+    bt = torch.from_numpy(b).cuda()
+    say("  oracle cg")
+    _, st_ref, it_ref, _ = oracle.cg(A, b)
+    assert st_ref == 0
+    for mode in (0, 1):
+        say("  gpu cg mode", mode)
+        st, xs, stats = P.cg_solve(M, bt, mode=mode)
+        torch.cuda.synchronize()
+        x = xs[0].cpu().numpy()
+        assert st == 0 and stats[0]["status"] == 0
+        if mode == 0:
+            assert abs(stats[0]["iters"] - it_ref) <= 2
+        assert oracle.relres(A, b, x) <= 1.5e-10
+        assert np.abs(x - 1).max() < 1e-6
 
 
 def test_fp64_cg_random_rhs_irregular():
@@ -244,6 +273,29 @@ def test_batched_window_phased_spmv(nrhs):
         for r in range(nrhs):
             assert s_graph[s * nrhs + r]["status"] == 0
             assert oracle.relres(A, B[:, r], X[:, r]) <= 1.5e-10
+
+
+def test_batched_full_size_64_systems():
+    """The full batched workload: 64 systems with grid sides drawn from 16..96
+    (seed 0), 8 right-hand sides each, in the replayed-graph mode the
+    benchmark times.  Every one of the 512 pairs reaches 1e-10 in the oracle's
+    own residual, and the reported residual agrees with it."""
+    say("case: batched full size")
+    torch = torch_mod()
+    P = lib()
+    grids = batched_grids(64, 16, 96, seed=0)
+    mats, As, bs = batched_case(grids, 8, seed=5)
+    st, xs, stats = P.cg_solve(mats, bs, nrhs=8, batched=2, max_iter=5000)
+    torch.cuda.synchronize()
+    assert st == 0
+    for s, A in enumerate(As):
+        X = xs[s].cpu().numpy()
+        B = bs[s].cpu().numpy()
+        for r in range(8):
+            q = stats[s * 8 + r]
+            rel = oracle.relres(A, B[:, r], X[:, r])
+            assert q["status"] == 0 and rel <= 1.5e-10
+            assert abs(q["relres_true"] - rel) <= 1e-12
 
 
 def test_batched_failures_are_per_pair():
