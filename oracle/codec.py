@@ -18,6 +18,12 @@ It follows the steps of Section V in the paper's order:
    Table" scheme (DIT); the sample code in the paper decodes it per row with
    ``j = i + columnDiff[type][idx]`` and value ``V[valueIdx]`` for
    ``idx < valueIdxEnd[i][valueIdx]``.
+6. The further step the paper proposes at the end of the section: register
+   the element values in the table as well, so that a row stores nothing but
+   its ID (``encode_dit(..., fold_values=True)``, format "DITV").  Here the
+   registered key is the displacement sequence together with T_i (which, with
+   V fixed, determines the value of every coded entry); raw values stay per
+   row as in DIT.
 
 Readings of points the paper leaves open (each is listed in the design notes):
 
@@ -33,8 +39,9 @@ Readings of points the paper leaves open (each is listed in the design notes):
   ``k_max`` most frequent such values are kept (ties: totalOrder).  All other
   entries are "raw": ordered after the coded ones, by column, and stored as
   FP64 values per row.
-* A pattern is the ordered displacement sequence (length included).  Pattern
-  IDs are assigned by first occurrence (lowest row).  Rows whose pattern is
+* A pattern is the ordered displacement sequence (length included); with the
+  values registered too it is that sequence plus T_i.  Pattern IDs are
+  assigned by first occurrence (lowest row).  Rows whose pattern is
   used by fewer than ``min_pattern_rows`` rows, falls outside the ``p_max``
   most frequent patterns (ties: first occurrence), or whose length exceeds
   255 (T is one byte) are escape rows, kept as plain CSR.
@@ -135,7 +142,7 @@ def canonicalize(A, k_max: int = 15, V=None) -> Canonical:
 class Encoding:
     """Logical content of a DT or DIT encoding (layout-independent)."""
 
-    fmt: str  # "DT" or "DIT"
+    fmt: str  # "DT", "DIT" or "DITV" (DIT with the values registered in the table)
     n_rows: int
     n_cols: int
     V: np.ndarray  # float64 [K]
@@ -155,6 +162,8 @@ class Encoding:
     pat_off: np.ndarray = field(default=None)  # int64, displacements in canonical order
     pat_rows: np.ndarray = field(default=None)  # int64 [P], rows using each pattern
     pat_first: np.ndarray = field(default=None)  # int64 [P], first row using it
+    # DITV only: T of each pattern (a row's T is its pattern's; the row stores no T)
+    pat_T: np.ndarray = field(default=None)  # int64 [P, K]
 
     @property
     def K(self) -> int:
@@ -200,10 +209,17 @@ def encode_dt(A, k_max: int = 15) -> Encoding:
                     S_ptr=S_ptr, S=can.S[sel].copy())
 
 
-def encode_dit(A, k_max: int = 15, p_max: int = 65535, min_pattern_rows: int = 2) -> Encoding:
-    """The "Data+Index Table" scheme: V, per-row pattern ID and T_i, pattern table."""
+def encode_dit(A, k_max: int = 15, p_max: int = 65535, min_pattern_rows: int = 2,
+               fold_values: bool = False) -> Encoding:
+    """The "Data+Index Table" scheme: V, per-row pattern ID and T_i, pattern table.
+
+    With ``fold_values`` the key registered per row is (displacements, T_i) and
+    the row keeps only the ID (format "DITV"); ``T`` of the result is then the
+    pattern's T repeated per row, for decoding, and is not part of the stream.
+    """
     can = canonicalize(A, k_max)
     n = can.n_rows
+    K = can.K
     rp = can.row_ptr
     lens = np.diff(rp)
     row_of = _row_of(rp)
@@ -211,22 +227,25 @@ def encode_dit(A, k_max: int = 15, p_max: int = 65535, min_pattern_rows: int = 2
     short = lens <= MAX_PATTERN_LEN
     short_rows = np.flatnonzero(short)
     W = int(lens[short].max()) if short_rows.size else 0
-    # step 5: one row of M per row = (length, displacements..., 0 padding)
-    M = np.zeros((short_rows.size, W + 1), dtype=np.int64)
+    # step 5: one row of M per row = (length, [T_i,] displacements..., 0 padding)
+    H = 1 + (K if fold_values else 0)
+    M = np.zeros((short_rows.size, W + H), dtype=np.int64)
     M[:, 0] = lens[short_rows]
+    if fold_values and K:
+        M[:, 1:H] = can.T[short_rows]
     if W > 0:
         ent = short[row_of]
         pos = np.arange(rp[-1], dtype=np.int64) - rp[row_of]
         slot = np.full(n, -1, dtype=np.int64)
         slot[short_rows] = np.arange(short_rows.size)
-        M[slot[row_of[ent]], 1 + pos[ent]] = disp[ent]
+        M[slot[row_of[ent]], H + pos[ent]] = disp[ent]
     if short_rows.size:
         uniq, first, inv, cnt = np.unique(M, axis=0, return_index=True, return_inverse=True,
                                           return_counts=True)
         inv = inv.reshape(-1)
         first_row = short_rows[first]
     else:
-        uniq = np.zeros((0, W + 1), dtype=np.int64)
+        uniq = np.zeros((0, W + H), dtype=np.int64)
         first_row = np.zeros(0, dtype=np.int64)
         inv = np.zeros(0, dtype=np.int64)
         cnt = np.zeros(0, dtype=np.int64)
@@ -243,14 +262,16 @@ def encode_dit(A, k_max: int = 15, p_max: int = 65535, min_pattern_rows: int = 2
     plen = uniq[kept, 0]
     pat_ptr = np.zeros(kept.size + 1, dtype=np.int64)
     np.cumsum(plen, out=pat_ptr[1:])
-    pat_off = np.concatenate([uniq[u, 1:1 + uniq[u, 0]] for u in kept]) if kept.size else \
+    pat_off = np.concatenate([uniq[u, H:H + uniq[u, 0]] for u in kept]) if kept.size else \
         np.zeros(0, dtype=np.int64)
     T = np.where(esc[:, None], 0, can.T)
     raw_ptr, raw = _raw_stream(can, ~esc)
     er, ep, ec, ev = _escape_csr(A, esc)
-    return Encoding("DIT", n, can.n_cols, can.V, T, raw_ptr, raw, er, ep, ec, ev,
+    pat_T = uniq[kept, 1:H].astype(np.int64) if fold_values else None
+    return Encoding("DITV" if fold_values else "DIT", n, can.n_cols, can.V, T, raw_ptr, raw, er, ep, ec, ev,
                     ids=ids, pat_ptr=pat_ptr, pat_off=pat_off.astype(np.int64),
-                    pat_rows=cnt[kept].astype(np.int64), pat_first=first_row[kept].astype(np.int64))
+                    pat_rows=cnt[kept].astype(np.int64), pat_first=first_row[kept].astype(np.int64),
+                    pat_T=pat_T)
 
 
 def _entries(enc: Encoding):
@@ -269,7 +290,8 @@ def _entries(enc: Encoding):
         cols = enc.S.astype(np.int64)
     else:
         cols = rows + enc.pat_off[enc.pat_ptr[enc.ids[rows]] + k]
-    Tr = enc.T[rows]  # [m, K]
+    # DITV: T_i comes from the row's pattern, not from a per-row stream
+    Tr = enc.pat_T[enc.ids[rows]] if enc.fmt == "DITV" else enc.T[rows]  # [m, K]
     code = (k[:, None] >= Tr).sum(axis=1) if K else np.zeros(rows.size, dtype=np.int64)
     vals = np.empty(rows.size, dtype=np.float64)
     coded = code < K
@@ -323,15 +345,16 @@ def walk_spmv(enc: Encoding, x) -> np.ndarray:
 
             def col_at(idx, base=base, i=i):
                 return i + int(enc.pat_off[base + idx])
+        Ti = enc.pat_T[int(enc.ids[i])] if enc.fmt == "DITV" else enc.T[i]
         idx = 0
         for c in range(K):
             a = float(enc.V[c])
-            while idx < int(enc.T[i, c]):
+            while idx < int(Ti[c]):
                 s = s + a * float(x[col_at(idx)])
                 idx += 1
         r0 = int(enc.raw_ptr[i])
         while idx < length:
-            s = s + float(enc.raw[r0 + idx - (int(enc.T[i, K - 1]) if K else 0)]) * float(x[col_at(idx)])
+            s = s + float(enc.raw[r0 + idx - (int(Ti[K - 1]) if K else 0)]) * float(x[col_at(idx)])
             idx += 1
         y[i] = s
     return y
@@ -343,9 +366,10 @@ def paper_row_bytes(row_len: int, K: int) -> dict:
     """Bytes per row at the paper's widths (4-byte indices, 8-byte values).
 
     ELL: (4 + 8) per element; DT: (len + K) * 4 (S_i and T_i); DIT: one 4-byte
-    type ID plus T_i, (1 + K) * 4 (Section V).
+    type ID plus T_i, (1 + K) * 4; DITV (values registered in the table too):
+    the 4-byte ID alone (Section V).
     """
-    return {"ELL": 12 * row_len, "DT": (row_len + K) * 4, "DIT": 4 * (1 + K)}
+    return {"ELL": 12 * row_len, "DT": (row_len + K) * 4, "DIT": 4 * (1 + K), "DITV": 4}
 
 
 def id_width(P: int) -> int:
@@ -365,8 +389,11 @@ def stream_bytes(enc: Encoding) -> dict:
     table = 8 * K
     if enc.fmt == "DT":
         rows = 4 * int(enc.S.size) + K * n
-    else:
+    elif enc.fmt == "DIT":
         rows = id_width(enc.P) * n + K * n
         table += 4 * int(enc.pat_off.size) + 4 * enc.P
+    else:  # DITV: the row holds its ID only; T_i lives in the table
+        rows = id_width(enc.P) * n
+        table += 4 * int(enc.pat_off.size) + 4 * enc.P + K * enc.P
     return {"rows": rows, "raw": raw, "escape": esc, "table": table,
             "total": rows + raw + esc + table}

@@ -1,7 +1,12 @@
 """Pins of the reference codec (the paper's Section V compression schemes).
 
 * Fig. 1's worked example (V, S, T) from a golden fixture;
-* the paper's bytes per 27-entry row (324 / 116 / 12);
+* the paper's bytes per 27-entry row (324 / 116 / 12, and about 4 once the
+  values are registered in the table too);
+* with the values registered (DITV), the signature count equals a brute-force
+  count of distinct (displacements, codes) row sequences, IDs follow first
+  occurrence, and the stencil gains no patterns (its T_i follows from the
+  displacement pattern);
 * the pattern count of the 27-point stencil, prod(min(n_a, 3)), and the rows
   per pattern, prod({1, n_a - 2, 1});
 * lossless round trip, bit for bit, on random CSR matrices with special values;
@@ -49,7 +54,7 @@ def test_fig1_worked_example():
 def test_section5_row_bytes():
     g = load("section5_row_bytes.json")
     b = codec.paper_row_bytes(g["row_len"], g["value_table_size"])
-    assert (b["ELL"], b["DT"], b["DIT"]) == (g["ELL"], g["DT"], g["DIT"])
+    assert (b["ELL"], b["DT"], b["DIT"], b["DITV"]) == (g["ELL"], g["DT"], g["DIT"], g["DITV"])
 
 
 def test_value_table_of_stencil_is_minus_one_and_26():
@@ -90,6 +95,104 @@ def test_pattern_ids_by_first_occurrence_and_cap():
     top = np.sort(full.pat_rows)[::-1][:5]
     assert sorted(capped.pat_rows.tolist(), reverse=True) == top.tolist()
     assert same_csr(codec.decode(capped), A)
+
+
+@pytest.mark.parametrize("grid", [(16, 16, 16), (5, 4, 3), (1, 3, 4)])
+def test_ditv_of_stencil_keeps_the_dit_patterns(grid):
+    """A stencil row's T_i is fixed by its displacement pattern (the diagonal
+    is the only 26), so registering the values adds no pattern: same IDs, and
+    each pattern's T is (len - 1, len).  The row stream is the 1-byte ID."""
+    A = stencil27(*grid)
+    dit = codec.encode_dit(A, min_pattern_rows=1)
+    ditv = codec.encode_dit(A, min_pattern_rows=1, fold_values=True)
+    assert ditv.fmt == "DITV" and ditv.P == dit.P
+    assert np.array_equal(ditv.ids, dit.ids) and np.array_equal(ditv.pat_off, dit.pat_off)
+    plen = np.diff(ditv.pat_ptr)
+    assert np.array_equal(ditv.pat_T, np.stack([plen - 1, plen], axis=1))
+    assert codec.stream_bytes(ditv)["rows"] == A.n_rows
+    assert same_csr(codec.decode(ditv), A)
+
+
+def _signature_brute_force(A, V):
+    """Per row, the tuple of (code, col - row) in (code, column) order -- the key
+    a row registers when its values go into the table -- from the CSR, in plain
+    Python; code K marks a raw value."""
+    keys = []
+    vb = [np.float64(v).view(np.uint64) for v in V]
+    for i in range(A.n_rows):
+        ent = []
+        for k in range(int(A.row_ptr[i]), int(A.row_ptr[i + 1])):
+            b = np.float64(A.val[k]).view(np.uint64)
+            code = vb.index(b) if b in vb else len(V)
+            ent.append((code, int(A.col[k]) - i))
+        keys.append(tuple(sorted(ent)))
+    return keys
+
+
+def _scattered(p_v1):
+    A = stencil27(6, 5, 4)
+    rng = np.random.default_rng(17)
+    A.val[:] = np.where(rng.random(A.nnz) < p_v1, 3.5, -1.0)
+    return A
+
+
+def _split_moves():
+    """3-point rows whose values ascend with the column, so the (code, column)
+    order is the column order for every row, but the split alternates:
+    (-1, -1, 3.5) on even rows, (-1, 3.5, 3.5) on odd rows."""
+    n = 12
+    cols, vals, rp = [], [], [0]
+    for i in range(n):
+        c = [j for j in (i - 1, i, i + 1) if 0 <= j < n]
+        v = [-1.0, -1.0, 3.5] if i % 2 == 0 else [-1.0, 3.5, 3.5]
+        cols += c
+        vals += v[3 - len(c):] if i == 0 else v[:len(c)]
+        rp.append(len(cols))
+    return CSR(n, n, np.array(rp), np.array(cols, dtype=np.int32), np.array(vals))
+
+
+@pytest.mark.parametrize("make", [lambda: _scattered(0.0), lambda: _scattered(0.3), lambda: _scattered(0.5),
+                                  _split_moves])
+def test_ditv_signatures_brute_force(make):
+    """Values from {-1, 3.5}: scattered per entry on a 27-point structure, or
+    ascending along 3-point rows with a split that alternates between rows.
+    The DITV pattern count is the number of distinct brute-force signatures,
+    rows with equal signatures share an ID, IDs follow first occurrence,
+    DIT's count is that of the displacement sequences (in (code, column)
+    order) alone, and both decode to A."""
+    A = make()
+    rng = np.random.default_rng(18)
+    ditv = codec.encode_dit(A, min_pattern_rows=1, fold_values=True)
+    dit = codec.encode_dit(A, min_pattern_rows=1)
+    keys = _signature_brute_force(A, ditv.V)
+    first = {}
+    for i, k in enumerate(keys):
+        first.setdefault(k, i)
+    assert ditv.P == len(first)
+    order = sorted(first.values())
+    expect = [order.index(first[k]) for k in keys]
+    assert ditv.ids.tolist() == expect
+    assert dit.P == len({tuple(d for _, d in k) for k in keys})  # DIT: the ordered displacements
+    assert ditv.P >= dit.P
+    if make is _split_moves:  # same displacement sequence, different T: DITV splits the pattern
+        assert ditv.P > dit.P
+    for enc in (dit, ditv):
+        assert same_csr(codec.decode(enc), A)
+    x = rng.integers(-50, 50, A.n_cols).astype(np.float64)
+    assert np.array_equal(codec.walk_spmv(ditv, x), oracle.spmv(A, x))
+
+
+def test_ditv_folded_table_decides_the_values():
+    """Decoding a DITV encoding takes T from the pattern table: changing a
+    pattern's registered T changes the decoded values, changing the per-row
+    T (not part of the stream) does not."""
+    A = stencil27(5, 5, 5)
+    enc = codec.encode_dit(A, min_pattern_rows=1, fold_values=True)
+    enc.T = np.zeros_like(enc.T)
+    assert same_csr(codec.decode(enc), A)
+    enc.pat_T = enc.pat_T.copy()
+    enc.pat_T[0, 0] -= 1
+    assert not same_csr(codec.decode(enc), A)
 
 
 def test_paper_width_bytes_at_104():
@@ -133,7 +236,8 @@ def random_csr(draw):
 @given(random_csr(), st.integers(0, 4), st.integers(1, 3))
 def test_roundtrip_random(A, k_max, min_rows):
     for enc in (codec.encode_dt(A, k_max=k_max),
-                codec.encode_dit(A, k_max=k_max, min_pattern_rows=min_rows)):
+                codec.encode_dit(A, k_max=k_max, min_pattern_rows=min_rows),
+                codec.encode_dit(A, k_max=k_max, min_pattern_rows=min_rows, fold_values=True)):
         assert same_csr(codec.decode(enc), A)
 
 
@@ -178,7 +282,7 @@ def test_walk_spmv_exact_on_integer_data(make):
     A = make()
     x = np.random.default_rng(3).integers(-1000, 1000, A.n_cols).astype(np.float64)
     y = oracle.spmv(A, x)
-    for enc in (codec.encode_dt(A), codec.encode_dit(A)):
+    for enc in (codec.encode_dt(A), codec.encode_dit(A), codec.encode_dit(A, fold_values=True)):
         assert np.array_equal(codec.walk_spmv(enc, x), y)
 
 
