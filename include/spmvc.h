@@ -14,7 +14,12 @@
  *   SPMVC_FMT_DIT  "Data+Index Table": columns replaced by displacements from
  *                  the diagonal, each row's displacement sequence registered in
  *                  a pattern table; a row stores only its pattern ID and T_i
- *                  (Section V, index-compression paragraph and sample code).
+ *                  (Section V, index-compression paragraph and sample code);
+ *   SPMVC_FMT_DITV DIT with the element values registered in the table as
+ *                  well (the further step Section V proposes at the end of
+ *                  that paragraph): the registered key is the displacement
+ *                  sequence together with T_i, so a row stores only its ID;
+ *                  raw (non-dictionary) values stay per row as in DIT.
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers unless the comment says "host".
@@ -53,7 +58,8 @@ typedef enum { SPMVC_F64 = 0, SPMVC_F32 = 1 } spmvc_dtype;
 typedef enum {
     SPMVC_FMT_ELL = 0,
     SPMVC_FMT_DT = 1,
-    SPMVC_FMT_DIT = 2
+    SPMVC_FMT_DIT = 2,
+    SPMVC_FMT_DITV = 3
 } spmvc_format;
 
 typedef struct spmvc_matrix_s *spmvc_matrix; /* opaque, owned by the library */
@@ -79,8 +85,9 @@ typedef struct {
  * totalOrder on the bit pattern (-0.0 and +0.0 distinct, NaN payloads kept).
  * Entries whose value is not in V are "raw": they follow the coded entries,
  * by column, and keep their FP64 value.  T_i stores exclusive run ends.
- * Pattern IDs follow first occurrence (lowest row).  Escape rows -- rows longer
- * than 255, and for DIT rows whose pattern is used by fewer than
+ * Pattern IDs follow first occurrence (lowest row); for DITV a pattern is the
+ * pair (displacement sequence, T_i) and the rows keep no T.  Escape rows --
+ * rows longer than 255, and for DIT/DITV rows whose pattern is used by fewer than
  * min_pattern_rows rows or falls outside the p_max most frequent -- are kept
  * as plain CSR.  The encoding is deterministic.
  *
@@ -167,7 +174,7 @@ spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx,
 typedef struct {
     int32_t fmt;           /* spmvc_format                                                */
     int32_t K;             /* value-table entries                                         */
-    int32_t P;             /* pattern-table entries (DIT)                                 */
+    int32_t P;             /* pattern-table entries (DIT, DITV)                           */
     int32_t id_bytes;      /* width of a pattern ID (DIT): 1, 2 or 4                      */
     int32_t width;         /* ELL/DT slots per row, DIT longest pattern                   */
     int32_t max_raw;       /* most raw entries in one row                                 */
@@ -175,7 +182,8 @@ typedef struct {
     int64_t n_escape_rows, n_escape_nnz, n_raw;
     int64_t bytes_stream;  /* bytes one FP64 spmv must read for the matrix (all arrays)   */
     int64_t bytes_ell;     /* the same matrix as FP64 ELL: 12 bytes per slot              */
-    int64_t bytes_paper;   /* at the paper's widths: ELL 12/slot, DT 4*(len+K), DIT 4*(1+K) per row */
+    int64_t bytes_paper;   /* at the paper's widths: ELL 12/slot, DT 4*(len+K), DIT 4*(1+K),
+                              DITV 4 per row */
     int32_t lds_windows;   /* x windows staged in LDS by the FP64 DIT kernel (0 = direct gather) */
     int32_t rows_per_block; /* rows per block of the FP64 spmv                             */
     double V[15];          /* the value table (first K entries)                           */
@@ -195,7 +203,8 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info /* host */);
  * blocking).  Layouts: ELL_VAL f64 / ELL_COL i32 / DT_S i32 are
  * [width][n_pad] column-major (n_pad = n_rows rounded up to 64, padding
  * column -1); IDS [n_pad] of id_bytes each (all-ones = escape row); T u8
- * [K][n_pad]; PAT_OFF i32 [P][width] displacements, PAT_LEN u8 [P]; RAW f64 in
+ * [K][n_pad] (empty for DITV); PAT_OFF i32 [P][width] displacements, PAT_LEN
+ * u8 [P]; PAT_T u8 [P][K] (DITV: the T of each pattern); RAW f64 in
  * slices of 64 rows, slice s at RAW_SLICE[s] (int64, elements), raw entry k
  * of row 64s+l at RAW[RAW_SLICE[s] + 64k + l]; ESC_ROWS i64, ESC_PTR i64
  * [n_esc+1], ESC_COL i32, ESC_VAL f64.
@@ -204,7 +213,7 @@ typedef enum {
     SPMVC_ARR_ELL_VAL = 0, SPMVC_ARR_ELL_COL = 1, SPMVC_ARR_DT_S = 2, SPMVC_ARR_IDS = 3,
     SPMVC_ARR_T = 4, SPMVC_ARR_PAT_OFF = 5, SPMVC_ARR_PAT_LEN = 6, SPMVC_ARR_RAW = 7,
     SPMVC_ARR_RAW_SLICE = 8, SPMVC_ARR_ESC_ROWS = 9, SPMVC_ARR_ESC_PTR = 10,
-    SPMVC_ARR_ESC_COL = 11, SPMVC_ARR_ESC_VAL = 12, SPMVC_ARR_V = 13
+    SPMVC_ARR_ESC_COL = 11, SPMVC_ARR_ESC_VAL = 12, SPMVC_ARR_V = 13, SPMVC_ARR_PAT_T = 14
 } spmvc_array_id;
 
 spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *bytes, void *stream);

@@ -14,19 +14,20 @@ import os
 
 __all__ = [
     "load", "compress", "Matrix", "cg_solve", "SpmvcError",
-    "FMT_ELL", "FMT_DT", "FMT_DIT", "F64", "F32",
+    "FMT_ELL", "FMT_DT", "FMT_DIT", "FMT_DITV", "F64", "F32",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspmvc.so")
 
-FMT_ELL, FMT_DT, FMT_DIT = 0, 1, 2
+FMT_ELL, FMT_DT, FMT_DIT, FMT_DITV = 0, 1, 2, 3
 F64, F32 = 0, 1
-_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT}
+_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT, "DITV": FMT_DITV}
 
 ARR = {
     "ELL_VAL": 0, "ELL_COL": 1, "DT_S": 2, "IDS": 3, "T": 4, "PAT_OFF": 5, "PAT_LEN": 6,
     "RAW": 7, "RAW_SLICE": 8, "ESC_ROWS": 9, "ESC_PTR": 10, "ESC_COL": 11, "ESC_VAL": 12, "V": 13,
+    "PAT_T": 14,
 }
 
 EXPORTED = [
@@ -178,7 +179,7 @@ class Matrix:
         _check(load().spmv_info(self._h, ctypes.byref(inf)))
         d = {f: getattr(inf, f) for f, _ in Info._fields_ if f != "V"}
         d["V"] = [inf.V[i] for i in range(inf.K)]
-        d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT"}[inf.fmt]
+        d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT", 3: "DITV"}[inf.fmt]
         names = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg", 3: "k_dit_march"}
         d["kernel_name"] = names[inf.kernel]
         d["kernel_name_f32"] = names[inf.kernel_f32]

@@ -114,7 +114,7 @@ spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const in
         if (nnz > 0 && n_cols == 0) return fail(SPMVC_ERANGE, "entries in a matrix with no columns");
         spmvc_compress_opts o{SPMVC_FMT_DIT, 15, 65535, 2, 1};
         if (opts) o = *opts;
-        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_DIT) return fail(SPMVC_EINVAL, "unknown format");
+        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_DITV) return fail(SPMVC_EINVAL, "unknown format");
         if (o.k_max < 0 || o.k_max > kMaxK) return fail(SPMVC_EINVAL, "k_max must be in 0..15");
         if (o.p_max < 1 || o.p_max > 0x7FFFFFFE) return fail(SPMVC_EINVAL, "p_max must be in 1..2^31-2");
         if (o.min_pattern_rows < 1) return fail(SPMVC_EINVAL, "min_pattern_rows must be >= 1");
@@ -205,7 +205,7 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
     return guarded([&]() -> spmvc_status {
         if (!A || !info) return fail(SPMVC_EINVAL, "null argument");
         spmvc_info r{};
-        r.fmt = A->fmt;
+        r.fmt = A->fold ? SPMVC_FMT_DITV : A->fmt;
         r.K = A->K;
         r.P = A->P;
         r.id_bytes = A->id_bytes;
@@ -231,8 +231,10 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
         else if (A->fmt == SPMVC_FMT_DT)
             r.bytes_paper = 4 * (A->nnz - A->n_esc_nnz) + k4 * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz +
                             8 * A->n_raw;
-        else
+        else if (!A->fold)
             r.bytes_paper = (4 + k4) * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
+        else  // DITV: the 4-byte ID alone
+            r.bytes_paper = 4 * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
         r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode[SPMVC_F64] >= 1) ? A->plan[SPMVC_F64].n_win : 0;
         r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan[SPMVC_F64].rows : kBlock;
         for (int c = 0; c < A->K; ++c) r.V[c] = A->V[c];
@@ -256,6 +258,7 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
         case SPMVC_ARR_T: b = &A->T; break;
         case SPMVC_ARR_PAT_OFF: b = &A->pat_off; break;
         case SPMVC_ARR_PAT_LEN: b = &A->pat_len; break;
+        case SPMVC_ARR_PAT_T: b = &A->pat_T; break;
         case SPMVC_ARR_RAW: b = &A->raw; break;
         case SPMVC_ARR_RAW_SLICE: b = &A->raw_slice; break;
         case SPMVC_ARR_ESC_ROWS: b = &A->esc_rows; break;

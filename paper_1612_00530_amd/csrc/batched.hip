@@ -41,6 +41,7 @@ struct SysDesc {
     int32_t ntiles, K, width, id_bytes, P;
     const void *ids;
     const uint8_t *T;
+    const uint8_t *pat_T;  // DITV: T of each pattern [P][K] (no per-row T), else null
     const int32_t *pat_off;
     const uint8_t *pat_len;
     const int64_t *esc_rows, *esc_ptr;
@@ -176,6 +177,11 @@ __device__ __forceinline__ void gather_row(const int32_t *__restrict__ pat, int 
 // last whole round of chunks keep their own index.
 constexpr int kChunk = 32;
 
+// T_i[c] of a non-escape row of system d: its own T byte, or for DITV its pattern's.
+__device__ __forceinline__ int sys_T(const SysDesc &d, int c, int64_t lrow, uint32_t id) {
+    return d.pat_T ? d.pat_T[static_cast<int64_t>(id) * d.K + c] : d.T[static_cast<int64_t>(c) * d.n_pad + lrow];
+}
+
 __device__ __forceinline__ int chunk_tile(unsigned bid, unsigned nb, int n_xcd) {
     const unsigned round = static_cast<unsigned>(kChunk) * n_xcd;
     const unsigned full = nb / round * round;
@@ -208,8 +214,9 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
         int64_t lrow = lbase + pass * (kT / LPR);
         lrow = lrow < d.n ? lrow : d.n - 1;
         idv[pass] = load_id(d.ids, d.id_bytes, lrow);
-        lenv[pass] = d.K > 0 ? static_cast<int>(d.T[static_cast<int64_t>(d.K - 1) * d.n_pad + lrow]) : 0;
-        t0v[pass] = d.K > 1 ? static_cast<int>(d.T[lrow]) : lenv[pass];
+        const uint32_t idc = idv[pass] == esc ? 0u : idv[pass];  // escape rows: any valid pattern
+        lenv[pass] = d.K > 0 ? sys_T(d, d.K - 1, lrow, idc) : 0;
+        t0v[pass] = d.K > 1 ? sys_T(d, 0, lrow, idc) : lenv[pass];
     }
     // the system's pattern table, copied to LDS once per block
     const int32_t *ptab = d.pat_off;
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
         int64_t lrow = r0 + ps * (kT / LPR) + lr;
         lrow = lrow < d.n ? lrow : d.n - 1;
         idv[ps] = load_id(d.ids, d.id_bytes, lrow);
-        t0v[ps] = d.K >= 2 ? static_cast<int>(d.T[lrow]) : 255;
+        t0v[ps] = d.K < 2 ? 255 : sys_T(d, 0, lrow, idv[ps] == esc ? 0u : idv[ps]);
     }
     {
         const int n16 = d.P * NW * (kWinSt / 4);
@@ -780,6 +787,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         d.id_bytes = M->id_bytes;
         d.ids = M->ids.p;
         d.T = M->T.as<uint8_t>();
+        d.pat_T = M->fold ? M->pat_T.as<uint8_t>() : nullptr;
         d.pat_off = M->pat_off.as<int32_t>();
         d.pat_len = M->pat_len.as<uint8_t>();
         d.esc_rows = M->esc_rows.as<int64_t>();

@@ -282,6 +282,7 @@ struct RowArgs {
     const int32_t *col;
     const double *val;
     VTab v;
+    int fold;  // DITV: a pattern is (displacement sequence, T_i)
 };
 
 __global__ void k_canon(RowArgs a, uint8_t *T, int32_t *nraw, uint64_t *hash, uint8_t *is_long) {
@@ -309,6 +310,8 @@ __global__ void k_canon(RowArgs a, uint8_t *T, int32_t *nraw, uint64_t *hash, ui
     }
     const int coded = a.v.K ? T[(a.v.K - 1) * a.n_pad + i] : 0;
     nraw[i] = static_cast<int32_t>(len) - coded;
+    if (a.fold)  // the registered key includes T_i (with V fixed: the values)
+        for (int c = 0; c < a.v.K; ++c) h = seq_hash_step(h, 0x40000000 + T[c * a.n_pad + i]);
     hash[i] = seq_hash_final(h, len);
 }
 
@@ -388,7 +391,7 @@ __global__ void k_pattern_lookup(RowArgs a, GTable t, const uint64_t *hash, cons
             return;
         }
         if (!hx) break;
-        if (static_cast<int64_t>(cx) - i != static_cast<int64_t>(cy) - rep) {
+        if (static_cast<int64_t>(cx) - i != static_cast<int64_t>(cy) - rep || (a.fold && kx != ky)) {
             atomicOr(t.flags, kFlagCollision);
             return;
         }
@@ -454,7 +457,7 @@ __global__ void k_write_ids(const int64_t *rowslot, const uint8_t *keep, const i
 // Pattern table row p = canonical displacement sequence of the pattern's first row.
 __global__ void k_write_patterns(RowArgs a, const int64_t *rowslot, const int64_t *minidx,
                                  const uint8_t *keep, const int64_t *slot_id, int width,
-                                 int32_t *pat_off, uint8_t *pat_len) {
+                                 int32_t *pat_off, uint8_t *pat_len, const uint8_t *T, uint8_t *pat_T) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_rows) return;
     const int64_t s = rowslot[i];
@@ -469,6 +472,8 @@ __global__ void k_write_patterns(RowArgs a, const int64_t *rowslot, const int64_
         ++k;
     }
     pat_len[p] = static_cast<uint8_t>(k);
+    if (pat_T)
+        for (int cc = 0; cc < a.v.K; ++cc) pat_T[p * a.v.K + cc] = T[cc * a.n_pad + i];
 }
 
 // Escape rows (long rows for ELL/DT; plus unkept patterns for DIT).
@@ -588,6 +593,7 @@ struct DecArgs {
     int fmt, K, width, id_bytes;
     const double *V;
     const uint8_t *T;
+    const uint8_t *pat_T;  // DITV: T of each pattern [P][K]; T is then unused
     const void *ids;
     const int32_t *pat_off;
     const uint8_t *pat_len;
@@ -663,10 +669,13 @@ __global__ void k_dec_fill(DecArgs a, const int64_t *out_rp, int32_t *out_col, d
     // DT / DIT: canonical order, then sort by column (insertion sort, <= 255 entries)
     const uint32_t id = a.fmt == SPMVC_FMT_DIT ? dec_id(a, i) : 0;
     const int64_t slice_base = a.raw_slice ? a.raw_slice[i / kSlice] + (i % kSlice) : 0;
-    const int coded_end = a.K ? a.T[(a.K - 1) * a.n_pad + i] : 0;
+    // T_i: the row's own (DT, DIT) or its pattern's (DITV)
+    const uint8_t *Ti = a.pat_T ? a.pat_T + static_cast<int64_t>(id) * a.K : a.T + i;
+    const int64_t ts = a.pat_T ? 1 : a.n_pad;
+    const int coded_end = a.K ? Ti[(a.K - 1) * ts] : 0;
     int c = 0;
     for (int64_t k = 0; k < n; ++k) {
-        while (c < a.K && k >= a.T[c * a.n_pad + i]) ++c;
+        while (c < a.K && k >= Ti[c * ts]) ++c;
         int32_t colk;
         if (a.fmt == SPMVC_FMT_DIT)
             colk = static_cast<int32_t>(i + a.pat_off[static_cast<int64_t>(id) * a.width + k]);
@@ -704,10 +713,14 @@ constexpr int kT = 256;
 
 // ---------------------------------------------------------------------------------------
 void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const double *val,
-              const spmvc_compress_opts &o, hipStream_t s) {
+              const spmvc_compress_opts &o_in, hipStream_t s) {
     const int64_t n = M->n_rows, nnz = M->nnz;
     M->n_pad = ((n + kSlice - 1) / kSlice) * kSlice;
     const int64_t n_pad = M->n_pad;
+    // DITV is DIT whose pattern key also holds T_i; the row's T is dropped at the end
+    spmvc_compress_opts o = o_in;
+    M->fold = o.fmt == SPMVC_FMT_DITV ? 1 : 0;
+    if (M->fold) o.fmt = SPMVC_FMT_DIT;
     M->fmt = o.fmt;
     M->f32_shadow = o.f32_shadow ? 1 : 0;
 
@@ -727,6 +740,11 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
     if (n == 0) {
         M->K = 0;
         M->P = 0;
+        if (M->fold) {
+            M->pat_T.alloc(16);
+            SPMVC_HIP(hipMemsetAsync(M->pat_T.p, 0, 16, s));
+            SPMVC_HIP(hipStreamSynchronize(s));
+        }
         return;
     }
 
@@ -797,7 +815,7 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
                                  sizeof(float) * kMaxK, hipMemcpyHostToDevice, s));
     }
 
-    RowArgs ra{n, n_pad, rp, col, val, vt};
+    RowArgs ra{n, n_pad, rp, col, val, vt, M->fold};
     const unsigned gr = grid_for(n, kT, 0x7fffffff);
 
     DevBuf esc_b;
@@ -885,6 +903,12 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
             SPMVC_CHECK_LAUNCH();
             const int64_t P = exclusive_scan(isrep.as<int64_t>(), isrep.as<int64_t>(), n, s);
             M->P = static_cast<int32_t>(P);
+            if (M->fold) {
+                // never null for DITV (the kernels tell DITV by it), large enough for
+                // pattern 0's K bytes even when every row escapes
+                M->pat_T.alloc(static_cast<size_t>(std::max<int64_t>(P, 1)) * std::max(vt.K, 1));
+                SPMVC_HIP(hipMemsetAsync(M->pat_T.p, 0, M->pat_T.bytes, s));
+            }
             M->id_bytes = P <= 255 ? 1 : (P <= 65535 ? 2 : 4);
             slot_id.alloc(sizeof(int64_t) * pcap);
             wbuf.alloc(sizeof(int));
@@ -912,8 +936,13 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
                 SPMVC_HIP(hipMemsetAsync(M->pat_off.p, 0, M->pat_off.bytes, s));
                 k_write_patterns<<<gr, kT, 0, s>>>(ra, rowslot.as<int64_t>(), pmin.as<int64_t>(), keep.as<uint8_t>(),
                                                    slot_id.as<int64_t>(), w, M->pat_off.as<int32_t>(),
-                                                   M->pat_len.as<uint8_t>());
+                                                   M->pat_len.as<uint8_t>(), M->T.as<uint8_t>(),
+                                                   vt.K > 0 ? M->pat_T.as<uint8_t>() : nullptr);
                 SPMVC_CHECK_LAUNCH();
+                if (M->fold && vt.K > 0) {
+                    M->h_pat_T.resize(static_cast<size_t>(P) * vt.K);
+                    SPMVC_HIP(hipMemcpyAsync(M->h_pat_T.data(), M->pat_T.p, M->h_pat_T.size(), hipMemcpyDeviceToHost, s));
+                }
                 M->h_pat_off.resize(static_cast<size_t>(P) * w);
                 M->h_pat_len.resize(static_cast<size_t>(P));
                 SPMVC_HIP(hipMemcpyAsync(M->h_pat_off.data(), M->pat_off.p, M->pat_off.bytes, hipMemcpyDeviceToHost, s));
@@ -998,6 +1027,7 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
         SPMVC_CHECK_LAUNCH();
     }
     SPMVC_HIP(hipStreamSynchronize(s));
+    if (M->fold) M->T.release();  // DITV rows keep no T: every kernel reads the pattern's
 }
 
 void decompress(const spmvc_matrix_s *M, int64_t *rp, int32_t *col, double *val, hipStream_t s) {
@@ -1023,6 +1053,7 @@ void decompress(const spmvc_matrix_s *M, int64_t *rp, int32_t *col, double *val,
     a.id_bytes = M->id_bytes;
     a.V = M->V_dev.as<double>();
     a.T = M->T.as<uint8_t>();
+    a.pat_T = M->fold ? M->pat_T.as<uint8_t>() : nullptr;
     a.ids = M->ids.p;
     a.pat_off = M->pat_off.as<int32_t>();
     a.pat_len = M->pat_len.as<uint8_t>();

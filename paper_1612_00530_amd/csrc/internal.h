@@ -115,18 +115,20 @@ constexpr int kRegTw = 32;  // uint16 per register-table row (64 bytes, 16-byte 
 // The opaque handle.
 struct spmvc_matrix_s {
     int64_t n_rows = 0, n_cols = 0, nnz = 0, n_pad = 0;
-    int32_t fmt = SPMVC_FMT_DIT;
+    int32_t fmt = SPMVC_FMT_DIT;  // ELL, DT or DIT (DITV is DIT with fold set)
+    int32_t fold = 0;             // DITV: T_i registered per pattern (pat_T), no per-row T
     int32_t K = 0, P = 0, id_bytes = 1, width = 0, max_raw = 0;
     int32_t f32_shadow = 1;
     double V[spmvc::kMaxK] = {};
     float V32[spmvc::kMaxK] = {};
     int64_t n_esc = 0, n_esc_nnz = 0, n_raw = 0, raw_elems = 0;
     // device arrays
-    spmvc::DevBuf ell_val, ell_col, dt_S, ids, T, pat_off, pat_len, raw, raw32, raw_slice,
+    spmvc::DevBuf ell_val, ell_col, dt_S, ids, T, pat_off, pat_len, pat_T, raw, raw32, raw_slice,
         esc_rows, esc_ptr, esc_col, esc_val, esc_val32, V_dev;
     // host copies of the (small) pattern table, for LDS plans
     std::vector<int32_t> h_pat_off; // [P][width]
     std::vector<uint8_t> h_pat_len; // [P]
+    std::vector<uint8_t> h_pat_T;   // [P][K], DITV only
     // kernel configuration
     int32_t rows_per_block[2] = {512, 512};  // per dtype (index SPMVC_F64 / SPMVC_F32)
     int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits,

@@ -50,6 +50,7 @@ struct SpmvArgs {
     int32_t K, width, P, raw_present, id_bytes;
     const void *ids;
     const uint8_t *T;
+    const uint8_t *pat_T;  // DITV: T of each pattern [P][K] (the rows keep none), else null
     const int32_t *pat_off;
     const uint8_t *pat_len;
     const int32_t *cols; // ELL col or DT S
@@ -91,6 +92,12 @@ struct SpmvArgs {
 template <class Real> __device__ __forceinline__ Real vtab(const SpmvArgs &a, int c);
 template <> __device__ __forceinline__ double vtab<double>(const SpmvArgs &a, int c) { return a.V[c]; }
 template <> __device__ __forceinline__ float vtab<float>(const SpmvArgs &a, int c) { return a.V32[c]; }
+
+// T_i[c] of a non-escape row: its own byte of the T stream, or -- values
+// registered in the pattern table (DITV) -- its pattern's.
+__device__ __forceinline__ int row_T(const SpmvArgs &a, int c, int64_t row, uint32_t id) {
+    return a.pat_T ? a.pat_T[static_cast<int64_t>(id) * a.K + c] : a.T[static_cast<int64_t>(c) * a.n_pad + row];
+}
 
 template <class T> __device__ __forceinline__ T ldg_stream(const T *p) {
     return __builtin_nontemporal_load(p);
@@ -215,8 +222,10 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
     } else {
         const int32_t *pat = nullptr;
         int len = 0;
+        uint32_t pid = 0;
         if constexpr (FMT == SPMVC_FMT_DIT) {
             const IdT id = static_cast<const IdT *>(a.ids)[row];
+            pid = id;
             if (id == esc_id<IdT>()) return 0.0;
             pat = a.pat_off + static_cast<int64_t>(id) * a.width;
             len = a.pat_len[id];
@@ -232,7 +241,7 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
         };
         int k = 0;
         for (int c = 0; c < a.K; ++c) {
-            const int tend = a.T[static_cast<int64_t>(c) * a.n_pad + row];
+            const int tend = row_T(a, c, row, pid);
             const Real v = vtab<Real>(a, c);
             for (; k < tend; ++k) apply(v, column(k));
         }
@@ -340,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
         Real acc = Real(0);
         int k = 0;
         for (int c = 0; c < a.K; ++c) {
-            const int tend = a.T[static_cast<int64_t>(c) * a.n_pad + row];
+            const int tend = row_T(a, c, row, id);
             const Real v = vtab<Real>(a, c);
             for (; k < tend; ++k) acc = fma(v, xr[t[k]], acc);
         }
@@ -422,7 +431,7 @@ __device__ __forceinline__ void load_tile_meta(const SpmvArgs &a, const Real *__
         const int64_t row = r0 + threadIdx.x + j * kBlock;
         const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
         idv[j] = load_id(a.ids, a.id_bytes, rc);
-        t0v[j] = KK >= 1 ? static_cast<int>(a.T[rc]) : 0;
+        t0v[j] = (KK >= 1 && !a.pat_T) ? static_cast<int>(a.T[rc]) : 0;  // DITV: from the pattern row
         xrow[j] = a.dot ? x[rc] : Real(0);
     }
 }
@@ -450,8 +459,10 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
             w[4 * q + 2] = u.z;
             w[4 * q + 3] = u.w;
         }
-        const int len = static_cast<int>(w[0] & 0xFFFFu);
-        const int m = KK == 2 ? len - t0v[j] : 0;  // leading entries that take V[1]
+        // word 0 of the pattern row: length, and for DITV the pattern's T_i[0]
+        const int len = static_cast<int>(w[0] & 0xFFu);
+        const int t0 = a.pat_T ? static_cast<int>((w[0] >> 8) & 0xFFu) : t0v[j];
+        const int m = KK == 2 ? len - t0 : 0;  // leading entries that take V[1]
         // Is the split the same in every active lane?  Reference: the lowest
         // active lane's m (two ballots and one lane read, all scalar results).
         int ms = 0;
@@ -627,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__
             const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
             const int64_t ib = rc * a.id_bytes;
             idw[j] = *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(a.ids) + (ib & ~int64_t(3)));
-            t0w[j] = KK >= 1 ? *reinterpret_cast<const uint32_t *>(a.T + (rc & ~int64_t(3))) : 0u;
+            t0w[j] = (KK >= 1 && !a.pat_T) ? *reinterpret_cast<const uint32_t *>(a.T + (rc & ~int64_t(3))) : 0u;
             xn[j] = a.dot ? x[rc] : Real(0);
         }
     };
@@ -723,8 +734,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, con
     } else {
         const int32_t *pat = nullptr;
         int len = 0;
+        uint32_t pid = 0;
         if constexpr (FMT == SPMVC_FMT_DIT) {
             const IdT id = static_cast<const IdT *>(a.ids)[row];
+            pid = id;
             if (id == esc_id<IdT>()) return;
             pat = a.pat_off + static_cast<int64_t>(id) * a.width;
             len = a.pat_len[id];
@@ -740,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, con
         };
         int k = 0;
         for (int c = 0; c < a.K; ++c) {
-            const int tend = a.T[static_cast<int64_t>(c) * a.n_pad + row];
+            const int tend = row_T(a, c, row, pid);
             const Real v = vtab<Real>(a, c);
             for (; k < tend; ++k) apply(v, column(k));
         }
@@ -795,7 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
         const int64_t row = r0 + threadIdx.x + j * kBlock;
         const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
         idv[j] = load_id(a.ids, a.id_bytes, rc);
-        t0v[j] = static_cast<int>(a.T[rc]);
+        t0v[j] = a.pat_T ? 0 : static_cast<int>(a.T[rc]);  // DITV: from the pattern row
     }
     // windows: element e of window w is the pair of row r0 + lo[w] + e
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -839,8 +852,8 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
             wv[4 * q + 2] = u.z;
             wv[4 * q + 3] = u.w;
         }
-        const int len = static_cast<int>(wv[0] & 0xFFFFu);
-        const int m = KK == 2 ? len - t0v[j] : 0;
+        const int len = static_cast<int>(wv[0] & 0xFFu);
+        const int m = KK == 2 ? len - (a.pat_T ? static_cast<int>((wv[0] >> 8) & 0xFFu) : t0v[j]) : 0;
         int ms = 0;
         bool uni = true;
         if constexpr (KK == 2) {
@@ -933,7 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
         const int64_t row = r0 + ps * (kBlock / LPR) + lr;
         const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
         idv[ps] = load_id(a.ids, a.id_bytes, rc);
-        t0v[ps] = a.K >= 2 ? static_cast<int>(a.T[rc]) : 255;
+        t0v[ps] = a.K < 2 ? 255 : (idv[ps] == esc ? 0 : row_T(a, 0, rc, idv[ps]));
     }
     {
         const int n16 = a.P * NW * (kWinSt / 4);
@@ -1000,6 +1013,7 @@ template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *ski
     a.id_bytes = M->id_bytes;
     a.ids = M->ids.p;
     a.T = M->T.as<uint8_t>();
+    a.pat_T = M->fold ? M->pat_T.as<uint8_t>() : nullptr;
     a.pat_off = M->pat_off.as<int32_t>();
     a.pat_len = M->pat_len.as<uint8_t>();
     a.cols = M->fmt == SPMVC_FMT_ELL ? M->ell_col.as<int32_t>() : M->dt_S.as<int32_t>();
@@ -1414,6 +1428,15 @@ unsigned launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStrea
 
 }  // namespace
 
+// Word 0 of a register-kernel pattern row: the length in the low byte and,
+// for DITV, the pattern's T_i[0] in the high byte (the kernels take the split
+// from there; DIT rows read theirs from the T stream).
+static uint16_t reg_row_head(const spmvc_matrix_s *M, int q) {
+    const int L = M->h_pat_len[q];
+    const int t0 = (M->fold && M->K >= 1) ? M->h_pat_T[static_cast<size_t>(q) * M->K] : 0;
+    return static_cast<uint16_t>(L | (t0 << 8));
+}
+
 // Plane-marching form of the register-kernel plan: applies when the windows
 // are equally spaced (by S rows, a multiple of 4) and equally long, so that
 // window w of the tile in plane z is window w - 1 of the tile in plane z + 1.
@@ -1447,7 +1470,7 @@ static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<st
             for (int q = 0; q < M->P; ++q) {
                 const int Lq = M->h_pat_len[q];
                 uint16_t *r = rt.data() + (static_cast<size_t>(ph) * M->P + q) * kRegTw;
-                r[0] = static_cast<uint16_t>(Lq);
+                r[0] = reg_row_head(M, q);
                 const bool rev = M->K >= 1;
                 for (int k = 0; k < kRegW; ++k) {
                     int64_t e = NB * L;  // zero window
@@ -1629,7 +1652,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
             for (int q = 0; q < M->P; ++q) {
                 const int L = M->h_pat_len[q];
                 uint16_t *r = rt.data() + static_cast<size_t>(q) * kRegTw;
-                r[0] = static_cast<uint16_t>(L);
+                r[0] = reg_row_head(M, q);
                 // dictionary kernels take the entries in reverse canonical order
                 const bool rev = M->K >= 1;
                 for (int k = 0; k < kRegW; ++k) {
@@ -1651,7 +1674,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
             for (int q = 0; q < M->P; ++q) {
                 const int L = M->h_pat_len[q];
                 uint16_t *r = rt.data() + static_cast<size_t>(q) * kRegTw;
-                r[0] = static_cast<uint16_t>(L);
+                r[0] = reg_row_head(M, q);
                 for (int k = 0; k < kRegW; ++k) {
                     const int64_t e = k < L ? lds_index(M->h_pat_off[static_cast<size_t>(q) * W + (L - 1 - k)]) : total;
                     r[1 + k] = static_cast<uint16_t>(e * 16);
@@ -1716,13 +1739,14 @@ int64_t stream_bytes(const spmvc_matrix_s *M, int dt) {
     if (M->fmt == SPMVC_FMT_ELL) {
         b += slots * (4 + 8);
     } else {
-        b += static_cast<int64_t>(M->K) * M->n_pad;            // T
+        if (!M->fold) b += static_cast<int64_t>(M->K) * M->n_pad;  // T (DITV: in the pattern table)
         b += M->raw_elems * vb;                               // raw values
         if (M->raw_elems) b += 8 * (M->n_pad / kSlice + 1);   // slice pointers
         if (M->fmt == SPMVC_FMT_DT)
             b += slots * 4;                                   // S
         else
-            b += static_cast<int64_t>(M->id_bytes) * M->n_pad + static_cast<int64_t>(M->P) * (M->width + 1) * 2;
+            b += static_cast<int64_t>(M->id_bytes) * M->n_pad + static_cast<int64_t>(M->P) * (M->width + 1) * 2 +
+                 (M->fold ? static_cast<int64_t>(M->P) * M->K : 0);
     }
     b += M->n_esc_nnz * (4 + vb) + M->n_esc * 16;
     return b;

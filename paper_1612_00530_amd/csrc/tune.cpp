@@ -33,7 +33,7 @@ std::string cache_key(const spmvc_matrix_s *M, int dt, int nrhs) {
     (void)hipGetDevice(&dev);
     (void)hipGetDeviceProperties(&prop, dev);
     std::ostringstream k;
-    k << prop.gcnArchName << "|fmt" << M->fmt << "|n" << M->n_rows << "|P" << M->P << "|K" << M->K << "|dt" << dt
+    k << prop.gcnArchName << "|fmt" << (M->fold ? SPMVC_FMT_DITV : M->fmt) << "|n" << M->n_rows << "|P" << M->P << "|K" << M->K << "|dt" << dt
       << "|nrhs" << nrhs;
     return k.str();
 }

@@ -34,7 +34,7 @@ def solve(A, b, fmt="DIT", **kw):
     return st, xs[0].cpu().numpy(), stats
 
 
-@pytest.mark.parametrize("fmt", ["ELL", "DT", "DIT"])
+@pytest.mark.parametrize("fmt", ["ELL", "DT", "DIT", "DITV"])
 @pytest.mark.parametrize("grid", [(16, 16, 16), (32, 32, 32)])
 def test_fp64_cg_ones(fmt, grid):
     say("case: cg ones", fmt, grid)
@@ -296,6 +296,31 @@ def test_batched_full_size_64_systems():
             rel = oracle.relres(A, B[:, r], X[:, r])
             assert q["status"] == 0 and rel <= 1.5e-10
             assert abs(q["relres_true"] - rel) <= 1e-12
+
+
+@pytest.mark.parametrize("nrhs", [3, 8])
+def test_batched_ditv_equals_dit(nrhs):
+    """Batched CG over DITV handles (T from the pattern table) gives DIT's
+    iterates bit for bit -- through the window-phased SpMV (8 right-hand
+    sides) and the lane-group one (3) -- and reaches the oracle's tolerance."""
+    say("case: batched DITV", nrhs)
+    torch = torch_mod()
+    P = lib()
+    grids = [(10, 12, 9), (16, 11, 13), (3, 3, 3)]
+    mats, As, bs = batched_case(grids, nrhs, seed=9)
+    mats_v = [compress(A, fmt="DITV") for A in As]
+    _, x_d, s_d = P.cg_solve(mats, bs, nrhs=nrhs, batched=2, check_every=4)
+    st, x_v, s_v = P.cg_solve(mats_v, bs, nrhs=nrhs, batched=2, check_every=4)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert [q["iters"] for q in s_v] == [q["iters"] for q in s_d]
+    for a, b in zip(x_v, x_d):
+        assert torch.equal(a, b)
+    for s, A in enumerate(As):
+        X = x_v[s].cpu().numpy()
+        B = bs[s].cpu().numpy()
+        for r in range(nrhs):
+            assert oracle.relres(A, B[:, r], X[:, r]) <= 1.5e-10
 
 
 def test_batched_failures_are_per_pair():

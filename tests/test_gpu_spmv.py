@@ -19,7 +19,7 @@ from gpu_util import compress, lib, max_rel_err, row_scale, same_bits, torch_mod
 
 pytestmark = pytest.mark.gpu
 
-FORMATS = ["ELL", "DT", "DIT"]
+FORMATS = ["ELL", "DT", "DIT", "DITV"]
 
 
 def say(*a):
@@ -43,6 +43,27 @@ def roundtrip_ok(M, A):
             and same_bits(val.cpu().numpy(), A.val))
 
 
+def _scattered_two_values(grid=(16, 13, 11), p_v1=0.3, seed=11):
+    """27-point structure, values drawn per entry from {-1, 3.5} (seeded)."""
+    A = stencil27(*grid)
+    rng = np.random.default_rng(seed)
+    A.val[:] = np.where(rng.random(A.nnz) < p_v1, 3.5, -1.0)
+    return A
+
+
+def _split_alternates(n=200):
+    """3-point rows whose values ascend with the column, split alternating
+    between rows: (-1, -1, 3.5) and (-1, 3.5, 3.5) -- one DIT pattern, two DITV ones."""
+    cols, vals, rp = [], [], [0]
+    for i in range(n):
+        c = [j for j in (i - 1, i, i + 1) if 0 <= j < n]
+        v = [-1.0, -1.0, 3.5] if i % 2 == 0 else [-1.0, 3.5, 3.5]
+        cols += c
+        vals += v[3 - len(c):] if i == 0 else v[:len(c)]
+        rp.append(len(cols))
+    return CSR(n, n, np.array(rp), np.array(cols, dtype=np.int32), np.array(vals))
+
+
 @pytest.mark.parametrize("fmt", FORMATS)
 def test_stencil16_parity_and_roundtrip(fmt):
     say("case: stencil 16^3", fmt)
@@ -63,9 +84,13 @@ def test_stencil104_full_size_parity(fmt):
     y = gpu_spmv(M, x)
     assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
     inf = M.info()
-    if fmt == "DIT":
+    if fmt in ("DIT", "DITV"):
         assert inf["K"] == 2 and inf["P"] == 19 and inf["n_escape_rows"] == 8
         assert inf["id_bytes"] == 1 and inf["lds_windows"] == 3
+    if fmt == "DITV":  # the row stream is the 1-byte ID alone
+        dit = compress(A, fmt="DIT").info()
+        assert inf["fmt_name"] == "DITV" and M.array("T").numel() == 0
+        assert dit["bytes_stream"] - inf["bytes_stream"] == 2 * ((A.n_rows + 63) // 64 * 64) - 2 * inf["P"]
     # closed form: A*1 = 26 - #neighbours, exact in any summation order
     y1 = gpu_spmv(M, np.ones(A.n_cols))
     assert np.array_equal(y1, oracle.spmv(A, np.ones(A.n_cols)))
@@ -138,7 +163,7 @@ def test_irregular128_parity_and_roundtrip(fmt):
     y = gpu_spmv(M, x)
     assert max_rel_err(A, x, y, oracle.spmv(A, x)) <= 1e-14
     assert roundtrip_ok(M, A)
-    if fmt == "DIT":
+    if fmt in ("DIT", "DITV"):
         inf = M.info()
         assert inf["K"] == 0 and inf["id_bytes"] == 2
         assert inf["n_escape_rows"] < 0.02 * A.n_rows
@@ -231,6 +256,49 @@ def test_block_lds_kernels(mode, grid, nrhs, ld):
         assert np.all(yb[:, nrhs:].cpu().numpy() == 5.0)
 
 
+@pytest.mark.parametrize("make", [_scattered_two_values, _split_alternates,
+                                  lambda: stencil27(40, 37, 23)])
+def test_ditv_equals_dit_in_every_kernel(make):
+    """DITV rows take T_i from their pattern (the register kernels from the
+    pattern row's header word, the others from the pattern's T bytes); the
+    entry order and the arithmetic are DIT's, so y is DIT's bit for bit in
+    every single-vector configuration (register, plane-marching, LDS walk,
+    direct gather; FP64 and FP32) and every block kernel, and within the bound
+    of the oracle.  Rows that escape in either format (a pattern that DITV
+    splits may fall under the two-row rule) are summed in CSR order there and
+    are compared with the oracle only."""
+    say("case: DITV vs DIT")
+    torch = torch_mod()
+    A = make()
+    Md, Mv = compress(A, fmt="DIT"), compress(A, fmt="DITV")
+    # (with the default escape rule a split pattern may fall under two rows and
+    # escape, so DITV can keep fewer patterns than DIT)
+    assert Mv.info()["fmt_name"] == "DITV" and Mv.info()["P"] == codec.encode_dit(A, fold_values=True).P
+    both = np.ones(A.n_rows, dtype=bool)  # rows on a pattern in both formats
+    for M in (Md, Mv):
+        both[_np(M.array("ESC_ROWS"), np.int64)] = False
+    x = uniform_vector(A.n_cols, seed=21)
+    ref = oracle.spmv(A, x)
+    for rows, lds in ((256, 1), (512, 1), (1024, 1), (2048, 1), (512, 0), (256, 2), (512, 2)):
+        Md.set_config(rows, lds)
+        Mv.set_config(rows, lds)
+        assert Mv.info()["kernel_name"] == Md.info()["kernel_name"]
+        yv = gpu_spmv(Mv, x)
+        assert same_bits(yv[both], gpu_spmv(Md, x)[both])
+        assert max_rel_err(A, x, yv, ref) <= 1e-14
+        assert same_bits(gpu_spmv(Mv, x, "f32")[both], gpu_spmv(Md, x, "f32")[both])
+    for mode in (3, 2, 1, 0):
+        Md.set_block_mode(mode)
+        Mv.set_block_mode(mode)
+        for nrhs in (2, 8):
+            X = torch.from_numpy(np.stack([uniform_vector(A.n_cols, seed=30 + r) for r in range(nrhs)], 1)).cuda()
+            Yv = Mv.spmv_block(X).cpu().numpy()
+            assert same_bits(Yv[both], Md.spmv_block(X).cpu().numpy()[both])
+            Yref = oracle.spmv_block(A, X.cpu().numpy())
+            for r in range(nrhs):
+                assert max_rel_err(A, X[:, r].cpu().numpy(), Yv[:, r], Yref[:, r]) <= 1e-14
+
+
 @pytest.mark.parametrize("mode", [3, 2, 1, 0])
 def test_block_spmv_scattered_two_value_dictionary(mode):
     """A 27-point structure whose values are drawn per entry from {-1, 3.5}
@@ -283,13 +351,18 @@ def _np(t, dtype):
     return t.cpu().numpy().view(dtype)
 
 
-@pytest.mark.parametrize("make", [lambda: stencil27(16, 16, 16), lambda: stencil27_irregular(20, 17, 13, seed=1),
-                                  lambda: stencil27(5, 3, 4)])
-def test_dit_arrays_equal_reference_codec(make):
-    say("case: DIT arrays")
+@pytest.mark.parametrize("fmt,make", [("DIT", lambda: stencil27(16, 16, 16)),
+                                      ("DIT", lambda: stencil27_irregular(20, 17, 13, seed=1)),
+                                      ("DIT", lambda: stencil27(5, 3, 4)),
+                                      ("DITV", lambda: stencil27(16, 16, 16)),
+                                      ("DITV", lambda: stencil27_irregular(20, 17, 13, seed=1)),
+                                      ("DITV", lambda: _scattered_two_values((9, 8, 7), 0.02)),
+                                      ("DITV", _split_alternates)])
+def test_dit_arrays_equal_reference_codec(fmt, make):
+    say("case: DIT arrays", fmt)
     A = make()
-    enc = codec.encode_dit(A)
-    M = compress(A, fmt="DIT")
+    enc = codec.encode_dit(A, fold_values=fmt == "DITV")
+    M = compress(A, fmt=fmt)
     inf = M.info()
     n, n_pad, K, W = A.n_rows, ((A.n_rows + 63) // 64) * 64, enc.K, inf["width"]
     assert inf["K"] == K and inf["P"] == enc.P
@@ -298,9 +371,15 @@ def test_dit_arrays_equal_reference_codec(make):
     ids = _np(M.array("IDS"), idt)[:n].astype(np.int64)
     ids[ids == np.iinfo(idt).max] = -1
     assert np.array_equal(ids, enc.ids)
-    if K:
+    if K and fmt == "DIT":
         T = _np(M.array("T"), np.uint8).reshape(K, n_pad)[:, :n].T
         assert np.array_equal(T, enc.T)
+    if fmt == "DITV":  # no per-row T; the patterns carry it
+        assert M.array("T").numel() == 0
+        if K and enc.P:
+            pT = _np(M.array("PAT_T"), np.uint8)[:enc.P * K].reshape(enc.P, K).astype(np.int64)
+            assert np.array_equal(pT, enc.pat_T)
+        assert roundtrip_ok(M, A)
     pl = _np(M.array("PAT_LEN"), np.uint8).astype(np.int64)
     assert np.array_equal(pl, np.diff(enc.pat_ptr))
     po = _np(M.array("PAT_OFF"), np.int32).reshape(enc.P, W)
