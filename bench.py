@@ -242,6 +242,23 @@ def main():
         D.spmv(x32, y32)
     f_mean = time_batch(lambda: D.spmv(x32, y32), max(20, args.steps // 2), torch)
 
+    # DITV: the values registered in the pattern table too, a row stores only its ID
+    rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+    DV = P.compress(rp, col, val, n_cols=n, fmt="DITV")
+    del rp, col, val
+    tuned_v = DV.tune(torch.float64) if not args.no_tune else None
+    vinf = DV.info()
+    for _ in range(5):
+        DV.spmv(x, y)
+    v_mean = time_batch(lambda: DV.spmv(x, y), max(20, args.steps // 2), torch)
+    alg_v = vinf["bytes_stream"] + 8 * n + 8 * n
+    ditv = {"launch_us_mean": round(v_mean * 1000, 3), "gflops": round(2.0 * nnz / (v_mean * 1e-3) / 1e9, 1),
+            "bytes_per_row": round(vinf["bytes_stream"] / n, 3), "bytes_per_launch": alg_v,
+            "GBps": round(alg_v / (v_mean * 1e-3) / 1e9, 1), "speedup_vs_ell": round(e_mean / v_mean, 3),
+            "kernel": vinf["kernel_name"], "tuned": tuned_v}
+    log(f"[bench] DITV: {ditv['launch_us_mean']} us, {ditv['gflops']} Gflops, {ditv['bytes_per_row']} B/row")
+    del DV
+
     # block SpMV, 8 right-hand sides (row-interleaved), same matrix: DIT and ELL
     X8 = torch.from_numpy(np.random.default_rng(5).uniform(-1.0, 1.0, (n, 8))).to(dev)
     Y8 = torch.empty((n, 8), dtype=torch.float64, device=dev)
@@ -316,6 +333,7 @@ def main():
         "cold_mall": cold,
         "block_spmv": block8,
         "dit_f32": {"launch_us_mean": round(f_mean * 1000, 3), "gflops": round(2.0 * nnz / (f_mean * 1e-3) / 1e9, 2)},
+        "ditv": ditv,
         "irregular": irregular,
         "cg": cg,
         "batched_cg": batched,
