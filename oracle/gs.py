@@ -1,0 +1,85 @@
+"""Symmetric Gauss-Seidel over a multicolor ordering -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite and the benchmark's CPU-baseline leg may use this module.
+It shares no code with the GPU library.
+
+SymGS is the other kernel that dominates the HPCG iteration the paper
+accelerates (Section III, Table I: SymGS beside SpMV); it walks the same
+matrix rows.  A sweep updates x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii row
+by row, forward through the rows and then backward.  For a GPU the rows are
+taken in a multicolor order: rows of one color share no entry, so they can
+be updated together, and the sweep visits the colors forward then backward.
+The coloring is greedy in row order over the pattern of A + A^T: each row
+takes the smallest color that no lower-numbered neighbour holds.
+
+Pins (tests/test_oracle_gs.py): the coloring of a 27-point stencil equals the
+parity coloring (x mod 2) + 2 (y mod 2) + 4 (z mod 2); a sweep equals the
+matrix-splitting form (D + L) x' = b - U x, (D + U) x'' = b - L x' of the
+color-permuted matrix, solved by dense triangular solves; repeated sweeps
+converge to A^-1 b on a diagonally dominant matrix.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def greedy_coloring(A) -> np.ndarray:
+    """Color of every row: greedy in row order over the pattern of A + A^T.
+
+    Plain Python loops: for matrices of a few ten thousand rows at most.
+    """
+    n = A.n_rows
+    rp = np.asarray(A.row_ptr, dtype=np.int64)
+    col = np.asarray(A.col, dtype=np.int64)
+    nbr = [set() for _ in range(n)]
+    for i in range(n):
+        for k in range(int(rp[i]), int(rp[i + 1])):
+            j = int(col[k])
+            if j != i and j < n:
+                nbr[i].add(j)
+                nbr[j].add(i)
+    color = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        used = {int(color[j]) for j in nbr[i] if j < i}
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    return color
+
+
+def diagonal(A) -> np.ndarray:
+    """a_ii of every row (0 where the row holds no diagonal entry)."""
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+    d = np.zeros(A.n_rows, dtype=np.float64)
+    on = np.asarray(A.col, dtype=np.int64) == rows
+    d[rows[on]] = np.asarray(A.val)[on]
+    return d
+
+
+def symgs(A, b, x, color, sweeps: int = 1) -> np.ndarray:
+    """`sweeps` symmetric Gauss-Seidel sweeps on A x = b in the order of `color`.
+
+    Each sweep visits the colors 0, 1, ..., C-1 and then C-1, ..., 0; the rows
+    of a color are updated with x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii,
+    every off-diagonal product taken from the current x.  Returns the new x.
+    """
+    n = A.n_rows
+    x = np.array(x, dtype=np.float64, copy=True)
+    b = np.asarray(b, dtype=np.float64)
+    color = np.asarray(color, dtype=np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+    col = np.asarray(A.col, dtype=np.int64)
+    val = np.asarray(A.val, dtype=np.float64)
+    d = diagonal(A)
+    off = col != rows
+    n_colors = int(color.max()) + 1 if n else 0
+    rows_of = [np.flatnonzero(color == c) for c in range(n_colors)]
+    ent_of = [np.flatnonzero(off & (color[rows] == c)) for c in range(n_colors)]
+    order = list(range(n_colors)) + list(range(n_colors - 1, -1, -1))
+    for _ in range(sweeps):
+        for c in order:
+            R, e = rows_of[c], ent_of[c]
+            s = np.bincount(rows[e], weights=val[e] * x[col[e]], minlength=n)
+            x[R] = (b[R] - s[R]) / d[R]
+    return x
