@@ -260,6 +260,31 @@ spmvc_status spmv_set_block_mode(spmvc_matrix A, int32_t mode);
 spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void *stream,
                        int32_t *best_rows_per_block, int32_t *best_lds, double *best_us);
 
+/*
+ * Symmetric Gauss-Seidel, the other kernel of the HPCG iteration (Section
+ * III, Table I: SymGS beside SpMV), over the compressed matrix: `sweeps`
+ * times, the rows are updated with x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii,
+ * color by color -- colors 0..C-1, then C-1..0 -- where the rows of a color
+ * share no entry, so each color is one parallel step.  The coloring is greedy
+ * in row order over the pattern of A + A^T (each row takes the smallest color
+ * no lower-numbered neighbour holds; the 27-point stencil gets its 8 parity
+ * classes).  FP64; b [n_rows] and x [n_rows] are device arrays, x is read as
+ * the initial guess and overwritten; they must not overlap.  Any format.
+ * The first call on a handle builds the coloring (blocking, O(nnz) on the
+ * host from the decompressed matrix) and must not run concurrently with other
+ * calls on that handle; later calls are asynchronous on `stream`.
+ * SPMVC_EINVAL: null argument, sweeps < 0, overlap, a non-square matrix or a
+ * row without a non-zero diagonal entry.
+ */
+spmvc_status spmv_symgs(spmvc_matrix A, const double *b, double *x, int32_t sweeps, void *stream);
+
+/*
+ * The coloring spmv_symgs uses: *n_colors (host) and, when color is not NULL,
+ * the color of every row into color [n_rows] int32 (device).  Builds the
+ * coloring on first use, as spmv_symgs does.  Blocking.
+ */
+spmvc_status spmv_colors(spmvc_matrix A, int32_t *n_colors, int32_t *color, void *stream);
+
 void spmv_free(spmvc_matrix A);
 
 const char *spmvc_status_string(int32_t status);

@@ -32,8 +32,8 @@ ARR = {
 
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
-    "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_free",
-    "spmvc_status_string", "spmvc_last_error",
+    "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
+    "spmv_free", "spmvc_status_string", "spmvc_last_error",
 ]
 
 
@@ -100,13 +100,16 @@ def load(path: str = LIB_PATH):
     lib.spmv_set_block_mode.argtypes = [P, i32]
     lib.spmv_tune.argtypes = [P, i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                               ctypes.POINTER(ctypes.c_double)]
+    lib.spmv_symgs.argtypes = [P, P, P, i32, P]
+    lib.spmv_colors.argtypes = [P, ctypes.POINTER(i32), P, P]
     lib.spmv_free.argtypes = [P]
     lib.spmv_free.restype = None
     lib.spmvc_status_string.argtypes = [i32]
     lib.spmvc_status_string.restype = ctypes.c_char_p
     lib.spmvc_last_error.restype = ctypes.c_char_p
     for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
-                 "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune"]:
+                 "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs",
+                 "spmv_colors"]:
         getattr(lib, name).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -215,6 +218,28 @@ class Matrix:
         _check(load().spmv_block(self._h, dt, nrhs, _dev_rows(X, X.dtype, "X"), max(X.stride(0), nrhs),
                                  _dev_rows(Y, X.dtype, "Y"), max(Y.stride(0), nrhs), _stream(stream)))
         return Y
+
+    def symgs(self, b, x=None, sweeps=1, stream=None):
+        """`sweeps` multicolor symmetric Gauss-Seidel sweeps on A x = b (FP64); x is
+        updated in place (a zero vector when None) and returned."""
+        import torch
+
+        if x is None:
+            x = torch.zeros(self.n_rows, dtype=torch.float64, device=b.device)
+        if b.numel() != self.n_rows or x.numel() != self.n_rows:
+            raise ValueError("b and x must have n_rows elements")
+        _check(load().spmv_symgs(self._h, _dev(b, torch.float64, "b"), _dev(x, torch.float64, "x"), int(sweeps),
+                                 _stream(stream)))
+        return x
+
+    def colors(self):
+        """(number of colors, int32 CUDA tensor of each row's color) of the SymGS coloring."""
+        import torch
+
+        nc = ctypes.c_int32()
+        col = torch.empty(max(self.n_rows, 1), dtype=torch.int32, device="cuda")
+        _check(load().spmv_colors(self._h, ctypes.byref(nc), ctypes.c_void_p(col.data_ptr()), _stream()))
+        return nc.value, col[: self.n_rows]
 
     def decompress(self):
         import torch

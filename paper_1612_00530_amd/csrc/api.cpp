@@ -201,6 +201,33 @@ spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx,
     });
 }
 
+spmvc_status spmv_symgs(spmvc_matrix A, const double *b, double *x, int32_t sweeps, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
+        if (sweeps < 0) return fail(SPMVC_EINVAL, "sweeps must be >= 0");
+        if (A->n_rows > 0 && (!b || !x)) return fail(SPMVC_EINVAL, "b / x is null");
+        if (overlap(b, 8 * A->n_rows, x, 8 * A->n_rows)) return fail(SPMVC_EINVAL, "b and x overlap");
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        build_coloring(A, s);
+        launch_symgs(A, b, x, sweeps, s);
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_colors(spmvc_matrix A, int32_t *n_colors, int32_t *color, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !n_colors) return fail(SPMVC_EINVAL, "null argument");
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        build_coloring(A, s);
+        *n_colors = A->gs_n_colors;
+        if (color && A->n_rows > 0) {
+            SPMVC_HIP(hipMemcpyAsync(color, A->gs_color.p, sizeof(int32_t) * A->n_rows, hipMemcpyDeviceToDevice, s));
+            SPMVC_HIP(hipStreamSynchronize(s));
+        }
+        return SPMVC_OK;
+    });
+}
+
 spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
     return guarded([&]() -> spmvc_status {
         if (!A || !info) return fail(SPMVC_EINVAL, "null argument");

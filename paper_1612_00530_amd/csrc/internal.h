@@ -139,6 +139,10 @@ struct spmvc_matrix_s {
                                            // of right-hand-side pairs in LDS (3 and 2 where they
                                            // apply, else 1); 1 = a lane group per row; 0 = one lane
                                            // per row (all rhs)
+    // multicolor Gauss-Seidel (symgs.hip): greedy coloring, built on first use
+    int32_t gs_ready = 0, gs_n_colors = 0;
+    std::vector<int64_t> gs_off;          // rows of color c: gs_rows[gs_off[c] .. gs_off[c+1])
+    spmvc::DevBuf gs_rows, gs_color;      // int32 [n]: rows by color (ascending); color of each row
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
     int32_t n_cu = 256;         // compute units of the device (grid sizing)
@@ -179,6 +183,10 @@ bool batched_supported(const spmvc_matrix *A, int n_sys);
 spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                               double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,
                               hipStream_t s, bool use_graph);
+
+// symgs.hip
+void build_coloring(spmvc_matrix_s *M, hipStream_t s);  // blocking; throws Error on a bad matrix
+void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s);
 
 // scan.hip: exclusive prefix sum of n int64 values (in may equal out); returns the total.
 int64_t exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

@@ -1,0 +1,242 @@
+// Symmetric Gauss-Seidel over the compressed matrix, in multicolor order.
+//
+// SymGS is the other kernel of the HPCG iteration the paper accelerates
+// (Section III, Table I: SymGS beside SpMV); it walks the same rows as the
+// SpMV.  A sweep updates x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii forward
+// through the rows and then backward.  On the GPU the rows are taken color by
+// color: rows of one color share no entry (a proper coloring of the pattern
+// of A + A^T), so one launch updates all of them; a sweep is the colors
+// forward, then backward.
+//
+// The coloring is greedy in row order: each row takes the smallest color no
+// lower-numbered neighbour holds (on a 27-point stencil: the 8 parity
+// classes).  It is built once per handle on first use, on the host from the
+// decompressed CSR -- an O(nnz) set-up step like the LDS plans -- and kept
+// on the device as the rows of each color, ascending.
+//
+// k_symgs_color: one thread per row of the color; the row is decoded from
+// the handle's own format (ELL, DT, DIT/DITV, raw values, escape rows) and
+// x is gathered straight from global memory, since the rows of a color are
+// spread over the whole grid.
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace spmvc {
+namespace {
+
+constexpr int kGsThreads = 256;
+
+struct GsArgs {
+    int64_t n_rows, n_pad;
+    int32_t fmt, K, width, id_bytes;
+    const void *ids;
+    const uint8_t *T;
+    const uint8_t *pat_T;  // DITV: T of each pattern
+    const int32_t *pat_off;
+    const uint8_t *pat_len;
+    const int32_t *cols;   // ELL columns or DT's S
+    const double *ell_val;
+    const double *raw;
+    const int64_t *raw_slice;
+    const int64_t *esc_rows, *esc_ptr;
+    const int32_t *esc_col;
+    const double *esc_val;
+    int64_t n_esc;
+    double V[kMaxK];
+};
+
+__device__ __forceinline__ uint32_t gs_id(const GsArgs &a, int64_t row) {
+    if (a.id_bytes == 1) return static_cast<const uint8_t *>(a.ids)[row];
+    if (a.id_bytes == 2) return static_cast<const uint16_t *>(a.ids)[row];
+    return static_cast<const uint32_t *>(a.ids)[row];
+}
+
+// Calls f(value, column) for every entry of `row`.
+template <class F> __device__ __forceinline__ void gs_visit(const GsArgs &a, int64_t row, F f) {
+    bool escape = false;
+    uint32_t id = 0;
+    if (a.fmt == SPMVC_FMT_DIT) {
+        id = gs_id(a, row);
+        escape = id == (a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu));
+    } else {
+        escape = a.cols[row] == kEscapeColumn;
+    }
+    if (escape) {  // plain CSR row: find it among the (ascending) escape rows
+        int64_t lo = 0, hi = a.n_esc;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            if (a.esc_rows[mid] <= row) lo = mid; else hi = mid;
+        }
+        for (int64_t k = a.esc_ptr[lo]; k < a.esc_ptr[lo + 1]; ++k) f(a.esc_val[k], static_cast<int64_t>(a.esc_col[k]));
+        return;
+    }
+    if (a.fmt == SPMVC_FMT_ELL) {
+        for (int k = 0; k < a.width; ++k) {
+            const int64_t o = static_cast<int64_t>(k) * a.n_pad + row;
+            const int32_t c = a.cols[o];
+            if (c >= 0) f(a.ell_val[o], static_cast<int64_t>(c));
+        }
+        return;
+    }
+    // DT and DIT: canonical order, the value of position k from T, raw values after the coded ones
+    const bool dit = a.fmt == SPMVC_FMT_DIT;
+    const int32_t *pat = dit ? a.pat_off + static_cast<int64_t>(id) * a.width : nullptr;
+    const int len = dit ? static_cast<int>(a.pat_len[id]) : a.width;
+    auto column = [&](int k) -> int64_t {
+        return dit ? row + pat[k] : static_cast<int64_t>(a.cols[static_cast<int64_t>(k) * a.n_pad + row]);
+    };
+    auto t_end = [&](int c) -> int {
+        return a.pat_T ? a.pat_T[static_cast<int64_t>(id) * a.K + c] : a.T[static_cast<int64_t>(c) * a.n_pad + row];
+    };
+    int k = 0;
+    for (int c = 0; c < a.K; ++c) {
+        const int te = t_end(c);
+        for (; k < te; ++k) f(a.V[c], column(k));
+    }
+    if (a.raw) {
+        const int64_t rb = a.raw_slice[row / kSlice] + (row % kSlice) - static_cast<int64_t>(k) * kSlice;
+        for (; k < len; ++k) {
+            const int64_t j = column(k);
+            if (!dit && j < 0) break;  // DT padding
+            f(a.raw[rb + static_cast<int64_t>(k) * kSlice], j);
+        }
+    }
+}
+
+// The rows rows[0..n) of one color: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.
+__global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int32_t *__restrict__ rows, int64_t n,
+                                                            const double *__restrict__ b, double *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = rows[t];
+    double s = 0.0, d = 0.0;
+    gs_visit(a, i, [&](double v, int64_t j) {
+        if (j == i)
+            d = v;
+        else
+            s = fma(v, x[j], s);
+    });
+    x[i] = (b[i] - s) / d;
+}
+
+GsArgs gs_args(const spmvc_matrix_s *M) {
+    GsArgs a{};
+    a.n_rows = M->n_rows;
+    a.n_pad = M->n_pad;
+    a.fmt = M->fmt;
+    a.K = M->K;
+    a.width = M->width;
+    a.id_bytes = M->id_bytes;
+    a.ids = M->ids.p;
+    a.T = M->T.as<uint8_t>();
+    a.pat_T = M->fold ? M->pat_T.as<uint8_t>() : nullptr;
+    a.pat_off = M->pat_off.as<int32_t>();
+    a.pat_len = M->pat_len.as<uint8_t>();
+    a.cols = M->fmt == SPMVC_FMT_ELL ? M->ell_col.as<int32_t>() : M->dt_S.as<int32_t>();
+    a.ell_val = M->ell_val.as<double>();
+    a.raw = M->raw_elems > 0 ? M->raw.as<double>() : nullptr;
+    a.raw_slice = M->raw_slice.as<int64_t>();
+    a.esc_rows = M->esc_rows.as<int64_t>();
+    a.esc_ptr = M->esc_ptr.as<int64_t>();
+    a.esc_col = M->esc_col.as<int32_t>();
+    a.esc_val = M->esc_val.as<double>();
+    a.n_esc = M->n_esc;
+    for (int c = 0; c < kMaxK; ++c) a.V[c] = M->V[c];
+    return a;
+}
+
+}  // namespace
+
+// Greedy row-order coloring of the pattern of A + A^T, built once per handle;
+// also checks that every row holds a non-zero diagonal entry.
+void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
+    if (M->gs_ready) return;
+    if (M->n_rows != M->n_cols) throw Error{SPMVC_EINVAL, "Gauss-Seidel needs a square matrix"};
+    const int64_t n = M->n_rows, nnz = M->nnz;
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> col(nnz);
+    std::vector<double> val(nnz);
+    if (n > 0) {
+        DevBuf drp, dcol, dval;
+        drp.alloc(sizeof(int64_t) * (n + 1));
+        dcol.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+        dval.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+        decompress(M, drp.as<int64_t>(), dcol.as<int32_t>(), dval.as<double>(), s);
+        SPMVC_HIP(hipMemcpyAsync(rp.data(), drp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        if (nnz > 0) {
+            SPMVC_HIP(hipMemcpyAsync(col.data(), dcol.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+            SPMVC_HIP(hipMemcpyAsync(val.data(), dval.p, sizeof(double) * nnz, hipMemcpyDeviceToHost, s));
+        }
+        SPMVC_HIP(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        bool ok = false;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (col[k] == i) ok = val[k] != 0.0;
+        if (!ok) throw Error{SPMVC_EINVAL, "Gauss-Seidel needs a non-zero diagonal entry in every row"};
+    }
+    // A^T's pattern: for each row, the rows that hold it as a column
+    std::vector<int64_t> tp(n + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) ++tp[col[k] + 1];
+    for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+    std::vector<int32_t> tr(nnz);
+    {
+        std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) tr[fill[col[k]]++] = static_cast<int32_t>(i);
+    }
+    std::vector<int32_t> color(n, -1);
+    std::vector<int64_t> mark(32, -1);
+    int32_t n_colors = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        auto take = [&](int64_t j) {
+            if (j < i) {
+                const int32_t c = color[j];
+                if (c >= static_cast<int32_t>(mark.size())) mark.resize(2 * c + 2, -1);
+                mark[c] = i;
+            }
+        };
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) take(col[k]);
+        for (int64_t k = tp[i]; k < tp[i + 1]; ++k) take(tr[k]);
+        int32_t c = 0;
+        while (c < static_cast<int32_t>(mark.size()) && mark[c] == i) ++c;
+        color[i] = c;
+        n_colors = std::max(n_colors, c + 1);
+    }
+    // rows of each color, ascending
+    M->gs_off.assign(n_colors + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++M->gs_off[color[i] + 1];
+    for (int c = 0; c < n_colors; ++c) M->gs_off[c + 1] += M->gs_off[c];
+    std::vector<int32_t> rows(n);
+    {
+        std::vector<int64_t> fill(M->gs_off.begin(), M->gs_off.end() - 1);
+        for (int64_t i = 0; i < n; ++i) rows[fill[color[i]]++] = static_cast<int32_t>(i);
+    }
+    M->gs_rows.alloc(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    M->gs_color.alloc(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    if (n > 0) {
+        SPMVC_HIP(hipMemcpyAsync(M->gs_rows.p, rows.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        SPMVC_HIP(hipMemcpyAsync(M->gs_color.p, color.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        SPMVC_HIP(hipStreamSynchronize(s));
+    }
+    M->gs_n_colors = n_colors;
+    M->gs_ready = 1;
+}
+
+void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s) {
+    const GsArgs a = gs_args(M);
+    const int C = M->gs_n_colors;
+    const int32_t *rows = M->gs_rows.as<int32_t>();
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int q = 0; q < 2 * C; ++q) {
+            const int c = q < C ? q : 2 * C - 1 - q;  // colors forward, then backward
+            const int64_t r0 = M->gs_off[c], cnt = M->gs_off[c + 1] - r0;
+            if (cnt == 0) continue;
+            k_symgs_color<<<grid_for(cnt, kGsThreads, 0x7fffffff), kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
+            SPMVC_CHECK_LAUNCH();
+        }
+}
+
+}  // namespace spmvc

@@ -1,0 +1,125 @@
+"""GPU multicolor symmetric Gauss-Seidel against the oracle (oracle/gs.py), through the C ABI.
+
+* the coloring equals the oracle's greedy row-order coloring exactly, and on
+  the full 104^3 stencil the parity coloring (x mod 2) + 2 (y mod 2) + 4 (z mod 2);
+* sweeps equal the oracle's to a tolerance from the arithmetic: each row
+  update is a <= 27-term sum with relative error <= gamma_27 of
+  (|b_i| + sum |a_ij||x_j|) / |a_ii| <= about 1.5e-15 on these matrices, and
+  a sweep chains 16 color steps of a diagonally dominant (contracting)
+  iteration, so 1e-12 of the vectors' size leaves a wide margin;
+* DITV gives DIT's result bit for bit (same entries in the same order);
+* bad inputs are rejected (non-square, zero diagonal, negative sweeps).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gs
+from synthetic import CSR, stencil27, stencil27_irregular, uniform_vector
+
+from gpu_util import compress, lib, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["ELL", "DT", "DIT", "DITV"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def parity_coloring(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return ((x % 2) + 2 * (y % 2) + 4 * (z % 2)).reshape(-1)
+
+
+def run(M, b, x0, sweeps=1):
+    torch = torch_mod()
+    x = torch.from_numpy(np.array(x0)).cuda()
+    M.symgs(torch.from_numpy(np.asarray(b)).cuda(), x, sweeps=sweeps)
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+def close(got, ref, *vecs):
+    scale = max([1.0] + [float(np.max(np.abs(v))) for v in (ref,) + vecs])
+    return float(np.max(np.abs(got - ref))) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("make", [lambda: stencil27(12, 10, 9), lambda: stencil27_irregular(10, 9, 8, seed=3),
+                                  lambda: stencil27(7, 1, 5)])
+def test_coloring_equals_oracle(make):
+    say("case: symgs coloring")
+    A = make()
+    M = compress(A, fmt="DIT")
+    nc, col = M.colors()
+    ref = gs.greedy_coloring(A)
+    assert nc == int(ref.max()) + 1
+    assert np.array_equal(col.cpu().numpy().astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("make", [lambda: stencil27(12, 10, 9), lambda: stencil27_irregular(14, 12, 10, seed=1)])
+def test_sweeps_equal_oracle(fmt, make):
+    say("case: symgs sweeps", fmt)
+    A = make()
+    M = compress(A, fmt=fmt)
+    color = gs.greedy_coloring(A)
+    b = uniform_vector(A.n_rows, seed=4)
+    x0 = uniform_vector(A.n_rows, seed=5)
+    for sweeps in (1, 3):
+        got = run(M, b, x0, sweeps)
+        ref = gs.symgs(A, b, x0, color, sweeps)
+        assert close(got, ref, b, x0)
+    assert np.array_equal(run(M, b, x0, 0), x0)  # no sweep: x untouched
+
+
+def test_full_size_104():
+    """The 104^3 stencil: the parity coloring, and one sweep from x = 0 equal
+    to the oracle's (the same launch the benchmark times)."""
+    say("case: symgs 104^3")
+    A = stencil27(104, 104, 104)
+    M = compress(A, fmt="DIT")
+    nc, col = M.colors()
+    assert nc == 8 and np.array_equal(col.cpu().numpy(), parity_coloring(104, 104, 104))
+    b = uniform_vector(A.n_rows, seed=6)
+    x0 = np.zeros(A.n_rows)
+    got = run(M, b, x0)
+    ref = gs.symgs(A, b, x0, parity_coloring(104, 104, 104))
+    assert close(got, ref, b)
+
+
+def test_ditv_equals_dit():
+    say("case: symgs DITV vs DIT")
+    A = stencil27(20, 18, 16)
+    b = uniform_vector(A.n_rows, seed=7)
+    x0 = uniform_vector(A.n_rows, seed=8)
+    assert np.array_equal(run(compress(A, fmt="DITV"), b, x0, 2), run(compress(A, fmt="DIT"), b, x0, 2))
+
+
+def test_bad_inputs_are_rejected():
+    say("case: symgs errors")
+    torch = torch_mod()
+    P = lib()
+    # a row without its diagonal entry
+    A = stencil27(4, 4, 4)
+    keep = np.ones(A.nnz, dtype=bool)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    keep[np.flatnonzero((rows == 5) & (A.col == 5))] = False
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=A.n_rows))])
+    B = CSR(A.n_rows, A.n_cols, rp, A.col[keep], A.val[keep])
+    M = compress(B, fmt="DIT")
+    z = torch.zeros(B.n_rows, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.SpmvcError):
+        M.symgs(z, z.clone())
+    # a non-square matrix
+    C = CSR(2, 3, np.array([0, 2, 3]), np.array([0, 2, 1], dtype=np.int32), np.array([1.0, 2.0, 3.0]))
+    Mc = compress(C, fmt="DIT")
+    with pytest.raises(P.SpmvcError):
+        Mc.symgs(torch.zeros(2, dtype=torch.float64, device="cuda"))
+    # negative sweeps
+    M2 = compress(A, fmt="DIT")
+    with pytest.raises(P.SpmvcError):
+        M2.symgs(z, z.clone(), sweeps=-1)
