@@ -259,6 +259,22 @@ def main():
     log(f"[bench] DITV: {ditv['launch_us_mean']} us, {ditv['gflops']} Gflops, {ditv['bytes_per_row']} B/row")
     del DV
 
+    # multicolor symmetric Gauss-Seidel, one sweep (colors forward, then backward): DIT and ELL
+    bgs = torch.from_numpy(uniform_vector(n, seed=6)).to(dev)
+    xgs = torch.zeros(n, dtype=torch.float64, device=dev)
+    n_colors = D.colors()[0]
+    E.colors()
+    D.symgs(bgs, xgs)
+    E.symgs(bgs, xgs)
+    g_dit = time_batch(lambda: D.symgs(bgs, xgs), max(10, args.steps // 10), torch)
+    g_ell = time_batch(lambda: E.symgs(bgs, xgs), max(10, args.steps // 10), torch)
+    symgs = {"colors": n_colors, "launches_per_sweep": 2 * n_colors,
+             "dit_us": round(g_dit * 1000, 3), "dit_gflops": round(4.0 * nnz / (g_dit * 1e-3) / 1e9, 1),
+             "ell_us": round(g_ell * 1000, 3), "ell_gflops": round(4.0 * nnz / (g_ell * 1e-3) / 1e9, 1),
+             "speedup_vs_ell": round(g_ell / g_dit, 3)}
+    log(f"[bench] SymGS sweep: DIT {symgs['dit_us']} us, ELL {symgs['ell_us']} us ({n_colors} colors)")
+    del bgs, xgs
+
     # block SpMV, 8 right-hand sides (row-interleaved), same matrix: DIT and ELL
     X8 = torch.from_numpy(np.random.default_rng(5).uniform(-1.0, 1.0, (n, 8))).to(dev)
     Y8 = torch.empty((n, 8), dtype=torch.float64, device=dev)
@@ -334,6 +350,7 @@ def main():
         "block_spmv": block8,
         "dit_f32": {"launch_us_mean": round(f_mean * 1000, 3), "gflops": round(2.0 * nnz / (f_mean * 1e-3) / 1e9, 2)},
         "ditv": ditv,
+        "symgs": symgs,
         "irregular": irregular,
         "cg": cg,
         "batched_cg": batched,
