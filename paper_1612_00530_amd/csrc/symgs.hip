@@ -229,9 +229,15 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
     const GsArgs a = gs_args(M);
     const int C = M->gs_n_colors;
     const int32_t *rows = M->gs_rows.as<int32_t>();
+    int last = -1;  // color of the previous launch
     for (int sw = 0; sw < sweeps; ++sw)
         for (int q = 0; q < 2 * C; ++q) {
             const int c = q < C ? q : 2 * C - 1 - q;  // colors forward, then backward
+            // Updating one color twice in a row repeats the same arithmetic on
+            // unchanged neighbours (a color's rows read only other colors), so
+            // the turn at the end of each half-sweep is launched once.
+            if (c == last) continue;
+            last = c;
             const int64_t r0 = M->gs_off[c], cnt = M->gs_off[c + 1] - r0;
             if (cnt == 0) continue;
             k_symgs_color<<<grid_for(cnt, kGsThreads, 0x7fffffff), kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
