@@ -17,7 +17,8 @@
 // k_symgs_color: one thread per row of the color; the row is decoded from
 // the handle's own format (ELL, DT, DIT/DITV, raw values, escape rows) and
 // x is gathered straight from global memory, since the rows of a color are
-// spread over the whole grid.
+// spread over the whole grid.  k_symgs_dit: the same for DIT/DITV stencil-like
+// matrices, with all of a row's gathers in flight at once.
 #include <algorithm>
 #include <vector>
 
@@ -118,6 +119,47 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int3
         else
             s = fma(v, x[j], s);
     });
+    x[i] = (b[i] - s) / d;
+}
+
+// The DIT form for a value table of at most two entries, no raw values and
+// patterns of at most MAXW entries (the stencil case), without branches on
+// the row's length: every lane issues its MAXW gathers at once (entries past
+// the row's length read x_i and take weight 0), then the FMAs.  The generic
+// loop above waits for each pattern offset and each gather in turn.
+template <int MAXW>
+__global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows, int64_t n,
+                                                          const double *__restrict__ b, double *x) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = rows[t];
+    const uint32_t id = gs_id(a, i);
+    double s = 0.0, d = 0.0;
+    if (id == (a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu))) {
+        gs_visit(a, i, [&](double v, int64_t j) {
+            if (j == i)
+                d = v;
+            else
+                s = fma(v, x[j], s);
+        });
+    } else {
+        const int32_t *pr = a.pat_off + static_cast<int64_t>(id) * a.width;
+        const int len = a.pat_len[id];
+        const int t0 = a.K >= 2 ? (a.pat_T ? a.pat_T[static_cast<int64_t>(id) * a.K] : a.T[i]) : len;
+        int32_t off[MAXW];
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) off[k] = k < a.width ? pr[k] : 0;
+        double xv[MAXW];
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) xv[k] = x[i + (k < len ? off[k] : 0)];
+#pragma unroll
+        for (int k = 0; k < MAXW; ++k) {
+            const double v = k < len ? (k < t0 ? a.V[0] : a.V[1]) : 0.0;
+            const bool diag = k < len && off[k] == 0;
+            d = diag ? v : d;
+            s = diag ? s : fma(v, xv[k], s);
+        }
+    }
     x[i] = (b[i] - s) / d;
 }
 
@@ -229,6 +271,7 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
     const GsArgs a = gs_args(M);
     const int C = M->gs_n_colors;
     const int32_t *rows = M->gs_rows.as<int32_t>();
+    const bool dit27 = M->fmt == SPMVC_FMT_DIT && M->raw_elems == 0 && M->K <= 2 && M->width <= 27 && M->P > 0;
     int last = -1;  // color of the previous launch
     for (int sw = 0; sw < sweeps; ++sw)
         for (int q = 0; q < 2 * C; ++q) {
@@ -240,7 +283,11 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
             last = c;
             const int64_t r0 = M->gs_off[c], cnt = M->gs_off[c + 1] - r0;
             if (cnt == 0) continue;
-            k_symgs_color<<<grid_for(cnt, kGsThreads, 0x7fffffff), kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
+            const unsigned g = grid_for(cnt, kGsThreads, 0x7fffffff);
+            if (dit27)
+                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
+            else
+                k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
             SPMVC_CHECK_LAUNCH();
         }
 }
