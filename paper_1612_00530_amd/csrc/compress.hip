@@ -1,10 +1,12 @@
-// GPU compressor and decompressor for the ELL, DT and DIT formats.
+// GPU compressor and decompressor for the ELL, DT, DIT and DITV formats.
 //
 // The steps follow Section V: (1) scan all values and build the ascending
 // value table V; (2) sort each row's entries by value, ties by column (the
 // sorted column list S_i); (3) record each value's run end (terminal indices
 // T_i); (4) turn columns into displacements from the diagonal; (5) register
-// each row's displacement sequence in a pattern table and store its type ID.
+// each row's displacement sequence in a pattern table and store its type ID;
+// (6, DITV) register T_i with the sequence as well, so the row keeps only the
+// ID and each pattern its T.
 //
 // Everything that touches per-entry or per-row data runs in the kernels
 // below.  The host only sizes and allocates, reads back a handful of scalars,

@@ -1,10 +1,12 @@
-// SpMV kernels: y = A x (Eq. 1) over the ELL, DT and DIT encodings.
+// SpMV kernels: y = A x (Eq. 1) over the ELL, DT, DIT and DITV encodings.
 //
 // Layout (all streams column-major over rows, so a wavefront's 64 lanes read 64
 // consecutive rows of one slot with one coalesced load):
 //   ELL  col/val [width][n_pad]            (Section IV-B baseline, 12 B per slot)
 //   DT   S [width][n_pad], T u8 [K][n_pad]  (value table + sorted columns, Fig. 1)
 //   DIT  ID [n_pad], T u8 [K][n_pad]        (pattern ID + terminal indices)
+//   DITV ID [n_pad]                         (values registered in the table too:
+//                                            T per pattern, pat_T [P][K]; row_T)
 // In the single-vector kernels one lane owns one row.  A row's entries are
 // consumed in the canonical order of Section V: first all entries of V[0]
 // (positions < T[0]), then V[1], ..., then the raw FP64 entries.
