@@ -476,10 +476,16 @@ def test_empty_matrix_and_single_row():
     torch = torch_mod()
     P = lib()
     A = CSR(3, 5, np.zeros(4, dtype=np.int64), np.zeros(0, np.int32), np.zeros(0))
-    M = P.compress(torch.zeros(4, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
-                   torch.zeros(0, dtype=torch.float64, device="cuda"), n_cols=5)
-    y = M.spmv(torch.ones(5, dtype=torch.float64, device="cuda"))
-    assert torch.all(y == 0)
+    for fmt in FORMATS:  # every row empty
+        M = P.compress(torch.zeros(4, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
+                       torch.zeros(0, dtype=torch.float64, device="cuda"), n_cols=5, fmt=fmt)
+        y = M.spmv(torch.ones(5, dtype=torch.float64, device="cuda"))
+        assert torch.all(y == 0)
+        assert roundtrip_ok(M, A)
+    for fmt in ("DIT", "DITV"):  # no rows at all
+        M = P.compress(torch.zeros(1, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
+                       torch.zeros(0, dtype=torch.float64, device="cuda"), n_cols=4, fmt=fmt)
+        assert M.spmv(torch.ones(4, dtype=torch.float64, device="cuda")).numel() == 0
     B = CSR(1, 66, [0, 5], [45, 49, 50, 51, 65], [-1.0, -1.0, 26.0, -1.0, -1.0])
     for fmt in FORMATS:
         M = compress(B, fmt=fmt, min_pattern_rows=1)
