@@ -143,6 +143,7 @@ struct spmvc_matrix_s {
     int32_t gs_ready = 0, gs_n_colors = 0;
     std::vector<int64_t> gs_off;          // rows of color c: gs_rows[gs_off[c] .. gs_off[c+1])
     spmvc::DevBuf gs_rows, gs_color;      // int32 [n]: rows by color (ascending); color of each row
+    spmvc::DevBuf gs_meta;                // DIT: uint32 [n] per entry of gs_rows: (T_i[0] << 24) | pattern ID
     int32_t block_rows = 256;   // spmv_block: rows per block
     int32_t n_xcd = 8;          // XCDs of the device (block-to-tile mapping)
     int32_t n_cu = 256;         // compute units of the device (grid sizing)

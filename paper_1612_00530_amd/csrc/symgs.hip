@@ -128,14 +128,18 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int3
 // the row's length read x_i and take weight 0), then the FMAs.  The generic
 // loop above waits for each pattern offset and each gather in turn.
 template <int MAXW>
-__global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows, int64_t n,
+__global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows,
+                                                          const uint32_t *__restrict__ meta, int64_t n,
                                                           const double *__restrict__ b, double *x) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
     if (t >= n) return;
     const int64_t i = rows[t];
-    const uint32_t id = gs_id(a, i);
+    // the row's pattern ID and T_i[0], stored in color order: read alongside
+    // the row index rather than after it
+    const uint32_t mw = meta[t];
+    const uint32_t id = mw & 0xFFFFFFu;
     double s = 0.0, d = 0.0;
-    if (id == (a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu))) {
+    if (id == 0xFFFFFFu) {  // escape row
         gs_visit(a, i, [&](double v, int64_t j) {
             if (j == i)
                 d = v;
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
     } else {
         const int32_t *pr = a.pat_off + static_cast<int64_t>(id) * a.width;
         const int len = a.pat_len[id];
-        const int t0 = a.K >= 2 ? (a.pat_T ? a.pat_T[static_cast<int64_t>(id) * a.K] : a.T[i]) : len;
+        const int t0 = a.K >= 2 ? static_cast<int>(mw >> 24) : len;
         int32_t off[MAXW];
 #pragma unroll
         for (int k = 0; k < MAXW; ++k) off[k] = k < a.width ? pr[k] : 0;
@@ -161,6 +165,22 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
         }
     }
     x[i] = (b[i] - s) / d;
+}
+
+// meta[t] = (T_i[0] << 24) | ID of row rows[t] (ID 0xFFFFFF: escape row).
+__global__ void k_gs_meta(GsArgs a, const int32_t *__restrict__ rows, int64_t n, uint32_t *meta) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = rows[t];
+    const uint32_t id = gs_id(a, i);
+    const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+    if (id == esc) {
+        meta[t] = 0xFFFFFFu;
+        return;
+    }
+    uint32_t t0 = 0;
+    if (a.K >= 2) t0 = a.pat_T ? a.pat_T[static_cast<int64_t>(id) * a.K] : a.T[i];
+    meta[t] = (t0 << 24) | id;
 }
 
 GsArgs gs_args(const spmvc_matrix_s *M) {
@@ -187,6 +207,13 @@ GsArgs gs_args(const spmvc_matrix_s *M) {
     a.n_esc = M->n_esc;
     for (int c = 0; c < kMaxK; ++c) a.V[c] = M->V[c];
     return a;
+}
+
+// The branch-free DIT kernel applies: DIT/DITV, at most two table values, no
+// raw values, patterns of at most 27 entries, IDs below 2^24.
+bool gs_dit27(const spmvc_matrix_s *M) {
+    return M->fmt == SPMVC_FMT_DIT && M->raw_elems == 0 && M->K <= 2 && M->width <= 27 && M->P > 0 &&
+           M->P < 0xFFFFFF;
 }
 
 }  // namespace
@@ -264,6 +291,13 @@ void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
         SPMVC_HIP(hipStreamSynchronize(s));
     }
     M->gs_n_colors = n_colors;
+    if (gs_dit27(M) && n > 0) {
+        M->gs_meta.alloc(sizeof(uint32_t) * n);
+        k_gs_meta<<<grid_for(n, kGsThreads, 0x7fffffff), kGsThreads, 0, s>>>(gs_args(M), M->gs_rows.as<int32_t>(), n,
+                                                                            M->gs_meta.as<uint32_t>());
+        SPMVC_CHECK_LAUNCH();
+        SPMVC_HIP(hipStreamSynchronize(s));
+    }
     M->gs_ready = 1;
 }
 
@@ -271,7 +305,7 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
     const GsArgs a = gs_args(M);
     const int C = M->gs_n_colors;
     const int32_t *rows = M->gs_rows.as<int32_t>();
-    const bool dit27 = M->fmt == SPMVC_FMT_DIT && M->raw_elems == 0 && M->K <= 2 && M->width <= 27 && M->P > 0;
+    const bool dit27 = gs_dit27(M);
     int last = -1;  // color of the previous launch
     for (int sw = 0; sw < sweeps; ++sw)
         for (int q = 0; q < 2 * C; ++q) {
@@ -285,7 +319,7 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
             if (cnt == 0) continue;
             const unsigned g = grid_for(cnt, kGsThreads, 0x7fffffff);
             if (dit27)
-                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
+                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rows + r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x);
             else
                 k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
             SPMVC_CHECK_LAUNCH();
