@@ -32,7 +32,6 @@ namespace spmvc {
 namespace {
 
 constexpr int kT = 256;     // threads per block = rows per tile
-constexpr int kMaxRhs = 16;
 
 struct SysDesc {
     int64_t row0, n;   // first global row, rows
@@ -314,10 +313,9 @@ __device__ __forceinline__ void lds_load16(const void *g, void *lds) {
 
 // Four entries of a row's (pattern, window) record against the x window: four
 // 16-byte x reads in flight, then four weighted FMAs (value V[0] for
-// canonical index < t0, else V[1]).  In the last group (TAIL) the entries
-// past `rem` are padding: they read window row 0 and take weight 0.
-template <int NRB, bool TAIL>
-__device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, int t0, int rem, double v0, double v1,
+// canonical index < t0, else V[1]).
+template <int NRB>
+__device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, int t0, double v0, double v1,
                                            double &a0, double &a1) {
     const uint32_t ent[4] = {e.x, e.y, e.z, e.w};
     double2 xv[4];
@@ -325,8 +323,7 @@ __device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, i
     for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const double2 *>(xrow + (ent[j] & 0xFFFFu) * NRB);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
-        if (TAIL && j > 0) wgt = j < rem ? wgt : 0.0;
+        const double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
         a0 = fma(wgt, xv[j].x, a0);
         a1 = fma(wgt, xv[j].y, a1);
     }
@@ -336,9 +333,9 @@ __device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, i
 // rows of one x window at a time -- whole rows of the row-interleaved block,
 // a contiguous range -- are copied into LDS, and every row adds the products
 // of its entries that fall in that window (per pattern and window a record of
-// the count and the zero-padded entries, read four entries at a time).  One
-// lane per right-hand-side pair, LPR lanes per row; each product is weighted
-// by its value-table entry as it is added.
+// the count and the entries, read four entries at a time, the last cnt mod 4
+// one by one).  One lane per right-hand-side pair, LPR lanes per row; each
+// product is weighted by its value-table entry as it is added.
 template <int LPR>
 __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restrict__ Pin,
                                                   double *__restrict__ Qout, double *part, int with_dot) {
@@ -408,10 +405,16 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
             const int cnt = static_cast<int>(rec[0].x);
             int k0 = 0;
             for (; k0 + 4 <= cnt; k0 += 4)
-                bwin_group<NR * 8, false>(rec[1 + (k0 >> 2)], xrow, t0v[ps], 4, v0, v1, acc[ps][0], acc[ps][1]);
-            if (k0 < cnt)
-                bwin_group<NR * 8, true>(rec[1 + (k0 >> 2)], xrow, t0v[ps], cnt - k0, v0, v1, acc[ps][0],
-                                         acc[ps][1]);
+                bwin_group<NR * 8>(rec[1 + (k0 >> 2)], xrow, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
+            // the last cnt mod 4 entries one at a time (no padded work)
+            const uint32_t *recw = reinterpret_cast<const uint32_t *>(rec) + 4;
+            for (; k0 < cnt; ++k0) {
+                const uint32_t e = recw[k0];
+                const double2 xv = *reinterpret_cast<const double2 *>(xrow + (e & 0xFFFFu) * (NR * 8));
+                const double wgt = static_cast<int>(e >> 16) < t0v[ps] ? v0 : v1;
+                acc[ps][0] = fma(wgt, xv.x, acc[ps][0]);
+                acc[ps][1] = fma(wgt, xv.y, acc[ps][1]);
+            }
         }
     }
     double dotc[2] = {0.0, 0.0};
@@ -503,7 +506,7 @@ template <int LPR> __global__ __launch_bounds__(kT) void k_bstart(Batch b) {
     double acc = 0.0;
     SPMVC_TILE_ELEMS(const double v = b.B[g]; b.X[g] = 0.0; b.R[g] = v; b.P[g] = v; acc += v * v;)
     const double t = rhs_sum<LPR>(acc);
-    if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
+    if (static_cast<int>(threadIdx.x) < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kT) void k_bstart_fin(Batch b) {
@@ -586,7 +589,7 @@ template <int LPR> __global__ __launch_bounds__(kT) void k_bupdate(Batch b) {
         })
     }
     const double t = rhs_sum<LPR>(acc);
-    if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
+    if (static_cast<int>(threadIdx.x) < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 // rho', convergence, beta
@@ -667,7 +670,7 @@ template <int LPR> __global__ __launch_bounds__(kT) void k_bresid(Batch b) {
     double acc = 0.0;
     SPMVC_TILE_ELEMS(const double v = b.B[g] - b.Q[g]; acc += v * v;)
     const double t = rhs_sum<LPR>(acc);
-    if (threadIdx.x < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
+    if (static_cast<int>(threadIdx.x) < nr) b.part[static_cast<int64_t>(tile) * nr + threadIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kT) void k_bresid_fin(Batch b, double *out) {
