@@ -785,7 +785,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, con
 struct D2 {
     double x, y;
 };
-__device__ __forceinline__ D2 operator+(D2 a, D2 b) { return D2{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ D2 &operator+=(D2 &a, D2 b) {
     a.x += b.x;
     a.y += b.y;
@@ -889,10 +888,9 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
 // ---- block SpMV, whole right-hand-side rows in LDS, one window at a time ----------
 // Four entries of a row's (pattern, window) record against the x window: four
 // 16-byte x reads in flight, then four weighted FMAs (value V[0] for
-// canonical index < t0, else V[1]).  In the last group (TAIL) the entries
-// past `rem` are padding: they read window row 0 and take weight 0.
-template <int NRB, bool TAIL>
-__device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, int t0, int rem, double v0, double v1,
+// canonical index < t0, else V[1]).
+template <int NRB>
+__device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, int t0, double v0, double v1,
                                           double &a0, double &a1) {
     const uint32_t ent[4] = {e.x, e.y, e.z, e.w};
     double2 xv[4];
@@ -900,8 +898,7 @@ __device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, in
     for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const double2 *>(xrow + (ent[j] & 0xFFFFu) * NRB);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
-        if (TAIL && j > 0) wgt = j < rem ? wgt : 0.0;
+        const double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
         a0 = ::fma(wgt, xv[j].x, a0);
         a1 = ::fma(wgt, xv[j].y, a1);
     }
@@ -909,16 +906,23 @@ __device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, in
 
 // The products of one row's entries that fall in the current x window, for
 // this lane's pair of right-hand sides: `rec` is the row's (pattern, window)
-// record (count, then the zero-padded entries from word 4), `xrow` the lane's
-// element pair in window row 0, NRB the bytes of a window row.  One 16-byte
-// table read per four entries.
+// record (count, then the entries from word 4), `xrow` the lane's element
+// pair in window row 0, NRB the bytes of a window row.  One 16-byte table
+// read per four entries; the last cnt mod 4 entries one at a time.
 template <int NRB>
 __device__ __forceinline__ void win_row(const uint4 *rec, const unsigned char *xrow, int t0, double v0, double v1,
                                         double &a0, double &a1) {
     const int cnt = static_cast<int>(rec[0].x);
     int k0 = 0;
-    for (; k0 + 4 <= cnt; k0 += 4) win_group<NRB, false>(rec[1 + (k0 >> 2)], xrow, t0, 4, v0, v1, a0, a1);
-    if (k0 < cnt) win_group<NRB, true>(rec[1 + (k0 >> 2)], xrow, t0, cnt - k0, v0, v1, a0, a1);
+    for (; k0 + 4 <= cnt; k0 += 4) win_group<NRB>(rec[1 + (k0 >> 2)], xrow, t0, v0, v1, a0, a1);
+    const uint32_t *recw = reinterpret_cast<const uint32_t *>(rec) + 4;
+    for (; k0 < cnt; ++k0) {
+        const uint32_t e = recw[k0];
+        const double2 xv = *reinterpret_cast<const double2 *>(xrow + (e & 0xFFFFu) * NRB);
+        const double wgt = static_cast<int>(e >> 16) < t0 ? v0 : v1;
+        a0 = ::fma(wgt, xv.x, a0);
+        a1 = ::fma(wgt, xv.y, a1);
+    }
 }
 
 // nrhs = 2 * LPR FP64 right-hand sides, row-interleaved and unpadded.  A block
