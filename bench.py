@@ -414,6 +414,7 @@ def run_batched(P, torch, dev, n_sys):
                      "relres_true_max": max(q["relres_true"] for q in stats)}
         log(f"[bench] batched {name}: {t * 1000:.1f} ms, iters {min(its)}..{max(its)}")
     res["speedup_graph_vs_sequential"] = round(res["sequential"]["seconds"] / res["graph"]["seconds"], 2)
+    res["tuned_spmv"] = P.batched_config()  # form: 0 window-phased, 1 lane groups (rhs pairs), 2 lane groups
     return res
 
 

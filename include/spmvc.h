@@ -261,6 +261,22 @@ spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void *stream,
                        int32_t *best_rows_per_block, int32_t *best_lds, double *best_us);
 
 /*
+ * The SpMV configuration the last batched cg_solve in this process chose
+ * (host outputs): *form 0 = window-phased (whole right-hand-side rows of one x
+ * window at a time in LDS), 1 = lane groups with two right-hand sides per
+ * lane, 2 = lane groups with one per lane; *chunk = consecutive row tiles
+ * handed to one XCD; *us_per_spmv = its time per batched SpMV at tuning.
+ * A batched solve times every applicable (form, chunk in {8, 32, 128}) on its
+ * own batch before iterating and keeps the fastest; the choice is cached per
+ * batch shape (systems, rows, tiles, nrhs, longest pattern), so repeated
+ * solves of one batch sum in the same order.  The environment variable
+ * SPMVC_BATCHED_SPMV="form,chunk" fixes the configuration instead (a form
+ * that does not apply falls back to the next).  *form = -1 before any
+ * batched solve.
+ */
+spmvc_status spmvc_batched_config(int32_t *form, int32_t *chunk, double *us_per_spmv);
+
+/*
  * Symmetric Gauss-Seidel, the other kernel of the HPCG iteration (Section
  * III, Table I: SymGS beside SpMV), over the compressed matrix: `sweeps`
  * times, the rows are updated with x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii,

@@ -33,7 +33,7 @@ ARR = {
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
-    "spmv_free", "spmvc_status_string", "spmvc_last_error",
+    "spmvc_batched_config", "spmv_free", "spmvc_status_string", "spmvc_last_error",
 ]
 
 
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
                               ctypes.POINTER(ctypes.c_double)]
     lib.spmv_symgs.argtypes = [P, P, P, i32, P]
     lib.spmv_colors.argtypes = [P, ctypes.POINTER(i32), P, P]
+    lib.spmvc_batched_config.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.spmv_free.argtypes = [P]
     lib.spmv_free.restype = None
     lib.spmvc_status_string.argtypes = [i32]
@@ -109,7 +110,7 @@ def load(path: str = LIB_PATH):
     lib.spmvc_last_error.restype = ctypes.c_char_p
     for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
                  "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs",
-                 "spmv_colors"]:
+                 "spmv_colors", "spmvc_batched_config"]:
         getattr(lib, name).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -318,3 +319,11 @@ def cg_solve(mats, bs, xs=None, rtol=1e-10, max_iter=10000, mode=0, inner_rtol=1
     out = [{"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status,
             "relres_true": s.relres_true, "relres_recursive": s.relres_recursive} for s in stats]
     return st, xs, out
+
+
+def batched_config():
+    """The SpMV configuration the last batched cg_solve chose: {"form", "chunk", "us"}
+    (form 0 window-phased, 1 lane groups with rhs pairs, 2 lane groups; -1 before any)."""
+    f, c, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load().spmvc_batched_config(ctypes.byref(f), ctypes.byref(c), ctypes.byref(us)))
+    return {"form": f.value, "chunk": c.value, "us": us.value}

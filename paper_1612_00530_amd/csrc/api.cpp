@@ -214,6 +214,14 @@ spmvc_status spmv_symgs(spmvc_matrix A, const double *b, double *x, int32_t swee
     });
 }
 
+spmvc_status spmvc_batched_config(int32_t *form, int32_t *chunk, double *us_per_spmv) {
+    return guarded([&]() -> spmvc_status {
+        if (!form || !chunk || !us_per_spmv) return fail(SPMVC_EINVAL, "null argument");
+        batched_last_tune(form, chunk, us_per_spmv);
+        return SPMVC_OK;
+    });
+}
+
 spmvc_status spmv_colors(spmvc_matrix A, int32_t *n_colors, int32_t *color, void *stream) {
     return guarded([&]() -> spmvc_status {
         if (!A || !n_colors) return fail(SPMVC_EINVAL, "null argument");

@@ -26,6 +26,12 @@
 #include <algorithm>
 #include <cmath>
 
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace spmvc {
@@ -81,6 +87,11 @@ struct Batch {
     int32_t win_x_bytes;  // window-phased SpMV: LDS bytes of the largest window (0: not used)
     int32_t win_tab_bytes; // ... and of the largest entry-list table
     int32_t n_xcd;      // XCDs the blocks are dispatched over (tile mapping of the SpMV)
+    // SpMV configuration (tuned per batch shape): 0 = window-phased (where it
+    // applies), 1 = lane groups with two right-hand sides per lane (16-byte
+    // gathers, even nrhs), 2 = lane groups with one per lane; tiles per XCD chunk
+    int32_t spmv_form;
+    int32_t chunk;
 };
 
 __device__ __forceinline__ uint32_t load_id(const void *ids, int id_bytes, int64_t row) {
@@ -169,24 +180,25 @@ __device__ __forceinline__ void gather_row(const int32_t *__restrict__ pat, int 
 // Q = A_s P for the tile's rows; per-tile partials of p.q for each rhs.
 // Rows with at most MAXW entries take the unrolled gather; longer ones a loop.
 // Blocks are dispatched round-robin over the XCDs.  Tiles are handed out in
-// chunks of kChunk consecutive tiles, chunk k to XCD k % n_xcd: the rows a
-// tile gathers from (adjacent lines and planes of its grid) mostly lie in its
-// own chunk and hit that XCD's L2, while every system's chunks stay spread
-// over all XCDs, so the work stays balanced as systems finish.  Tiles past the
-// last whole round of chunks keep their own index.
-constexpr int kChunk = 32;
+// chunks of `chunk` consecutive tiles (tuned: 8, 32 or 128), chunk k to XCD
+// k % n_xcd: the rows a tile gathers from (adjacent lines and planes of its
+// grid) mostly lie in its own chunk and hit that XCD's L2, while every
+// system's chunks stay spread over all XCDs, so the work stays balanced as
+// systems finish.  Tiles past the last whole round of chunks keep their own
+// index.
 
 // T_i[c] of a non-escape row of system d: its own T byte, or for DITV its pattern's.
 __device__ __forceinline__ int sys_T(const SysDesc &d, int c, int64_t lrow, uint32_t id) {
     return d.pat_T ? d.pat_T[static_cast<int64_t>(id) * d.K + c] : d.T[static_cast<int64_t>(c) * d.n_pad + lrow];
 }
 
-__device__ __forceinline__ int chunk_tile(unsigned bid, unsigned nb, int n_xcd) {
-    const unsigned round = static_cast<unsigned>(kChunk) * n_xcd;
+__device__ __forceinline__ int chunk_tile(unsigned bid, unsigned nb, int n_xcd, int chunk) {
+    const unsigned ch = static_cast<unsigned>(chunk);
+    const unsigned round = ch * n_xcd;
     const unsigned full = nb / round * round;
     if (n_xcd <= 1 || bid >= full) return static_cast<int>(bid);
     const unsigned x = bid % n_xcd, j = bid / n_xcd;
-    return static_cast<int>(((j / kChunk) * n_xcd + x) * kChunk + j % kChunk);
+    return static_cast<int>(((j / ch) * n_xcd + x) * ch + j % ch);
 }
 
 // VEC = 2 when nrhs is even: each lane takes two adjacent right-hand sides
@@ -195,7 +207,7 @@ template <int LPR, int MAXW, int VEC>
 __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict__ Pin, double *__restrict__ Qout,
                                               double *part, int with_dot) {
     extern __shared__ int32_t pat_s[];
-    const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd);
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd, b.chunk);
     const int s = b.tile_sys[tile];
     if (!b.sys_active[s]) return;  // uniform per block
     const SysDesc &d = b.sys[s];
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
     extern __shared__ __align__(16) unsigned char wsm[];
     constexpr int NR = 2 * LPR;
     constexpr int PASSES = kT / (kT / LPR);  // = LPR
-    const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd);
+    const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd, b.chunk);
     const int s = b.tile_sys[tile];
     if (!b.sys_active[s]) return;  // uniform per block
     const SysDesc &d = b.sys[s];
@@ -723,7 +735,7 @@ constexpr int kTabLdsInts = 4096;  // pattern tables up to 16 KB are copied to L
 
 void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles);
-    if (b.win_x_bytes > 0) {
+    if (b.spmv_form == 0 && b.win_x_bytes > 0) {
         const size_t wsh = static_cast<size_t>(b.win_x_bytes) + static_cast<size_t>(b.win_tab_bytes);
         if (b.nrhs == 2)
             k_bspmv_win<1><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
@@ -735,7 +747,7 @@ void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot,
     }
     const size_t sh = b.tab_lds ? sizeof(int32_t) * static_cast<size_t>(b.tab_ints) : 0;
     // two right-hand sides per lane when every row's block starts 16-byte aligned
-    const bool pairs = b.nrhs % 2 == 0;
+    const bool pairs = b.nrhs % 2 == 0 && b.spmv_form != 2;
     if (b.max_width <= 28) {
         if (pairs)
             SPMVC_BSPMV_LAUNCH(28, 2, g, sh, s, b, Pin, Qout, b.part, with_dot);
@@ -749,6 +761,66 @@ void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot,
     }
 }
 
+// Tuned SpMV configurations, per batch shape (systems, rows, tiles, nrhs,
+// longest pattern, first and last system's rows); the last one chosen.
+struct BatchTune {
+    int32_t form, chunk;
+    double us;
+};
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, BatchTune> g_tune_cache;
+BatchTune g_last_tune{-1, 0, 0.0};
+
+// Times each candidate SpMV configuration on the batch (P already holds the
+// right-hand sides; Q is scratch; no partials written) and keeps the fastest:
+// forms {window-phased, lane-group pairs, lane-group singles} that apply x
+// chunks {8, 32, 128}.  The choice is cached per batch shape, so repeated
+// solves of one batch take the same summation order.
+BatchTune tune_bspmv(Batch &b, const std::vector<int64_t> &key, hipStream_t s) {
+    // SPMVC_BATCHED_SPMV="form,chunk" fixes the configuration (tests, experiments)
+    if (const char *env = std::getenv("SPMVC_BATCHED_SPMV")) {
+        int f = -1, ch = 0;
+        if (std::sscanf(env, "%d,%d", &f, &ch) == 2 && f >= 0 && f <= 2 && ch >= 1 && ch <= 4096) {
+            if (f == 0 && b.win_x_bytes == 0) f = b.nrhs % 2 == 0 ? 1 : 2;
+            if (f == 1 && b.nrhs % 2 != 0) f = 2;
+            return {f, ch, 0.0};
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    std::vector<int> forms;
+    if (b.win_x_bytes > 0) forms.push_back(0);
+    if (b.nrhs % 2 == 0) forms.push_back(1);
+    forms.push_back(2);
+    hipEvent_t e0, e1;
+    SPMVC_HIP(hipEventCreate(&e0));
+    SPMVC_HIP(hipEventCreate(&e1));
+    BatchTune best{forms[0], 32, 1e300};
+    for (int f : forms)
+        for (int ch : {8, 32, 128}) {
+            b.spmv_form = f;
+            b.chunk = ch;
+            launch_bspmv(b, b.P, b.Q, 0, s);  // warm
+            SPMVC_HIP(hipEventRecord(e0, s));
+            constexpr int kReps = 3;
+            for (int r = 0; r < kReps; ++r) launch_bspmv(b, b.P, b.Q, 0, s);
+            SPMVC_HIP(hipEventRecord(e1, s));
+            SPMVC_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            SPMVC_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1000.0 * ms / kReps;
+            if (us < best.us) best = {f, ch, us};
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
+}
+
 void record_iteration(const Batch &b, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(b.n_tiles), ns = static_cast<unsigned>(b.n_sys);
     launch_bspmv(b, b.P, b.Q, 1, s);
@@ -759,6 +831,14 @@ void record_iteration(const Batch &b, hipStream_t s) {
 }
 
 }  // namespace
+
+// The SpMV configuration the last batched solve used (form, chunk, microseconds per launch).
+void batched_last_tune(int32_t *form, int32_t *chunk, double *us) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    *form = g_last_tune.form;
+    *chunk = g_last_tune.chunk;
+    *us = g_last_tune.us;
+}
 
 // Is the batched solver able to take these matrices (DIT, value table <= 2, no raw values)?
 bool batched_supported(const spmvc_matrix *A, int n_sys) {
@@ -860,13 +940,15 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         b.tab_ints = std::max(b.tab_ints, sd[q].P * sd[q].width);
     }
     b.tab_lds = b.tab_ints > 0 && b.tab_ints <= kTabLdsInts;
-    // window-phased SpMV when every system has its window plan, nrhs is 2, 4
-    // or 8 and the largest window and table fit the LDS budget
+    // window-phased SpMV when every system has its window plan (or no pattern
+    // at all: then every row is an escape row, taken from global memory), nrhs
+    // is 2, 4 or 8 and the largest window and table fit the LDS budget
     b.win_x_bytes = 0;
     b.win_tab_bytes = 0;
     bool win_ok = nrhs == 2 || nrhs == 4 || nrhs == 8;
     for (int q = 0; q < n_sys && win_ok; ++q) {
         const LdsPlan &pl = A[q]->plan[SPMVC_F64];
+        if (!pl.bw && A[q]->P == 0) continue;
         if (!pl.bw) {
             win_ok = false;
             break;
@@ -896,9 +978,21 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     b.rtol = o.rtol;
     b.max_iter = o.max_iter;
 
+    b.spmv_form = b.win_x_bytes > 0 ? 0 : (nrhs % 2 == 0 ? 1 : 2);
+    b.chunk = 32;
     SPMVC_LPR_LAUNCH(k_bstart, static_cast<unsigned>(n_tiles), st, b);
     k_bstart_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b);
     SPMVC_CHECK_LAUNCH();
+    {
+        // the SpMV configuration for this batch shape (P = the right-hand sides now)
+        const std::vector<int64_t> key{n_sys, n_total, n_tiles, nrhs, b.max_width, sd.front().n, sd.back().n,
+                                       b.win_x_bytes};
+        const BatchTune t = tune_bspmv(b, key, st);
+        b.spmv_form = t.form;
+        b.chunk = t.chunk;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_last_tune = t;
+    }
 
     int32_t *h_active = nullptr;
     SPMVC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_active), sizeof(int32_t), hipHostMallocDefault));

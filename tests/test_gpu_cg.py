@@ -251,7 +251,7 @@ def test_batched_graph_replays_equal_eager():
 
 
 @pytest.mark.parametrize("nrhs", [2, 4, 8])
-def test_batched_window_phased_spmv(nrhs):
+def test_batched_window_phased_spmv(nrhs, monkeypatch):
     """Even nrhs of 2, 4 or 8 take the window-phased batched SpMV (each
     system's windows staged whole-row in LDS).  Systems from a single row of
     tiles to several planes, thin and tiny grids; graph replays equal eager
@@ -259,12 +259,13 @@ def test_batched_window_phased_spmv(nrhs):
     say("case: batched window-phased", nrhs)
     torch = torch_mod()
     P = lib()
-    grids = [(2, 2, 2), (40, 3, 3), (9, 31, 4), (24, 20, 18)]
+    monkeypatch.setenv("SPMVC_BATCHED_SPMV", "0,32")
+    grids = [(2, 2, 2), (40, 3, 3), (9, 31, 4), (24, 20, 18)]  # 2^3: every row an escape row
     mats, As, bs = batched_case(grids, nrhs, seed=7)
     _, x_eager, s_eager = P.cg_solve(mats, bs, nrhs=nrhs, batched=1, check_every=4)
     st, x_graph, s_graph = P.cg_solve(mats, bs, nrhs=nrhs, batched=2, check_every=4)
     torch.cuda.synchronize()
-    assert st == 0
+    assert st == 0 and P.batched_config()["form"] == 0
     for a, b in zip(x_eager, x_graph):
         assert torch.equal(a, b)
     for s, A in enumerate(As):
@@ -321,6 +322,47 @@ def test_batched_ditv_equals_dit(nrhs):
         B = bs[s].cpu().numpy()
         for r in range(nrhs):
             assert oracle.relres(A, B[:, r], X[:, r]) <= 1.5e-10
+
+
+@pytest.mark.parametrize("form,chunk", [(0, 8), (0, 128), (1, 32), (2, 8), (2, 128)])
+def test_batched_spmv_configurations(form, chunk, monkeypatch):
+    """Each batched SpMV configuration the tuner can pick (window-phased, lane
+    groups with right-hand-side pairs or singles; 8 to 128 tiles per XCD
+    chunk), fixed through SPMVC_BATCHED_SPMV: every pair reaches the oracle's
+    tolerance, graph replays equal eager launches, and the configuration is
+    the one reported."""
+    say("case: batched config", form, chunk)
+    torch = torch_mod()
+    P = lib()
+    monkeypatch.setenv("SPMVC_BATCHED_SPMV", f"{form},{chunk}")
+    grids = [(12, 10, 9), (20, 7, 5), (3, 3, 3), (30, 26, 22)]
+    mats, As, bs = batched_case(grids, 8, seed=11)
+    _, x_e, s_e = P.cg_solve(mats, bs, nrhs=8, batched=1, check_every=4)
+    st, x_g, s_g = P.cg_solve(mats, bs, nrhs=8, batched=2, check_every=4)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert P.batched_config()["form"] == form and P.batched_config()["chunk"] == chunk
+    for a, b in zip(x_e, x_g):
+        assert torch.equal(a, b)
+    for s, A in enumerate(As):
+        X = x_g[s].cpu().numpy()
+        B = bs[s].cpu().numpy()
+        for r in range(8):
+            assert s_g[s * 8 + r]["status"] == 0
+            assert oracle.relres(A, B[:, r], X[:, r]) <= 1.5e-10
+
+
+def test_batched_tuner_reports_its_choice(monkeypatch):
+    say("case: batched tuner")
+    torch = torch_mod()
+    P = lib()
+    monkeypatch.delenv("SPMVC_BATCHED_SPMV", raising=False)
+    grids = [(14, 12, 10), (9, 9, 9)]
+    mats, As, bs = batched_case(grids, 4, seed=12)
+    st, _, _ = P.cg_solve(mats, bs, nrhs=4, batched=2)
+    torch.cuda.synchronize()
+    cfg = P.batched_config()
+    assert st == 0 and cfg["form"] in (0, 1, 2) and cfg["chunk"] in (8, 32, 128) and cfg["us"] > 0
 
 
 def test_batched_failures_are_per_pair():
