@@ -301,6 +301,23 @@ spmvc_status spmv_symgs(spmvc_matrix A, const double *b, double *x, int32_t swee
  */
 spmvc_status spmv_colors(spmvc_matrix A, int32_t *n_colors, int32_t *color, void *stream);
 
+/*
+ * Device memory of the library (handle arrays, solver vectors, scratch):
+ * from now on allocated with alloc_fn(bytes, stream, ctx) and released with
+ * free_fn(ptr, stream, ctx) -- e.g. a framework's caching allocator -- instead
+ * of hipMalloc / hipFree.  `stream` is passed as NULL (the null stream): the
+ * memory must be usable on any stream once alloc_fn returns, and the library
+ * frees a buffer only after the work that used it has finished on its stream
+ * (spmv_compress, cg_solve and spmv_colors synchronise; handle arrays are
+ * freed by spmv_free, after which the caller must not have work in flight
+ * on the handle).  alloc_fn returning NULL gives SPMVC_ENOMEM.  Buffers keep
+ * the allocator that made them and are returned to it, so the hooks may be
+ * changed at any time; both NULL restores hipMalloc / hipFree.  alloc_fn and
+ * free_fn must both be set or both be NULL (else SPMVC_EINVAL).  Process-wide.
+ */
+spmvc_status spmvc_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
+                                 void (*free_fn)(void *ptr, void *stream, void *ctx), void *ctx);
+
 void spmv_free(spmvc_matrix A);
 
 const char *spmvc_status_string(int32_t status);

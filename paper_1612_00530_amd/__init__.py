@@ -33,8 +33,13 @@ ARR = {
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
-    "spmvc_batched_config", "spmv_free", "spmvc_status_string", "spmvc_last_error",
+    "spmvc_batched_config", "spmvc_set_allocator", "spmv_free", "spmvc_status_string", "spmvc_last_error",
 ]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_alloc_hooks = []  # every installed pair of ctypes callbacks, kept alive: buffers return to their own
 
 
 class SpmvcError(RuntimeError):
@@ -103,6 +108,7 @@ def load(path: str = LIB_PATH):
     lib.spmv_symgs.argtypes = [P, P, P, i32, P]
     lib.spmv_colors.argtypes = [P, ctypes.POINTER(i32), P, P]
     lib.spmvc_batched_config.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    lib.spmvc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
     lib.spmv_free.argtypes = [P]
     lib.spmv_free.restype = None
     lib.spmvc_status_string.argtypes = [i32]
@@ -110,7 +116,7 @@ def load(path: str = LIB_PATH):
     lib.spmvc_last_error.restype = ctypes.c_char_p
     for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
                  "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs",
-                 "spmv_colors", "spmvc_batched_config"]:
+                 "spmv_colors", "spmvc_batched_config", "spmvc_set_allocator"]:
         getattr(lib, name).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -327,3 +333,24 @@ def batched_config():
     f, c, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(load().spmvc_batched_config(ctypes.byref(f), ctypes.byref(c), ctypes.byref(us)))
     return {"form": f.value, "chunk": c.value, "us": us.value}
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's device allocations through torch's caching allocator
+    (spmvc_set_allocator), or back to hipMalloc / hipFree with enable=False.
+    Buffers already allocated go back to the allocator that made them."""
+    import torch
+
+    if not enable:
+        _check(load().spmvc_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _alloc_hooks.append(hooks)
+    _check(load().spmvc_set_allocator(hooks[0], hooks[1], None))

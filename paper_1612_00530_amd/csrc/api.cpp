@@ -5,6 +5,8 @@
 #include <fstream>
 #include <sstream>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace spmvc {
@@ -81,6 +83,17 @@ void default_plan(spmvc_matrix_s *M) {
 
 using namespace spmvc;
 
+namespace spmvc {
+namespace {
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+}  // namespace
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+}  // namespace spmvc
+
 extern "C" {
 
 const char *spmvc_status_string(int32_t st) {
@@ -99,6 +112,19 @@ const char *spmvc_status_string(int32_t st) {
 }
 
 const char *spmvc_last_error(void) { return g_last_error.c_str(); }
+
+spmvc_status spmvc_set_allocator(void *(*alloc_fn)(size_t, void *, void *), void (*free_fn)(void *, void *, void *),
+                                 void *ctx) {
+    return guarded([&]() -> spmvc_status {
+        if ((alloc_fn == nullptr) != (free_fn == nullptr))
+            return fail(SPMVC_EINVAL, "alloc and free must both be set or both be NULL");
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_alloc.alloc = reinterpret_cast<void *(*)(size_t, hipStream_t, void *)>(alloc_fn);
+        g_alloc.free = reinterpret_cast<void (*)(void *, hipStream_t, void *)>(free_fn);
+        g_alloc.ctx = alloc_fn ? ctx : nullptr;
+        return SPMVC_OK;
+    });
+}
 
 spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const int64_t *row_ptr,
                            const int32_t *col_idx, const double *vals, const spmvc_compress_opts *opts,

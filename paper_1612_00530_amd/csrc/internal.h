@@ -40,17 +40,39 @@ struct Error {
 #define SPMVC_CHECK_LAUNCH() SPMVC_HIP(hipGetLastError())
 
 // ---- device buffers ------------------------------------------------------------------
+// Device memory comes from the allocator set with spmvc_set_allocator, else
+// hipMalloc / hipFree.  Each buffer keeps the allocator that gave it its
+// memory and returns it there, so changing the allocator never mixes them.
+struct Allocator {
+    void *(*alloc)(size_t, hipStream_t, void *) = nullptr;
+    void (*free)(void *, hipStream_t, void *) = nullptr;
+    void *ctx = nullptr;
+};
+Allocator current_allocator();  // api.cpp
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    Allocator owner;  // where p came from (hipMalloc when owner.alloc is null)
     void alloc(size_t n) {
         release();
         if (n == 0) return;
-        SPMVC_HIP(hipMalloc(&p, n));
+        owner = current_allocator();
+        if (owner.alloc) {
+            p = owner.alloc(n, nullptr, owner.ctx);
+            if (!p) throw Error{SPMVC_ENOMEM, "the allocator set with spmvc_set_allocator returned NULL"};
+        } else {
+            SPMVC_HIP(hipMalloc(&p, n));
+        }
         bytes = n;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (owner.alloc)
+                owner.free(p, nullptr, owner.ctx);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }

@@ -65,6 +65,16 @@ def test_null_arguments_rejected_on_host():
     assert lib.spmv_set_block_mode(None, 1) == -1
     lib.spmv_set_config.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     assert lib.spmv_set_config(None, 512, 1) == -1
+    lib.spmv_symgs.argtypes = [P, P, P, ctypes.c_int32, P]
+    assert lib.spmv_symgs(None, None, None, 1, None) == -1
+    # allocator hooks: both or neither
+    alloc_t = ctypes.CFUNCTYPE(P, ctypes.c_size_t, P, P)
+    free_t = ctypes.CFUNCTYPE(None, P, P, P)
+    lib.spmvc_set_allocator.argtypes = [alloc_t, free_t, P]
+    assert lib.spmvc_set_allocator(alloc_t(lambda n, s, c: None), free_t(), None) == -1
+    assert lib.spmvc_set_allocator(alloc_t(), free_t(), None) == 0
+    lib.spmvc_batched_config.argtypes = [P, P, P]
+    assert lib.spmvc_batched_config(None, None, None) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -519,3 +519,63 @@ def test_invalid_csr_is_rejected():
     with pytest.raises(P.SpmvcError) as e:  # x and y alias
         M.spmv(x, x)
     assert e.value.status == -1
+
+
+def test_torch_allocator_hooks():
+    """spmvc_set_allocator: with torch's caching allocator installed, compression,
+    SpMV, block SpMV, CG and SymGS allocate through it (counted here) and give
+    the oracle's results; handles made under it are freed back to it after the
+    hooks are removed again."""
+    say("case: allocator hooks")
+    torch = torch_mod()
+    P = lib()
+    import ctypes
+
+    counts = {"alloc": 0, "free": 0}
+    alloc_t = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+    free_t = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+    def _alloc(n, s, c):
+        counts["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(int(n))
+
+    def _free(p, s, c):
+        counts["free"] += 1
+        torch.cuda.caching_allocator_delete(p)
+
+    hooks = (alloc_t(_alloc), free_t(_free))
+    P._alloc_hooks.append(hooks)  # kept alive for as long as buffers made with them may exist
+    assert P.load().spmvc_set_allocator(hooks[0], hooks[1], None) == 0
+    try:
+        A = stencil27(20, 18, 16)
+        x = uniform_vector(A.n_cols, seed=31)
+        for fmt in ("DIT", "DITV", "ELL"):
+            M = compress(A, fmt=fmt)
+            assert max_rel_err(A, x, gpu_spmv(M, x), oracle.spmv(A, x)) <= 1e-14
+            X = np.stack([uniform_vector(A.n_cols, seed=40 + r) for r in range(8)], axis=1)
+            Y = M.spmv_block(torch.from_numpy(X).cuda()).cpu().numpy()
+            Yref = oracle.spmv_block(A, X)
+            assert all(max_rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14 for r in range(8))
+        b = oracle.spmv(A, np.ones(A.n_cols))
+        st, xs, stats = P.cg_solve(M, torch.from_numpy(b).cuda())
+        torch.cuda.synchronize()
+        assert st == 0 and oracle.relres(A, b, xs[0].cpu().numpy()) <= 1.5e-10
+        Mg = compress(A, fmt="DIT")
+        xg = Mg.symgs(torch.from_numpy(b).cuda())
+        torch.cuda.synchronize()
+        assert np.all(np.isfinite(xg.cpu().numpy()))
+        assert counts["alloc"] > 0 and counts["free"] > 0
+    finally:
+        P.use_torch_allocator(False)
+    n_alloc = counts["alloc"]
+    del M, Mg
+    import gc
+
+    gc.collect()
+    torch.cuda.synchronize()
+    assert counts["alloc"] == n_alloc  # nothing new after the hooks were removed
+    assert counts["free"] == counts["alloc"]  # every buffer went back to the hooks that made it
+    # and plain hipMalloc again afterwards
+    M2 = compress(A, fmt="DIT")
+    assert max_rel_err(A, x, gpu_spmv(M2, x), oracle.spmv(A, x)) <= 1e-14
+    assert counts["alloc"] == n_alloc
