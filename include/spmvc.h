@@ -59,7 +59,8 @@ typedef enum {
     SPMVC_FMT_ELL = 0,
     SPMVC_FMT_DT = 1,
     SPMVC_FMT_DIT = 2,
-    SPMVC_FMT_DITV = 3
+    SPMVC_FMT_DITV = 3,
+    SPMVC_FMT_AUTO = 4  /* spmv_compress only: DIT, or ELL when DIT's stream would not be smaller */
 } spmvc_format;
 
 typedef struct spmvc_matrix_s *spmvc_matrix; /* opaque, owned by the library */

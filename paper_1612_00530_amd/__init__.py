@@ -20,9 +20,9 @@ __all__ = [
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspmvc.so")
 
-FMT_ELL, FMT_DT, FMT_DIT, FMT_DITV = 0, 1, 2, 3
+FMT_ELL, FMT_DT, FMT_DIT, FMT_DITV, FMT_AUTO = 0, 1, 2, 3, 4
 F64, F32 = 0, 1
-_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT, "DITV": FMT_DITV}
+_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT, "DITV": FMT_DITV, "AUTO": FMT_AUTO}
 
 ARR = {
     "ELL_VAL": 0, "ELL_COL": 1, "DT_S": 2, "IDS": 3, "T": 4, "PAT_OFF": 5, "PAT_LEN": 6,

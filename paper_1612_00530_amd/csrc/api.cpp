@@ -140,7 +140,9 @@ spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const in
         if (nnz > 0 && n_cols == 0) return fail(SPMVC_ERANGE, "entries in a matrix with no columns");
         spmvc_compress_opts o{SPMVC_FMT_DIT, 15, 65535, 2, 1};
         if (opts) o = *opts;
-        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_DITV) return fail(SPMVC_EINVAL, "unknown format");
+        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_AUTO) return fail(SPMVC_EINVAL, "unknown format");
+        const bool autofmt = o.fmt == SPMVC_FMT_AUTO;
+        if (autofmt) o.fmt = SPMVC_FMT_DIT;
         if (o.k_max < 0 || o.k_max > kMaxK) return fail(SPMVC_EINVAL, "k_max must be in 0..15");
         if (o.p_max < 1 || o.p_max > 0x7FFFFFFE) return fail(SPMVC_EINVAL, "p_max must be in 1..2^31-2");
         if (o.min_pattern_rows < 1) return fail(SPMVC_EINVAL, "min_pattern_rows must be >= 1");
@@ -150,6 +152,28 @@ spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const in
         M->nnz = nnz;
         try {
             compress(M, row_ptr, col_idx, vals, o, static_cast<hipStream_t>(stream));
+            if (autofmt && M->n_rows > 0) {
+                // AUTO: DIT unless its stream is not smaller than ELL's (12 bytes per
+                // slot of the longest pattern, escape rows as CSR)
+                int64_t maxlen = 0;
+                for (int q = 0; q < M->P; ++q) maxlen = std::max<int64_t>(maxlen, M->h_pat_len[q]);
+                const int64_t ell = 12 * maxlen * M->n_pad + 12 * M->n_esc_nnz + 16 * M->n_esc;
+                if (stream_bytes(M, SPMVC_F64) >= ell) {
+                    auto *E = new spmvc_matrix_s();
+                    E->n_rows = n_rows;
+                    E->n_cols = n_cols;
+                    E->nnz = nnz;
+                    o.fmt = SPMVC_FMT_ELL;
+                    try {
+                        compress(E, row_ptr, col_idx, vals, o, static_cast<hipStream_t>(stream));
+                    } catch (...) {
+                        delete E;
+                        throw;
+                    }
+                    delete M;
+                    M = E;
+                }
+            }
             default_plan(M);
         } catch (...) {
             delete M;

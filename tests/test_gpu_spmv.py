@@ -579,3 +579,24 @@ def test_torch_allocator_hooks():
     M2 = compress(A, fmt="DIT")
     assert max_rel_err(A, x, gpu_spmv(M2, x), oracle.spmv(A, x)) <= 1e-14
     assert counts["alloc"] == n_alloc
+
+
+def test_auto_format_choice():
+    """fmt=AUTO keeps DIT for the stencil (3 B/row against ELL's 324) and falls
+    back to ELL where every row's pattern is unique (all rows would escape as
+    CSR, more bytes than ELL's 12 per slot); both multiply correctly."""
+    say("case: AUTO format")
+    A = stencil27(16, 16, 16)
+    M = compress(A, fmt="AUTO")
+    assert M.info()["fmt_name"] == "DIT"
+    x = uniform_vector(A.n_cols, seed=33)
+    assert max_rel_err(A, x, gpu_spmv(M, x), oracle.spmv(A, x)) <= 1e-14
+    rng = np.random.default_rng(34)
+    n, L = 500, 8
+    cols = np.concatenate([np.sort(rng.choice(2000, L, replace=False)) for _ in range(n)]).astype(np.int32)
+    B = CSR(n, 2000, np.arange(0, n * L + 1, L, dtype=np.int64), cols, rng.choice([-1.0, 2.0], n * L))
+    Mb = compress(B, fmt="AUTO")
+    assert Mb.info()["fmt_name"] == "ELL"
+    xb = uniform_vector(B.n_cols, seed=35)
+    assert max_rel_err(B, xb, gpu_spmv(Mb, xb), oracle.spmv(B, xb)) <= 1e-14
+    assert roundtrip_ok(Mb, B)
