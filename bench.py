@@ -229,7 +229,14 @@ def main():
             reps1 += 1
         t_cpu1 = (time.perf_counter() - t1) / reps1
         oracle.set_threads(nthr)
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": 2.0 * nnz / t_cpu / 1e9, "unit": "Gflops", "cores": nthr,
+                               "cpu_model": cpu_model,
                                "kind": "oracle",
                                "sample": f"{reps} full CSR SpMVs of the {g}^3 stencil matrix (FP64, OpenMP rows)",
                                "value_1thread": round(2.0 * nnz / t_cpu1 / 1e9, 3),
@@ -292,6 +299,16 @@ def main():
         f"ELL {block8['ell_us']} us ({block8['ell_gflops']} Gflops)")
     del X8, Y8
 
+    # practical HBM rate on this machine: a 1 GiB -> 1 GiB device copy (4x the MALL)
+    src = torch.ones(128 << 20, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    c_ms = time_batch(lambda: dst.copy_(src), 10, torch)
+    practical_gbs = 2.0 * src.numel() * 8 / (c_ms * 1e-3) / 1e9
+    log(f"[bench] 1 GiB device copy: {practical_gbs:.0f} GB/s (read + write)")
+    del src, dst
+
     # cold-cache launches: the MALL flushed before each one
     flush = torch.empty(128 << 20, dtype=torch.float64, device=dev)
     c_dit = time_cold(lambda: D.spmv(x, y), 30, torch, flush)
@@ -331,6 +348,8 @@ def main():
                    "rows_per_block": dinf["rows_per_block"], "lds_windows": dinf["lds_windows"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "practical_peak_GBps": round(practical_gbs, 1),
+                     "frac_of_practical": round(achieved / practical_gbs, 4),
                      "kernel": dinf["kernel_name"], "algorithmic_bytes_per_launch": alg_dit,
                      "launch_us_mean": round(k_mean * 1000, 3),
                      "single_launch_event_us_median": round(k_med * 1000, 3)},
