@@ -894,6 +894,10 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     const int64_t n_total = row0;
     const int n_tiles = static_cast<int>(tile0);
     const int np = n_sys * nrhs;
+    if (n_total == 0) {  // every system empty: nothing to solve
+        for (int q = 0; q < np; ++q) stat[q] = spmvc_cg_stat{0, 0, SPMVC_OK, 0, 0.0, 0.0};
+        return SPMVC_OK;
+    }
     DevBuf dsys, dtile, B, X, R, P, Q, part, rho, rho0, alpha, beta, relres, iters, status, done, step, sact, sstep,
         nact, rr;
     dsys.alloc(sizeof(SysDesc) * n_sys);

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synthetic import batched_grids, stencil27, stencil27_irregular, uniform_vector
+from synthetic import CSR, batched_grids, stencil27, stencil27_irregular, uniform_vector
 
 from gpu_util import compress, lib, torch_mod
 
@@ -363,6 +363,18 @@ def test_batched_tuner_reports_its_choice(monkeypatch):
     torch.cuda.synchronize()
     cfg = P.batched_config()
     assert st == 0 and cfg["form"] in (0, 1, 2) and cfg["chunk"] in (8, 32, 128) and cfg["us"] > 0
+
+
+def test_batched_all_systems_empty():
+    """A batch whose systems have no rows returns at once: every pair done, no iteration."""
+    say("case: batched empty")
+    torch = torch_mod()
+    P = lib()
+    E = CSR(0, 0, np.zeros(1, dtype=np.int64), np.zeros(0, np.int32), np.zeros(0))
+    mats = [compress(E, fmt="DIT"), compress(E, fmt="DIT")]
+    bs = [torch.zeros((0, 2), dtype=torch.float64, device="cuda") for _ in mats]
+    st, xs, stats = P.cg_solve(mats, bs, nrhs=2, batched=2)
+    assert st == 0 and all(q["iters"] == 0 and q["status"] == 0 for q in stats)
 
 
 def test_batched_failures_are_per_pair():
