@@ -16,7 +16,9 @@ Pins (tests/test_oracle_gs.py): the coloring of a 27-point stencil equals the
 parity coloring (x mod 2) + 2 (y mod 2) + 4 (z mod 2); a sweep equals the
 matrix-splitting form (D + L) x' = b - U x, (D + U) x'' = b - L x' of the
 color-permuted matrix, solved by dense triangular solves; repeated sweeps
-converge to A^-1 b on a diagonally dominant matrix.
+converge to A^-1 b on a diagonally dominant matrix; ``pcg`` with M = I
+takes the C oracle's CG iteration count, and its SymGS preconditioner equals
+the dense M = (D + L) D^-1 (D + U) of the color-permuted matrix.
 """
 from __future__ import annotations
 
@@ -83,3 +85,44 @@ def symgs(A, b, x, color, sweeps: int = 1) -> np.ndarray:
             s = np.bincount(rows[e], weights=val[e] * x[col[e]], minlength=n)
             x[R] = (b[R] - s[R]) / d[R]
     return x
+
+
+def pcg(A, b, color, rtol: float = 1e-10, max_iter: int = 100000, precondition: bool = True):
+    """Preconditioned CG from x0 = 0, with M^-1 r = one symmetric Gauss-Seidel
+    sweep on A z = r from z = 0 in the multicolor order `color` (the role
+    SymGS plays inside the preconditioner of the HPCG iteration, Table I).
+    With precondition=False, M = I (plain CG).  Stops when ||r|| <= rtol ||b||.
+    Returns (x, iterations, ||r|| / ||b||)."""
+    b = np.asarray(b, dtype=np.float64)
+    n = A.n_rows
+
+    def matvec(v):
+        rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+        return np.bincount(rows, weights=np.asarray(A.val) * v[np.asarray(A.col)], minlength=n)
+
+    def prec(r):
+        return symgs(A, r, np.zeros(n), color, 1) if precondition else r.copy()
+
+    x = np.zeros(n)
+    r = b.copy()
+    bn = np.sqrt(b @ b)
+    if bn == 0.0:
+        return x, 0, 0.0
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while it < max_iter:
+        q = matvec(p)
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        it += 1
+        rn = np.sqrt(r @ r)
+        if rn <= rtol * bn:
+            break
+        z = prec(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, float(np.sqrt(r @ r) / bn)
