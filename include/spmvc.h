@@ -124,7 +124,8 @@ spmvc_status spmv_block(spmvc_matrix A, int32_t dt, int32_t nrhs, const void *X,
 typedef struct {
     double rtol;         /* stop when ||r|| <= rtol * ||b||, default 1e-10                 */
     int32_t max_iter;    /* SpMV cap per (system, rhs) [FP64 mode; inner total in MIXED], 10000 */
-    int32_t mode;        /* 0 = FP64 CG, 1 = mixed precision with iterative refinement     */
+    int32_t mode;        /* 0 = FP64 CG, 1 = mixed precision with iterative refinement,
+                            2 = FP64 CG preconditioned by one SymGS sweep                 */
     double inner_rtol;   /* MIXED: inner FP32 solve tolerance relative to ||r||, 1e-5      */
     int32_t max_outer;   /* MIXED: refinement steps cap, default 20                        */
     int32_t check_every; /* iterations between host convergence checks, default 16         */
@@ -158,6 +159,11 @@ typedef struct {
  * failing pair's status (SPMVC_ENOTSPD, SPMVC_ENOCONV).  Blocking.
  * mode 1 (MIXED): outer FP64 residual r = b - A x, inner FP32 CG on A d = r
  * with FP64 dot products, FP64 update x += d; requires nrhs == 1, n_sys == 1.
+ * mode 2 (PCG): FP64 CG preconditioned by one multicolor symmetric
+ * Gauss-Seidel sweep (z = M^-1 r: the sweep of spmv_symgs on A z = r from
+ * z = 0; the coloring is built on first use) -- the iteration of Table I with
+ * SymGS as the whole preconditioner; stops on ||r|| <= rtol ||b||; requires
+ * nrhs == 1, n_sys == 1 and a non-zero diagonal in every row (SPMVC_EINVAL).
  */
 spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs,
                       const double *const *b, double *const *x, const spmvc_cg_opts *opts,

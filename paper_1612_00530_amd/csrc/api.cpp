@@ -221,11 +221,13 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs, const 
         if (nrhs < 1 || nrhs > 16) return fail(SPMVC_EINVAL, "nrhs must be in 1..16");
         spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16, 2};
         if (opts) o = *opts;
-        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || (o.mode != 0 && o.mode != 1) ||
+        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || o.mode < 0 || o.mode > 2 ||
             o.batched < 0 || o.batched > 2)
             return fail(SPMVC_EINVAL, "invalid cg options");
         if (o.mode == 1 && (n_sys != 1 || nrhs != 1))
             return fail(SPMVC_EUNSUPPORTED, "mixed-precision mode takes one system with one right-hand side");
+        if (o.mode == 2 && (n_sys != 1 || nrhs != 1))
+            return fail(SPMVC_EUNSUPPORTED, "preconditioned mode takes one system with one right-hand side");
         if (o.mode == 1 && (!(o.inner_rtol > 0.0) || o.max_outer < 0)) return fail(SPMVC_EINVAL, "invalid inner options");
         for (int s = 0; s < n_sys; ++s) {
             if (!A[s]) return fail(SPMVC_EINVAL, "matrix handle is null");

@@ -278,6 +278,145 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
     }
 }
 
+// ---- preconditioned CG with one multicolor SymGS sweep as M^-1 (mode 2) -------------
+// The iteration of Table I with SymGS as the whole preconditioner (no
+// multigrid levels): z = M^-1 r is one symmetric Gauss-Seidel sweep on
+// A z = r from z = 0.  rho[] holds r.z; the stopping test uses r.r.
+
+// z = 0 (a fill kernel, no memset), unless the solve has stopped
+__global__ __launch_bounds__(kRT) void k_pcg_zero(int64_t n, double *__restrict__ z, const CgScal *st) {
+    if (st->done) return;
+    SPMVC_STREAM4(
+_Pragma("unroll") for (int u = 0; u < 4; ++u) z[i + u * stride_] = 0.0;
+        ,
+        z[i] = 0.0;
+    )
+}
+
+// p = z; partials of r.z (start of the iteration)
+__global__ __launch_bounds__(kRT) void k_pcg_init(int64_t n, const double *__restrict__ r, const double *__restrict__ z,
+                                                  double *__restrict__ p, double *rz_part) {
+    double acc = 0.0;
+    SPMVC_STREAM4(
+        double rv[4]; double zv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = r[i + u * stride_]; zv[u] = z[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            p[i + u * stride_] = zv[u];
+            acc += rv[u] * zv[u];
+        }
+        ,
+        p[i] = z[i];
+        acc += r[i] * z[i];
+    )
+    const double b = block_sum<kRT>(acc);
+    if (threadIdx.x == 0) rz_part[blockIdx.x] = b;
+}
+
+// rho[0] = r.z (one block)
+__global__ __launch_bounds__(kRT) void k_pcg_init_fin(const double *rz_part, int np, CgScal *st) {
+    const double tot = sum_partials<kRT>(rz_part, np);
+    if (threadIdx.x == 0 && !st->done) st->rho[0] = tot;
+}
+
+// sigma = p.q (the SpMV's partials); alpha = rho / sigma; x += alpha p;
+// r -= alpha q; partials of r.r.  Block 0 records sigma and go[par].
+__global__ __launch_bounds__(kRT) void k_pcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                    const double *__restrict__ p, const double *__restrict__ q,
+                                                    const double *sig_part, int n_sig, double *rr_part, CgScal *st,
+                                                    int par, int it) {
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st->done) {
+        if (lead) st->go[par] = 0;
+        return;
+    }
+    const double sigma = sum_partials<kRT>(sig_part, n_sig);
+    if (!(sigma > 0.0) || !isfinite(sigma)) {
+        if (lead) {
+            st->sigma = sigma;
+            st->done = 1;
+            st->status = SPMVC_ENOTSPD;
+            st->iters = it + 1;
+            st->go[par] = 0;
+        }
+        return;
+    }
+    if (lead) {
+        st->sigma = sigma;
+        st->go[par] = 1;
+    }
+    const double alpha = st->rho[par] / sigma;
+    double acc = 0.0;
+    SPMVC_STREAM4(
+        double xv[4]; double rv[4]; double pv[4]; double qv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            xv[u] = x[i + u * stride_]; rv[u] = r[i + u * stride_];
+            pv[u] = p[i + u * stride_]; qv[u] = q[i + u * stride_];
+        }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            x[i + u * stride_] = xv[u] + alpha * pv[u];
+            const double ri = rv[u] - alpha * qv[u];
+            r[i + u * stride_] = ri;
+            acc += ri * ri;
+        }
+        ,
+        x[i] = x[i] + alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    )
+    const double b = block_sum<kRT>(acc);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = b;
+}
+
+// The stopping test on r.r; partials of r.z (z = M^-1 r of this iteration).
+__global__ __launch_bounds__(kRT) void k_pcg_rz(int64_t n, const double *__restrict__ r, const double *__restrict__ z,
+                                                const double *rr_part, int n_rr, double *rz_part, CgScal *st, int par,
+                                                int it) {
+    if (!st->go[par]) return;
+    const double rr = sum_partials<kRT>(rr_part, n_rr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iters = it + 1;
+        st->rel = sqrt(rr) / sqrt(st->rho0);
+        if (sqrt(rr) <= st->rtol * sqrt(st->rho0)) {
+            st->done = 1;
+            st->status = SPMVC_OK;
+        } else if (!isfinite(rr)) {
+            st->done = 1;
+            st->status = SPMVC_ENOTSPD;
+        } else if (it + 1 >= st->max_iter) {
+            st->done = 1;
+            st->status = SPMVC_ENOCONV;
+        }
+    }
+    double acc = 0.0;
+    SPMVC_STREAM4(
+        double rv[4]; double zv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = r[i + u * stride_]; zv[u] = z[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) acc += rv[u] * zv[u];
+        ,
+        acc += r[i] * z[i];
+    )
+    const double b = block_sum<kRT>(acc);
+    if (threadIdx.x == 0) rz_part[blockIdx.x] = b;
+}
+
+// beta = rho' / rho (rho' = r.z); p = z + beta p.  `done` was settled by the
+// previous kernel, so it can be read here.
+__global__ __launch_bounds__(kRT) void k_pcg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                               const double *rz_part, int n_rz, CgScal *st, int par) {
+    if (!st->go[par] || st->done) return;
+    const double rz = sum_partials<kRT>(rz_part, n_rz);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[par ^ 1] = rz;
+    const double beta = rz / st->rho[par];
+    SPMVC_STREAM4(
+        double zv[4]; double pv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) { zv[u] = z[i + u * stride_]; pv[u] = p[i + u * stride_]; }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) p[i + u * stride_] = zv[u] + beta * pv[u];
+        ,
+        p[i] = z[i] + beta * p[i];
+    )
+}
+
 // partials of (b - ax).(b - ax), optionally storing r = b - ax; partials of b.b
 __global__ __launch_bounds__(kRT) void k_residual(int64_t n, const double *__restrict__ b,
                                                   const double *__restrict__ ax, double *__restrict__ r,
@@ -449,6 +588,60 @@ spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, con
     return static_cast<spmvc_status>(h.status);
 }
 
+// Preconditioned CG (mode 2): M^-1 r = one multicolor SymGS sweep from zero.
+spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o, spmvc_cg_stat &stat,
+                       hipStream_t s) {
+    const int64_t n = M->n_rows;
+    const int64_t nn = std::max<int64_t>(n, 1);
+    build_coloring(M, s);  // throws for a non-square matrix or a missing / zero diagonal
+    Solver sv(s, spmv_dot_blocks(M));
+    DevBuf r, z, p, q;
+    r.alloc(sizeof(double) * nn);
+    z.alloc(sizeof(double) * nn);
+    p.alloc(sizeof(double) * nn);
+    q.alloc(sizeof(double) * nn);
+    const unsigned g = rgrid(n);
+    double *pr = r.as<double>(), *pz = z.as<double>(), *pp = p.as<double>(), *pq = q.as<double>();
+    const int *done = &sv.st()->done;
+    // x = 0, r = b, rho0 = b.b; z = M^-1 r; p = z; rho = r.z
+    k_cg_start<double, double><<<g, kRT, 0, s>>>(n, b, x, pr, pp, sv.part_a.as<double>());
+    k_cg_start_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), o.rtol, o.max_iter);
+    k_pcg_zero<<<g, kRT, 0, s>>>(n, pz, sv.st());
+    SPMVC_CHECK_LAUNCH();
+    launch_symgs(M, pr, pz, 1, s, done);
+    k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.part_a.as<double>());
+    k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st());
+    SPMVC_CHECK_LAUNCH();
+    const int chunk = std::max(1, o.check_every);
+    int it = 0;
+    while (it < o.max_iter) {
+        if (sv.read().done) break;
+        for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
+            const int par = it & 1;
+            const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.part_sig.as<double>());
+            k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.part_sig.as<double>(), static_cast<int>(ns),
+                                           sv.part_b.as<double>(), sv.st(), par, it);
+            k_pcg_zero<<<g, kRT, 0, s>>>(n, pz, sv.st());
+            launch_symgs(M, pr, pz, 1, s, done);
+            k_pcg_rz<<<g, kRT, 0, s>>>(n, pr, pz, sv.part_b.as<double>(), static_cast<int>(g), sv.part_a.as<double>(),
+                                       sv.st(), par, it);
+            k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.part_a.as<double>(), static_cast<int>(g), sv.st(), par);
+        }
+        SPMVC_CHECK_LAUNCH();
+    }
+    CgScal h = sv.read();
+    if (!h.done) {
+        h.done = 1;
+        h.status = SPMVC_ENOCONV;
+    }
+    stat.iters = h.iters;
+    stat.outer_iters = 0;
+    stat.status = h.status;
+    stat.relres_recursive = h.rel;
+    stat.relres_true = true_relres(M, sv, b, x, pq);
+    return static_cast<spmvc_status>(h.status);
+}
+
 // Mixed precision: FP64 residual / update outside, FP32-SpMV CG inside.  The
 // inner tolerance is inner_rtol, loosened for the last step to what the outer
 // tolerance still needs (0.9 rtol ||b|| / ||r||), so no step over-solves.
@@ -511,6 +704,11 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
     spmvc_status first_bad = SPMVC_OK;
     if (o.mode == 1) {
         const spmvc_status st = solve_mixed(A[0], b[0], x[0], o, stat[0], s);
+        SPMVC_HIP(hipStreamSynchronize(s));
+        return st;
+    }
+    if (o.mode == 2) {
+        const spmvc_status st = solve_pcg(const_cast<spmvc_matrix_s *>(A[0]), b[0], x[0], o, stat[0], s);
         SPMVC_HIP(hipStreamSynchronize(s));
         return st;
     }

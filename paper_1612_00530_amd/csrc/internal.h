@@ -210,7 +210,9 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
 
 // symgs.hip
 void build_coloring(spmvc_matrix_s *M, hipStream_t s);  // blocking; throws Error on a bad matrix
-void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s);
+// `skip` (device int, may be null): when *skip != 0 the sweep's kernels return at once.
+void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s,
+                  const int *skip = nullptr);
 
 // scan.hip: exclusive prefix sum of n int64 values (in may equal out); returns the total.
 int64_t exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

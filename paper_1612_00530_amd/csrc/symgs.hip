@@ -108,7 +108,8 @@ template <class F> __device__ __forceinline__ void gs_visit(const GsArgs &a, int
 
 // The rows rows[0..n) of one color: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.
 __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int32_t *__restrict__ rows, int64_t n,
-                                                            const double *__restrict__ b, double *x) {
+                                                            const double *__restrict__ b, double *x, const int *skip) {
+    if (skip && *skip) return;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
     if (t >= n) return;
     const int64_t i = rows[t];
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int3
 template <int MAXW>
 __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows,
                                                           const uint32_t *__restrict__ meta, int64_t n,
-                                                          const double *__restrict__ b, double *x) {
+                                                          const double *__restrict__ b, double *x, const int *skip) {
+    if (skip && *skip) return;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
     if (t >= n) return;
     const int64_t i = rows[t];
@@ -301,7 +303,7 @@ void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
     M->gs_ready = 1;
 }
 
-void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s) {
+void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s, const int *skip) {
     const GsArgs a = gs_args(M);
     const int C = M->gs_n_colors;
     const int32_t *rows = M->gs_rows.as<int32_t>();
@@ -319,9 +321,9 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
             if (cnt == 0) continue;
             const unsigned g = grid_for(cnt, kGsThreads, 0x7fffffff);
             if (dit27)
-                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rows + r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x);
+                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rows + r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x, skip);
             else
-                k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x);
+                k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x, skip);
             SPMVC_CHECK_LAUNCH();
         }
 }

@@ -391,3 +391,40 @@ def test_batched_failures_are_per_pair():
     assert [s["status"] for s in stats] == [0, 0, -6, -6]
     st, xs, stats = P.cg_solve([mats[0]], [bs[0]], nrhs=2, max_iter=4)
     assert st == -7 and all(s["iters"] == 4 for s in stats)
+
+
+@pytest.mark.parametrize("fmt,grid", [("DIT", (24, 22, 20)), ("DITV", (17, 13, 11)), ("ELL", (16, 16, 16)),
+                                      ("DIT", (64, 64, 64))])
+def test_pcg_symgs_matches_oracle(fmt, grid):
+    """CG preconditioned by one multicolor SymGS sweep (mode 2): the oracle's
+    preconditioned CG (same coloring, same sweep) takes the same iteration
+    count within 2, fewer than plain CG, and both reach 1e-10 in the oracle's
+    own residual."""
+    say("case: pcg", fmt, grid)
+    A = stencil27(*grid)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    st, x, stats = solve(A, b, fmt=fmt, mode=2)
+    assert st == 0 and stats[0]["status"] == 0
+    assert oracle.relres(A, b, x) <= 1.5e-10
+    assert np.abs(x - 1).max() < 1e-7
+    if A.n_rows <= 20000:
+        from oracle import gs
+
+        _, it_ref, _ = gs.pcg(A, b, gs.greedy_coloring(A))
+        assert abs(stats[0]["iters"] - it_ref) <= 2
+    _, _, it_cg, _ = oracle.cg(A, b)
+    assert stats[0]["iters"] < it_cg
+
+
+def test_pcg_rejects_missing_diagonal_and_zero_rhs():
+    say("case: pcg errors")
+    A = stencil27(6, 6, 6)
+    keep = np.ones(A.nnz, dtype=bool)
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    keep[np.flatnonzero((rows == 7) & (A.col == 7))] = False
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=A.n_rows))])
+    B = CSR(A.n_rows, A.n_cols, rp, A.col[keep], A.val[keep])
+    st, _, _ = solve(B, np.ones(B.n_rows), mode=2)
+    assert st == -1
+    st, x, stats = solve(A, np.zeros(A.n_rows), mode=2)
+    assert st == 0 and stats[0]["iters"] == 0 and np.all(x == 0)
