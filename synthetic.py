@@ -112,6 +112,30 @@ def stencil27(nx: int, ny: int, nz: int) -> CSR:
     return CSR(n, n, row_ptr, col, val, grid=(nx, ny, nz))
 
 
+
+def stencil_hierarchy(nx: int, ny: int, nz: int, n_levels: int):
+    """Grid hierarchy of HPCG's multigrid problem: level l is the 27-point
+    matrix on the (nx, ny, nz) / 2^l grid, and f2c[l] (int32, one entry per row
+    of level l + 1) holds, for the coarse point (ix, iy, iz), the fine row of
+    the point (2 ix, 2 iy, 2 iz).  Each side must be divisible by
+    2^(n_levels - 1).  Returns (list of CSR, list of n_levels - 1 arrays)."""
+    if n_levels < 1:
+        raise ValueError("n_levels must be >= 1")
+    step = 1 << (n_levels - 1)
+    if nx % step or ny % step or nz % step:
+        raise ValueError("grid sides must be divisible by 2^(n_levels - 1)")
+    mats, f2c = [], []
+    g = (nx, ny, nz)
+    for lev in range(n_levels):
+        mats.append(stencil27(*g))
+        if lev + 1 < n_levels:
+            cx, cy, cz = g[0] // 2, g[1] // 2, g[2] // 2
+            i = np.arange(cx * cy * cz, dtype=np.int64)
+            ix, iy, iz = i % cx, (i // cx) % cy, i // (cx * cy)
+            f2c.append((2 * ix + g[0] * (2 * iy + g[1] * 2 * iz)).astype(np.int32))
+            g = (cx, cy, cz)
+    return mats, f2c
+
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)

@@ -153,3 +153,104 @@ def test_pcg_symgs_converges_faster():
     Minv_r = np.linalg.solve((np.tril(Mp) @ np.linalg.inv(D)) @ np.triu(Mp), r[perm])
     z = gs.symgs(S, r, np.zeros(S.n_rows), cs, 1)
     assert np.max(np.abs(z[perm] - Minv_r)) <= 1e-13 * np.max(np.abs(Minv_r))
+
+
+def _sweep_operator(A, color):
+    """Dense S = M^-1, M = (D + L) D^-1 (D + U) of the color-permuted A, in the
+    original row order: one SymGS sweep from zero maps r to S r."""
+    perm = np.lexsort((np.arange(A.n_rows), color))
+    Mp = dense(A)[np.ix_(perm, perm)]
+    D = np.diag(np.diag(Mp))
+    Sp = np.linalg.inv((np.tril(Mp) @ np.linalg.inv(D)) @ np.triu(Mp))
+    S = np.empty_like(Sp)
+    S[np.ix_(perm, perm)] = Sp
+    return S
+
+
+def _vcycle_operator(levels, f2c, colors, level=0, post=True):
+    """B_l = S + (I - S A)(S + P B_{l+1} R (I - A S)) from dense matrices, with
+    R the injection (R[i, f2c[i]] = 1) and P = R^T; B_last = S."""
+    A = dense(levels[level])
+    S = _sweep_operator(levels[level], colors[level].max() - colors[level])  # smoother in reverse color order
+    if level + 1 == len(levels):
+        return S
+    n = A.shape[0]
+    R = np.zeros((levels[level + 1].n_rows, n))
+    R[np.arange(R.shape[0]), f2c[level]] = 1.0
+    Bc = _vcycle_operator(levels, f2c, colors, level + 1, post)
+    z2 = S + R.T @ Bc @ R @ (np.eye(n) - A @ S)
+    return S + (np.eye(n) - S @ A) @ z2 if post else z2
+
+
+def test_hierarchy_injects_the_even_points():
+    from synthetic import stencil_hierarchy
+
+    mats, f2c = stencil_hierarchy(8, 12, 4, 3)
+    assert [m.grid for m in mats] == [(8, 12, 4), (4, 6, 2), (2, 3, 1)]
+    assert [len(m) for m in f2c] == [48, 6]
+    for lev, m in enumerate(f2c):
+        nx, ny, nz = mats[lev].grid
+        i = np.arange(mats[lev].n_rows)
+        even = np.flatnonzero(((i % nx) % 2 == 0) & (((i // nx) % ny) % 2 == 0) & ((i // (nx * ny)) % 2 == 0))
+        assert np.array_equal(np.asarray(m, dtype=np.int64), even)
+    with pytest.raises(ValueError):
+        stencil_hierarchy(6, 6, 6, 3)
+
+
+def test_vcycle_equals_operator_form_and_is_spd():
+    """The oracle's V-cycle, applied to the unit vectors, is the dense operator
+    B_0 of a 3-level hierarchy; B_0 is symmetric positive definite, while the
+    V-cycle without post-smoothing (a plausible mistake) is not symmetric."""
+    from synthetic import stencil_hierarchy
+
+    mats, f2c = stencil_hierarchy(8, 8, 4, 3)
+    colors = [gs.greedy_coloring(m) for m in mats]
+    n = mats[0].n_rows
+    got = np.column_stack([gs.vcycle(mats, f2c, colors, e) for e in np.eye(n)])
+    ref = _vcycle_operator(mats, f2c, colors)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(got - got.T)) <= 1e-12 * np.max(np.abs(got))
+    assert np.linalg.eigvalsh(0.5 * (got + got.T)).min() > 0
+    pre_only = _vcycle_operator(mats, f2c, colors, post=False)
+    assert np.max(np.abs(pre_only - pre_only.T)) > 1e-3 * np.max(np.abs(pre_only))
+
+
+def test_single_level_vcycle_is_one_sweep():
+    """With one level the V-cycle is z = 0 plus one sweep in reverse color
+    order: MG-preconditioned CG is then the SymGS-preconditioned CG with the
+    colors renumbered C-1-c, iterate for iterate."""
+    A = stencil27(9, 8, 7)
+    b = dense(A) @ np.ones(A.n_rows)
+    c = gs.greedy_coloring(A)
+    x1, it1, rel1 = gs.pcg_mg([A], [], [c], b)
+    x2, it2, rel2 = gs.pcg(A, b, c.max() - c)
+    assert it1 == it2 and rel1 == rel2 and np.array_equal(x1, x2)
+
+
+def test_mg_pcg_converges_faster_than_one_sweep():
+    from synthetic import stencil_hierarchy
+
+    mats, f2c = stencil_hierarchy(16, 16, 16, 4)
+    colors = [gs.greedy_coloring(m) for m in mats]
+    A = mats[0]
+    b = dense(A) @ np.ones(A.n_rows)
+    x, it, rel = gs.pcg_mg(mats, f2c, colors, b)
+    _, it_gs, _ = gs.pcg(A, b, colors[0])
+    assert rel <= 1e-10 and np.max(np.abs(x - 1)) < 1e-8
+    assert it < it_gs
+
+
+def test_forward_order_smoother_zeroes_the_injected_residual():
+    """Why the V-cycle's smoother runs the colors in reverse: after a sweep in
+    the forward order the residual vanishes on color 0, which on the stencil
+    hierarchy is exactly the set of injection points; in reverse order it
+    does not."""
+    from synthetic import stencil_hierarchy
+
+    mats, f2c = stencil_hierarchy(8, 8, 8, 2)
+    A, c = mats[0], gs.greedy_coloring(mats[0])
+    assert set(np.flatnonzero(c == 0)) == set(f2c[0].tolist())
+    r = uniform_vector(A.n_rows, seed=4)
+    res = lambda z: (r - dense(A) @ z)[f2c[0]]
+    assert np.abs(res(gs.symgs(A, r, np.zeros(A.n_rows), c))).max() < 1e-13
+    assert np.abs(res(gs.symgs(A, r, np.zeros(A.n_rows), c, reverse=True))).max() > 0.1
