@@ -5,8 +5,9 @@ Workload (default): the HPCG 27-point stencil matrix on a 104^3 grid
 (seed 0).  One step = one y = A x over the DIT-compressed matrix (pattern ID +
 terminal indices per row, value table {-1, 26}).  Inputs are resident in HBM
 before the timed region.  The same matrix as FP64 ELL is timed beside it, and
-(unless --no-cg) unpreconditioned CG to 1e-10 on the 192^3 grid with b = A*1,
-FP64 and mixed precision.
+(unless --no-cg) CG to 1e-10 on the 192^3 grid with b = A*1: FP64, mixed
+precision, preconditioned by one SymGS sweep, and preconditioned by one
+multigrid V-cycle over the 192/96/48/24 grid hierarchy.
 
 Prints one JSON line (see the repository's design notes for the fields).
 """
@@ -439,10 +440,12 @@ def run_batched(P, torch, dev, n_sys):
 
 def run_cg(g, P, torch, dev):
     """CG to 1e-10 on the g^3 stencil with b = A*1: FP64 DIT, mixed-precision DIT, FP64 ELL."""
-    from synthetic import stencil27
+    from synthetic import stencil27, stencil_hierarchy
 
     log(f"[bench] CG: generating {g}^3")
-    A = stencil27(g, g, g)
+    mg_levels = 4 if g % 8 == 0 else 1
+    mats, f2c = stencil_hierarchy(g, g, g, mg_levels)
+    A = mats[0]
     rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
     D = P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT")
     E = P.compress(rp, col, val, n_cols=A.n_cols, fmt="ELL")
@@ -463,6 +466,27 @@ def run_cg(g, P, torch, dev):
                      "outer_iters": stats[0]["outer_iters"], "relres_true_fp64": stats[0]["relres_true"],
                      "max_abs_err_vs_ones": err}
         log(f"[bench] CG {name}: {t * 1000:.2f} ms, {stats[0]['iters']} iters, relres {stats[0]['relres_true']:.2e}")
+    # preconditioned: one SymGS sweep (mode 2); one V-cycle over the grid hierarchy
+    levels = [D] + [P.compress(*(torch.from_numpy(a).to(dev) for a in (m.row_ptr, m.col, m.val)),
+                               n_cols=m.n_cols, fmt="DIT") for m in mats[1:]]
+    maps = [torch.from_numpy(f).to(dev) for f in f2c]
+    for name, run in (("pcg_symgs_dit", lambda it: P.cg_solve(D, b, mode=2, max_iter=it)),
+                      ("mg_pcg_dit", lambda it: P.cg_solve_mg(levels, maps, b, max_iter=it))):
+        run(3)  # warm-up: coloring and code path
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = run(5000)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = out[0]
+        x = out[1][0] if isinstance(out[1], list) else out[1]
+        s0 = out[2][0] if isinstance(out[2], list) else out[2]
+        res[name] = {"status": st, "seconds": round(t, 5), "iters": s0["iters"],
+                     "relres_true_fp64": s0["relres_true"],
+                     "max_abs_err_vs_ones": float((x - 1.0).abs().max().item())}
+        if name == "mg_pcg_dit":
+            res[name]["levels"] = [[m.grid[0], m.grid[1], m.grid[2]] for m in mats]
+        log(f"[bench] CG {name}: {t * 1000:.2f} ms, {s0['iters']} iters, relres {s0['relres_true']:.2e}")
     return res
 
 

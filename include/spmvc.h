@@ -170,6 +170,40 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs,
                       spmvc_cg_stat *stat, void *stream);
 
 /*
+ * Solve levels[0] x = b by FP64 CG preconditioned by one multigrid V-cycle
+ * per iteration: the HPCG iteration of Table I (Section III), with the
+ * V-cycle in that table's order.  On each level l above the coarsest: z = 0,
+ * one multicolor SymGS sweep on A_l z = r, t = A_l z (SpMV), restriction by
+ * injection r_{l+1}[i] = (r - t)[f2c[l][i]], the V-cycle on level l + 1,
+ * prolongation z[f2c[l][i]] += z_{l+1}[i], one more SymGS sweep.  On the
+ * coarsest level: z = 0 and one SymGS sweep.  The sweeps visit the colors
+ * backward, then forward (so that the rows updated last, which keep zero
+ * residual, are not the injection points of a grid hierarchy: greedy
+ * coloring gives those color 0).
+ *   levels:   host array [n_levels] of handles; levels[0] is the matrix of
+ *             the system, each level square with a non-zero diagonal in every
+ *             row, levels l >= 1 not empty and no larger than level l - 1.
+ *   f2c:      host array [n_levels - 1] of device pointers; f2c[l] holds
+ *             levels[l+1]'s row count entries (int32): the row of level l that
+ *             coarse row i is injected from.  Entries must lie in
+ *             [0, rows of level l) and be distinct: checked on the device at
+ *             the start (SPMVC_EINVAL).  The caller keeps them alive for the
+ *             call.  NULL when n_levels == 1.
+ *   n_levels: 1..16; with 1 the preconditioner is one SymGS sweep (colors
+ *             backward, then forward).
+ *   b, x:     device FP64 vectors of levels[0]'s row count; x is overwritten
+ *             (the last iterate on failure).
+ *   opts:     rtol, max_iter and check_every as for cg_solve; the other fields
+ *             are ignored.  NULL = defaults.
+ *   stat:     one host result.
+ * Stops on ||r|| <= rtol ||b||.  Returns SPMVC_OK, SPMVC_ENOCONV,
+ * SPMVC_ENOTSPD or SPMVC_EINVAL (bad arguments, f2c or diagonal).  Blocking.
+ */
+spmvc_status cg_solve_mg(const spmvc_matrix *levels, const int32_t *const *f2c, int32_t n_levels,
+                         const double *b, double *x, const spmvc_cg_opts *opts, spmvc_cg_stat *stat,
+                         void *stream);
+
+/*
  * Rebuild the CSR matrix (columns ascending per row, values bit-identical)
  * into caller-owned device arrays row_ptr [n_rows+1], col_idx [nnz],
  * vals [nnz].  Blocking.  The lossless round trip of Section V.

@@ -13,7 +13,7 @@ import ctypes
 import os
 
 __all__ = [
-    "load", "compress", "Matrix", "cg_solve", "SpmvcError",
+    "load", "compress", "Matrix", "cg_solve", "cg_solve_mg", "SpmvcError",
     "FMT_ELL", "FMT_DT", "FMT_DIT", "FMT_DITV", "F64", "F32",
 ]
 
@@ -31,7 +31,7 @@ ARR = {
 }
 
 EXPORTED = [
-    "spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
+    "spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_mg", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
     "spmvc_batched_config", "spmvc_set_allocator", "spmv_free", "spmvc_status_string", "spmvc_last_error",
 ]
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.spmv_block.argtypes = [P, i32, i32, P, i64, P, i64, P]
     lib.cg_solve.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(P), ctypes.POINTER(P),
                              ctypes.POINTER(CgOpts), ctypes.POINTER(CgStat), P]
+    lib.cg_solve_mg.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32, P, P, ctypes.POINTER(CgOpts),
+                                ctypes.POINTER(CgStat), P]
     lib.spmv_decompress.argtypes = [P, P, P, P, P]
     lib.spmv_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.spmv_get_array.argtypes = [P, i32, P, ctypes.POINTER(i64), P]
@@ -114,7 +116,7 @@ def load(path: str = LIB_PATH):
     lib.spmvc_status_string.argtypes = [i32]
     lib.spmvc_status_string.restype = ctypes.c_char_p
     lib.spmvc_last_error.restype = ctypes.c_char_p
-    for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "spmv_decompress", "spmv_info",
+    for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_mg", "spmv_decompress", "spmv_info",
                  "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs",
                  "spmv_colors", "spmvc_batched_config", "spmvc_set_allocator"]:
         getattr(lib, name).restype = ctypes.c_int
@@ -325,6 +327,28 @@ def cg_solve(mats, bs, xs=None, rtol=1e-10, max_iter=10000, mode=0, inner_rtol=1
     out = [{"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status,
             "relres_true": s.relres_true, "relres_recursive": s.relres_recursive} for s in stats]
     return st, xs, out
+
+
+def cg_solve_mg(levels, f2c, b, x=None, rtol=1e-10, max_iter=10000, check_every=16, stream=None):
+    """CG on levels[0] x = b preconditioned by one multigrid V-cycle per iteration.
+    levels: list of Matrix (finest first); f2c: list of len(levels) - 1 CUDA int32
+    tensors (fine row of each coarse row); b, x: CUDA float64 vectors."""
+    import torch
+
+    n_lev = len(levels)
+    if len(f2c) != n_lev - 1:
+        raise ValueError("f2c needs one map per coarse level")
+    if x is None:
+        x = torch.empty_like(b)
+    H = (ctypes.c_void_p * n_lev)(*[m.handle for m in levels])
+    F = (ctypes.c_void_p * max(n_lev - 1, 1))(*[_dev(f, torch.int32, "f2c").value for f in f2c])
+    o = CgOpts(rtol, max_iter, 0, 1e-5, 20, check_every, 0)
+    stat = (CgStat * 1)()
+    st = load().cg_solve_mg(H, F, n_lev, _dev(b, torch.float64, "b"), _dev(x, torch.float64, "x"),
+                            ctypes.byref(o), stat, _stream(stream))
+    s = stat[0]
+    return st, x, {"iters": s.iters, "status": s.status, "relres_true": s.relres_true,
+                   "relres_recursive": s.relres_recursive}
 
 
 def batched_config():

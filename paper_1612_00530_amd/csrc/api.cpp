@@ -244,6 +244,35 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs, const 
     });
 }
 
+spmvc_status cg_solve_mg(const spmvc_matrix *levels, const int32_t *const *f2c, int32_t n_levels, const double *b,
+                         double *x, const spmvc_cg_opts *opts, spmvc_cg_stat *stat, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!levels || !stat) return fail(SPMVC_EINVAL, "null argument");
+        if (n_levels < 1 || n_levels > 16) return fail(SPMVC_EINVAL, "n_levels must be in 1..16");
+        if (n_levels > 1 && !f2c) return fail(SPMVC_EINVAL, "f2c is null");
+        spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16, 2};
+        if (opts) o = *opts;
+        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1) return fail(SPMVC_EINVAL, "invalid cg options");
+        for (int l = 0; l < n_levels; ++l) {
+            const spmvc_matrix_s *A = levels[l];
+            if (!A) return fail(SPMVC_EINVAL, "matrix handle is null");
+            if (A->n_rows != A->n_cols) return fail(SPMVC_EINVAL, "CG needs square matrices");
+            if (l > 0) {
+                if (A->n_rows < 1 || A->n_rows > levels[l - 1]->n_rows)
+                    return fail(SPMVC_EINVAL, "a coarse level must be non-empty and no larger than the level above");
+                if (!f2c[l - 1]) return fail(SPMVC_EINVAL, "f2c entry is null");
+            }
+        }
+        const int64_t n = levels[0]->n_rows;
+        if (n > 0 && (!b || !x)) return fail(SPMVC_EINVAL, "b / x is null");
+        if (overlap(b, 8 * n, x, 8 * n)) return fail(SPMVC_EINVAL, "b and x overlap");
+        stat[0] = spmvc_cg_stat{};
+        const spmvc_status st = cg_solve_mg_impl(levels, f2c, n_levels, b, x, o, stat, static_cast<hipStream_t>(stream));
+        if (st != SPMVC_OK) set_error(spmvc_status_string(st));
+        return st;
+    });
+}
+
 spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx, double *vals, void *stream) {
     return guarded([&]() -> spmvc_status {
         if (!A || !row_ptr) return fail(SPMVC_EINVAL, "null argument");

@@ -589,11 +589,13 @@ spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, con
 }
 
 // Preconditioned CG (mode 2): M^-1 r = one multicolor SymGS sweep from zero.
+// prec(r, z, st, done) enqueues z = M^-1 r on s; every launch it makes
+// returns at once once st->done is set.
+template <class Prec>
 spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o, spmvc_cg_stat &stat,
-                       hipStream_t s) {
+                       hipStream_t s, Prec &&prec) {
     const int64_t n = M->n_rows;
     const int64_t nn = std::max<int64_t>(n, 1);
-    build_coloring(M, s);  // throws for a non-square matrix or a missing / zero diagonal
     Solver sv(s, spmv_dot_blocks(M));
     DevBuf r, z, p, q;
     r.alloc(sizeof(double) * nn);
@@ -606,9 +608,8 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
     // x = 0, r = b, rho0 = b.b; z = M^-1 r; p = z; rho = r.z
     k_cg_start<double, double><<<g, kRT, 0, s>>>(n, b, x, pr, pp, sv.part_a.as<double>());
     k_cg_start_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), o.rtol, o.max_iter);
-    k_pcg_zero<<<g, kRT, 0, s>>>(n, pz, sv.st());
     SPMVC_CHECK_LAUNCH();
-    launch_symgs(M, pr, pz, 1, s, done);
+    prec(pr, pz, sv.st(), done);
     k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.part_a.as<double>());
     k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st());
     SPMVC_CHECK_LAUNCH();
@@ -621,8 +622,7 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
             const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.part_sig.as<double>());
             k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.part_sig.as<double>(), static_cast<int>(ns),
                                            sv.part_b.as<double>(), sv.st(), par, it);
-            k_pcg_zero<<<g, kRT, 0, s>>>(n, pz, sv.st());
-            launch_symgs(M, pr, pz, 1, s, done);
+            prec(pr, pz, sv.st(), done);
             k_pcg_rz<<<g, kRT, 0, s>>>(n, pr, pz, sv.part_b.as<double>(), static_cast<int>(g), sv.part_a.as<double>(),
                                        sv.st(), par, it);
             k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.part_a.as<double>(), static_cast<int>(g), sv.st(), par);
@@ -640,6 +640,74 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
     stat.relres_recursive = h.rel;
     stat.relres_true = true_relres(M, sv, b, x, pq);
     return static_cast<spmvc_status>(h.status);
+}
+
+// ---- multigrid V-cycle as M^-1 -------------------------------------------------------
+// One V-cycle per iteration, in the order of Table I: on each level above the
+// coarsest z = 0, SymGS, t = A z, restriction r_c = (r - t)[f2c], the next
+// level, prolongation z[f2c] += z_c, SymGS; on the coarsest z = 0 and SymGS.
+// The smoother visits the colors backward, then forward: the rows a sweep
+// updates last keep zero residual, and in the forward order those are color
+// 0, which on a grid hierarchy holds the injection points (the coarse levels
+// would receive a zero residual).
+
+// r_c[i] = r[f2c[i]] - t[f2c[i]]
+__global__ __launch_bounds__(kRT) void k_mg_restrict(int64_t nc, const int32_t *__restrict__ f2c,
+                                                     const double *__restrict__ r, const double *__restrict__ t,
+                                                     double *__restrict__ rc, const CgScal *st) {
+    if (st->done) return;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRT) + threadIdx.x; i < nc;
+         i += static_cast<int64_t>(gridDim.x) * kRT) {
+        const int64_t j = f2c[i];
+        rc[i] = r[j] - t[j];
+    }
+}
+
+// z[f2c[i]] += z_c[i]  (f2c is injective, checked at set-up)
+__global__ __launch_bounds__(kRT) void k_mg_prolong(int64_t nc, const int32_t *__restrict__ f2c,
+                                                    const double *__restrict__ zc, double *__restrict__ z,
+                                                    const CgScal *st) {
+    if (st->done) return;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRT) + threadIdx.x; i < nc;
+         i += static_cast<int64_t>(gridDim.x) * kRT)
+        z[f2c[i]] += zc[i];
+}
+
+// bad = 1 unless every f2c entry lies in [0, nf) and none repeats (hits: nf zeros)
+__global__ __launch_bounds__(kRT) void k_mg_check(int64_t nc, const int32_t *__restrict__ f2c, int64_t nf,
+                                                  int *hits, int *bad) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kRT) + threadIdx.x; i < nc;
+         i += static_cast<int64_t>(gridDim.x) * kRT) {
+        const int64_t j = f2c[i];
+        if (j < 0 || j >= nf || atomicAdd(&hits[j], 1) != 0) atomicOr(bad, 1);
+    }
+}
+
+struct MgLevel {
+    spmvc_matrix_s *A = nullptr;
+    const int32_t *f2c = nullptr;  // this level's rows -> rows of the level above (levels >= 1)
+    DevBuf r, z;                   // right-hand side and correction (levels >= 1)
+    DevBuf t;                      // A z (every level but the coarsest)
+};
+
+void vcycle(std::vector<MgLevel> &L, size_t l, const double *r, double *z, const CgScal *st, const int *done,
+            hipStream_t s) {
+    spmvc_matrix_s *A = L[l].A;
+    const int64_t n = A->n_rows;
+    k_pcg_zero<<<rgrid(n), kRT, 0, s>>>(n, z, st);
+    SPMVC_CHECK_LAUNCH();
+    launch_symgs(A, r, z, 1, s, done, true);
+    if (l + 1 == L.size()) return;
+    MgLevel &c = L[l + 1];
+    const int64_t nc = c.A->n_rows;
+    double *t = L[l].t.as<double>();
+    launch_spmv(A, SPMVC_F64, z, t, s, done);
+    k_mg_restrict<<<rgrid(nc), kRT, 0, s>>>(nc, c.f2c, r, t, c.r.as<double>(), st);
+    SPMVC_CHECK_LAUNCH();
+    vcycle(L, l + 1, c.r.as<double>(), c.z.as<double>(), st, done, s);
+    k_mg_prolong<<<rgrid(nc), kRT, 0, s>>>(nc, c.f2c, c.z.as<double>(), z, st);
+    SPMVC_CHECK_LAUNCH();
+    launch_symgs(A, r, z, 1, s, done, true);
 }
 
 // Mixed precision: FP64 residual / update outside, FP32-SpMV CG inside.  The
@@ -699,6 +767,46 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
 
 }  // namespace
 
+spmvc_status cg_solve_mg_impl(spmvc_matrix const *levels, const int32_t *const *f2c, int n_levels, const double *b,
+                              double *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat, hipStream_t s) {
+    std::vector<MgLevel> L(n_levels);
+    for (int l = 0; l < n_levels; ++l) {
+        L[l].A = const_cast<spmvc_matrix_s *>(levels[l]);
+        build_coloring(L[l].A, s);  // throws for a missing or zero diagonal
+    }
+    {  // every injection map in range and injective
+        DevBuf flag;
+        flag.alloc(sizeof(int));
+        SPMVC_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+        for (int l = 1; l < n_levels; ++l) {
+            const int64_t nf = L[l - 1].A->n_rows, nc = L[l].A->n_rows;
+            DevBuf hits;
+            hits.alloc(sizeof(int) * nf);
+            SPMVC_HIP(hipMemsetAsync(hits.p, 0, sizeof(int) * nf, s));
+            k_mg_check<<<rgrid(nc), kRT, 0, s>>>(nc, f2c[l - 1], nf, hits.as<int>(), flag.as<int>());
+            SPMVC_CHECK_LAUNCH();
+            SPMVC_HIP(hipStreamSynchronize(s));  // before hits is released
+        }
+        int bad = 0;
+        SPMVC_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPMVC_HIP(hipStreamSynchronize(s));
+        if (bad) throw Error{SPMVC_EINVAL, "f2c entry out of range or repeated"};
+    }
+    for (int l = 0; l < n_levels; ++l) {
+        const size_t bytes = sizeof(double) * L[l].A->n_rows;
+        if (l > 0) {
+            L[l].f2c = f2c[l - 1];
+            L[l].r.alloc(bytes);
+            L[l].z.alloc(bytes);
+        }
+        if (l + 1 < n_levels) L[l].t.alloc(bytes);
+    }
+    const spmvc_status st = solve_pcg(L[0].A, b, x, o, stat[0], s, [&](const double *r, double *z, const CgScal *sc,
+                                                                       const int *done) { vcycle(L, 0, r, z, sc, done, s); });
+    SPMVC_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
 spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b, double *const *x,
                            const spmvc_cg_opts &o, spmvc_cg_stat *stat, hipStream_t s) {
     spmvc_status first_bad = SPMVC_OK;
@@ -708,7 +816,15 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
         return st;
     }
     if (o.mode == 2) {
-        const spmvc_status st = solve_pcg(const_cast<spmvc_matrix_s *>(A[0]), b[0], x[0], o, stat[0], s);
+        spmvc_matrix_s *M = const_cast<spmvc_matrix_s *>(A[0]);
+        build_coloring(M, s);  // throws for a missing or zero diagonal
+        const int64_t n = M->n_rows;
+        const spmvc_status st =
+            solve_pcg(M, b[0], x[0], o, stat[0], s, [&](const double *r, double *z, const CgScal *sc, const int *done) {
+                k_pcg_zero<<<rgrid(n), kRT, 0, s>>>(n, z, sc);
+                SPMVC_CHECK_LAUNCH();
+                launch_symgs(M, r, z, 1, s, done);
+            });
         SPMVC_HIP(hipStreamSynchronize(s));
         return st;
     }

@@ -194,6 +194,8 @@ unsigned launch_spmv_dot(const spmvc_matrix_s *M, int dt, const void *x, void *y
 int64_t spmv_dot_blocks(const spmvc_matrix_s *M);
 
 // cg.hip
+spmvc_status cg_solve_mg_impl(spmvc_matrix const *levels, const int32_t *const *f2c, int n_levels, const double *b,
+                              double *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat, hipStream_t s);
 spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                            double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,
                            hipStream_t s);
@@ -212,7 +214,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
 void build_coloring(spmvc_matrix_s *M, hipStream_t s);  // blocking; throws Error on a bad matrix
 // `skip` (device int, may be null): when *skip != 0 the sweep's kernels return at once.
 void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s,
-                  const int *skip = nullptr);
+                  const int *skip = nullptr, bool reverse = false);
 
 // scan.hip: exclusive prefix sum of n int64 values (in may equal out); returns the total.
 int64_t exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

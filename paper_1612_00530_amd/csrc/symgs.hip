@@ -303,7 +303,8 @@ void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
     M->gs_ready = 1;
 }
 
-void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s, const int *skip) {
+void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s, const int *skip,
+                  bool reverse) {
     const GsArgs a = gs_args(M);
     const int C = M->gs_n_colors;
     const int32_t *rows = M->gs_rows.as<int32_t>();
@@ -311,7 +312,8 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
     int last = -1;  // color of the previous launch
     for (int sw = 0; sw < sweeps; ++sw)
         for (int q = 0; q < 2 * C; ++q) {
-            const int c = q < C ? q : 2 * C - 1 - q;  // colors forward, then backward
+            const int cq = q < C ? q : 2 * C - 1 - q;  // colors forward, then backward
+            const int c = reverse ? C - 1 - cq : cq;      // or backward, then forward
             // Updating one color twice in a row repeats the same arithmetic on
             // unchanged neighbours (a color's rows read only other colors), so
             // the turn at the end of each half-sweep is launched once.

@@ -75,6 +75,16 @@ def test_null_arguments_rejected_on_host():
     assert lib.spmvc_set_allocator(alloc_t(), free_t(), None) == 0
     lib.spmvc_batched_config.argtypes = [P, P, P]
     assert lib.spmvc_batched_config(None, None, None) == -1
+    lib.cg_solve_mg.argtypes = [P, P, ctypes.c_int32, P, P, P, P, P]
+    stat = (ctypes.c_byte * 32)()
+    levels = (P * 2)(None, None)
+    assert lib.cg_solve_mg(None, None, 1, None, None, None, stat, None) == -1
+    assert lib.cg_solve_mg(levels, None, 0, None, None, None, stat, None) == -1
+    assert lib.cg_solve_mg(levels, None, 17, None, None, None, stat, None) == -1
+    assert lib.cg_solve_mg(levels, None, 2, None, None, None, stat, None) == -1
+    assert b"f2c" in lib.spmvc_last_error()
+    assert lib.cg_solve_mg(levels, None, 1, None, None, None, stat, None) == -1
+    assert b"handle" in lib.spmvc_last_error()
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
