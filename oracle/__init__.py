@@ -9,15 +9,20 @@ library (``paper_1612_00530_amd``) and never imports it.
 * ``codec`` -- the reference codec for the paper's compression schemes
   (Section V: value table V, sorted column list S_i, terminal indices T_i,
   displacement-pattern table), written with numpy.
-* ``gs`` -- multicolor symmetric Gauss-Seidel (the SymGS kernel of Table I)
-  and its greedy row-order coloring, written with numpy.
+* ``gs`` -- multicolor symmetric Gauss-Seidel (the SymGS kernel of Table I),
+  its greedy row-order coloring, and CG preconditioned by one sweep or by a
+  multigrid V-cycle, written with numpy.
+* ``reorder`` -- reverse Cuthill-McKee reordering and the symmetric
+  permutation B = P A P^T (the reordering Section V proposes after Table II).
 
 Pin status: ``spmv``/``spmv_block`` are pinned by dense brute force and by the
 stencil's closed forms; ``cg`` by ``numpy.linalg.solve`` on small systems, by
 x* = 1 for b = A*1 and by Krylov iteration-count bounds; ``codec`` by the
 paper's Fig. 1 example, its byte counts, lossless round trip and a
 decoded-walk SpMV; ``gs`` by the stencil's parity coloring and by the
-matrix-splitting form of Gauss-Seidel solved with dense triangular solves.
+matrix-splitting form of Gauss-Seidel solved with dense triangular solves,
+its V-cycle by the dense operator form; ``reorder`` by closed forms (paths,
+stars), a hand-numbered example and a level-by-level formulation.
 Nothing here is "parity unpinned".
 """
 from __future__ import annotations
