@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-irregular", action="store_true")
+    ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--batched-systems", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -324,6 +325,9 @@ def main():
     irregular = None
     if not args.no_irregular:
         irregular = run_irregular(P, torch, dev, args.steps)
+    reordered = None
+    if not args.no_reorder:
+        reordered = run_reorder(P, torch, dev, args.steps)
     cg = None
     if not args.no_cg:
         cg = run_cg(args.cg_grid, P, torch, dev)
@@ -372,6 +376,7 @@ def main():
         "ditv": ditv,
         "symgs": symgs,
         "irregular": irregular,
+        "reorder": reordered,
         "cg": cg,
         "batched_cg": batched,
         "paper_context_gflops_per_chip": {"uncompressed": 11.6, "compressed": 32.4, "hardware": "PEZY-SC"},
@@ -402,6 +407,50 @@ def run_irregular(P, torch, dev, steps):
            "dit_bytes": di["bytes_stream"] + 16 * A.n_rows, "ell_bytes": ei["bytes_stream"] + 16 * A.n_rows,
            "dit_GBps": round((di["bytes_stream"] + 16 * A.n_rows) / (d_us * 1e-6) / 1e9, 1), "tuned": tuned}
     log(f"[bench] irregular: DIT {d_us:.1f} us vs ELL {e_us:.1f} us")
+    return res
+
+
+def run_reorder(P, torch, dev, steps):
+    """The 104^3 stencil under a random row/column labelling (seed 0, applied with
+    the library's own permute): SpMV as given vs after reverse Cuthill-McKee
+    (spmv_rcm + spmv_permute), each compressed with format AUTO."""
+    from synthetic import stencil27, uniform_vector
+
+    log("[bench] reorder: scrambled 104^3")
+    A = stencil27(104, 104, 104)
+    rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+    scramble = torch.from_numpy(np.random.default_rng(0).permutation(A.n_rows).astype(np.int32)).to(dev)
+    srp, scol, sval = P.permute(rp, col, val, scramble)
+    del rp, col, val
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    perm = P.rcm(srp, scol)
+    torch.cuda.synchronize()
+    t_rcm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    brp, bcol, bval = P.permute(srp, scol, sval, perm)
+    torch.cuda.synchronize()
+    t_perm = time.perf_counter() - t0
+
+    def bandwidth(rp_, col_):
+        rows = torch.repeat_interleave(torch.arange(A.n_rows, device=dev), rp_[1:] - rp_[:-1])
+        return int((rows - col_.long()).abs().max().item())
+
+    res = {"grid": [104, 104, 104], "n": A.n_rows, "nnz": A.nnz, "rcm_seconds": round(t_rcm, 4),
+           "permute_seconds": round(t_perm, 4)}
+    x = torch.from_numpy(uniform_vector(A.n_cols, seed=0)).to(dev)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    for name, (r_, c_, v_) in (("scrambled", (srp, scol, sval)), ("rcm", (brp, bcol, bval))):
+        M = P.compress(r_, c_, v_, n_cols=A.n_cols, fmt="AUTO")
+        M.tune(torch.float64)
+        us = time_batch(lambda: M.spmv(x, y), max(20, steps // 2), torch) * 1000
+        info = M.info()
+        res[name] = {"format": info["fmt_name"] if "fmt_name" in info else info.get("fmt"), "P": info["P"],
+                     "escape_rows": info["n_escape_rows"], "bandwidth": bandwidth(r_, c_), "us": round(us, 3),
+                     "gflops": round(2.0 * A.nnz / (us * 1e-6) / 1e9, 2)}
+        log(f"[bench] reorder {name}: {us:.1f} us, bandwidth {res[name]['bandwidth']}, format {res[name]['format']}")
+        del M
+    res["speedup"] = round(res["scrambled"]["us"] / res["rcm"]["us"], 3)
     return res
 
 

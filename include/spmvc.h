@@ -204,6 +204,41 @@ spmvc_status cg_solve_mg(const spmvc_matrix *levels, const int32_t *const *f2c, 
                          void *stream);
 
 /*
+ * Reverse Cuthill-McKee reordering (the reordering of matrix and vector that
+ * Section V proposes after Table II, for locality of the x reads).
+ *   n:        rows = columns; 0..2^31-1.
+ *   row_ptr:  device int64 [n+1]; col_idx: device int32 [row_ptr[n]], strictly
+ *             ascending within each row; the pattern must be structurally
+ *             symmetric ((i, j) present iff (j, i) present); the diagonal is
+ *             optional and ignored.  Checked on the device: SPMVC_ERANGE,
+ *             SPMVC_EUNSORTED, SPMVC_EINVAL (not symmetric).
+ *   perm:     device int32 [n], caller-owned output: perm[k] = the old index of
+ *             the row numbered k.
+ * Numbering: each connected component starts at the unnumbered row of least
+ * (degree, index), degree = off-diagonal entries; breadth first, each level in
+ * order of the least number among a row's neighbours in the level before,
+ * then (degree, index); the whole sequence reversed.  Rows without
+ * off-diagonal entries come first in index order (last after the reversal).
+ * Cost: one pass per breadth-first level, plus one O(n) search per component
+ * of two or more rows.  Blocking.
+ */
+spmvc_status spmv_rcm(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int32_t *perm,
+                      void *stream);
+
+/*
+ * B = P A P^T: row k of B is row perm[k] of A with each column j renamed to
+ * the k' with perm[k'] == j; columns ascending.  Inputs as for spmv_rcm plus
+ * vals (device f64 [nnz]) and perm (device int32 [n], a permutation of
+ * 0..n-1, checked: SPMVC_EINVAL); symmetry is not required.  Outputs are
+ * caller-owned device arrays out_row_ptr [n+1], out_col_idx [nnz],
+ * out_vals [nnz] (values bit-identical).  Blocking.  x' = x[perm] then gives
+ * B x' = (A x)[perm].
+ */
+spmvc_status spmv_permute(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                          const double *vals, const int32_t *perm, int64_t *out_row_ptr,
+                          int32_t *out_col_idx, double *out_vals, void *stream);
+
+/*
  * Rebuild the CSR matrix (columns ascending per row, values bit-identical)
  * into caller-owned device arrays row_ptr [n_rows+1], col_idx [nnz],
  * vals [nnz].  Blocking.  The lossless round trip of Section V.

@@ -13,7 +13,7 @@ import ctypes
 import os
 
 __all__ = [
-    "load", "compress", "Matrix", "cg_solve", "cg_solve_mg", "SpmvcError",
+    "load", "compress", "Matrix", "cg_solve", "cg_solve_mg", "rcm", "permute", "SpmvcError",
     "FMT_ELL", "FMT_DT", "FMT_DIT", "FMT_DITV", "F64", "F32",
 ]
 
@@ -33,7 +33,8 @@ ARR = {
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_mg", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
-    "spmvc_batched_config", "spmvc_set_allocator", "spmv_free", "spmvc_status_string", "spmvc_last_error",
+    "spmvc_batched_config", "spmvc_set_allocator", "spmv_rcm", "spmv_permute", "spmv_free", "spmvc_status_string",
+    "spmvc_last_error",
 ]
 
 
@@ -101,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.cg_solve_mg.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32, P, P, ctypes.POINTER(CgOpts),
                                 ctypes.POINTER(CgStat), P]
     lib.spmv_decompress.argtypes = [P, P, P, P, P]
+    lib.spmv_rcm.argtypes = [i64, P, P, P, P]
+    lib.spmv_permute.argtypes = [i64, P, P, P, P, P, P, P, P]
     lib.spmv_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.spmv_get_array.argtypes = [P, i32, P, ctypes.POINTER(i64), P]
     lib.spmv_set_config.argtypes = [P, i32, i32]
@@ -118,7 +121,7 @@ def load(path: str = LIB_PATH):
     lib.spmvc_last_error.restype = ctypes.c_char_p
     for name in ["spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_mg", "spmv_decompress", "spmv_info",
                  "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs",
-                 "spmv_colors", "spmvc_batched_config", "spmvc_set_allocator"]:
+                 "spmv_colors", "spmvc_batched_config", "spmvc_set_allocator", "spmv_rcm", "spmv_permute"]:
         getattr(lib, name).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -349,6 +352,33 @@ def cg_solve_mg(levels, f2c, b, x=None, rtol=1e-10, max_iter=10000, check_every=
     s = stat[0]
     return st, x, {"iters": s.iters, "status": s.status, "relres_true": s.relres_true,
                    "relres_recursive": s.relres_recursive}
+
+
+def rcm(row_ptr, col, stream=None):
+    """Reverse Cuthill-McKee permutation (CUDA int32 tensor, perm[new] = old) of a
+    structurally symmetric CSR matrix given as CUDA int64 row_ptr / int32 col."""
+    import torch
+
+    n = row_ptr.numel() - 1
+    perm = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+    _check(load().spmv_rcm(n, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col, torch.int32, "col"),
+                           _dev(perm, torch.int32, "perm"), _stream(stream)))
+    return perm
+
+
+def permute(row_ptr, col, val, perm, stream=None):
+    """B = P A P^T of a CSR matrix (CUDA tensors); returns (row_ptr, col, val) of B."""
+    import torch
+
+    n = row_ptr.numel() - 1
+    out_rp = torch.empty_like(row_ptr)
+    out_col = torch.empty_like(col)
+    out_val = torch.empty_like(val)
+    _check(load().spmv_permute(n, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col, torch.int32, "col"),
+                               _dev(val, torch.float64, "val"), _dev(perm, torch.int32, "perm"),
+                               _dev(out_rp, torch.int64, "out_row_ptr"), _dev(out_col, torch.int32, "out_col"),
+                               _dev(out_val, torch.float64, "out_val"), _stream(stream)))
+    return out_rp, out_col, out_val
 
 
 def batched_config():

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspmvc.so")
-SOURCES = ["api.cpp", "tune.cpp", "scan.hip", "compress.hip", "spmv.hip", "cg.hip", "batched.hip", "symgs.hip"]
+SOURCES = ["api.cpp", "tune.cpp", "scan.hip", "compress.hip", "spmv.hip", "cg.hip", "batched.hip", "symgs.hip", "reorder.hip"]
 ARCH = os.environ.get("SPMVC_ARCH", "gfx950")
 
 FLAGS = [

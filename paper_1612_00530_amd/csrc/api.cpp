@@ -273,6 +273,27 @@ spmvc_status cg_solve_mg(const spmvc_matrix *levels, const int32_t *const *f2c, 
     });
 }
 
+spmvc_status spmv_rcm(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, int32_t *perm, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (n < 0 || n > INT32_MAX) return fail(SPMVC_EINVAL, "n must be in 0..2^31-1");
+        if (!row_ptr || (n > 0 && !perm)) return fail(SPMVC_EINVAL, "null argument");
+        rcm_order(n, row_ptr, col_idx, perm, static_cast<hipStream_t>(stream));
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_permute(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const double *vals,
+                          const int32_t *perm, int64_t *out_row_ptr, int32_t *out_col_idx, double *out_vals,
+                          void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (n < 0 || n > INT32_MAX) return fail(SPMVC_EINVAL, "n must be in 0..2^31-1");
+        if (!row_ptr || !out_row_ptr || (n > 0 && !perm)) return fail(SPMVC_EINVAL, "null argument");
+        permute_csr(n, row_ptr, col_idx, vals, perm, out_row_ptr, out_col_idx, out_vals,
+                    static_cast<hipStream_t>(stream));
+        return SPMVC_OK;
+    });
+}
+
 spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx, double *vals, void *stream) {
     return guarded([&]() -> spmvc_status {
         if (!A || !row_ptr) return fail(SPMVC_EINVAL, "null argument");

@@ -193,6 +193,11 @@ unsigned launch_spmv_dot(const spmvc_matrix_s *M, int dt, const void *x, void *y
                          const int *skip, double *dot);
 int64_t spmv_dot_blocks(const spmvc_matrix_s *M);
 
+// reorder.hip (blocking; throw Error on a bad matrix or permutation)
+void rcm_order(int64_t n, const int64_t *rp, const int32_t *col, int32_t *perm, hipStream_t s);
+void permute_csr(int64_t n, const int64_t *rp, const int32_t *col, const double *val, const int32_t *perm,
+                 int64_t *out_rp, int32_t *out_col, double *out_val, hipStream_t s);
+
 // cg.hip
 spmvc_status cg_solve_mg_impl(spmvc_matrix const *levels, const int32_t *const *f2c, int n_levels, const double *b,
                               double *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat, hipStream_t s);

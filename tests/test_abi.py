@@ -85,6 +85,12 @@ def test_null_arguments_rejected_on_host():
     assert b"f2c" in lib.spmvc_last_error()
     assert lib.cg_solve_mg(levels, None, 1, None, None, None, stat, None) == -1
     assert b"handle" in lib.spmvc_last_error()
+    lib.spmv_rcm.argtypes = [ctypes.c_int64, P, P, P, P]
+    assert lib.spmv_rcm(-1, None, None, None, None) == -1
+    assert lib.spmv_rcm(4, None, None, None, None) == -1
+    assert lib.spmv_rcm(1 << 31, None, None, None, None) == -1
+    lib.spmv_permute.argtypes = [ctypes.c_int64] + [P] * 8
+    assert lib.spmv_permute(4, None, None, None, None, None, None, None, None) == -1
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
