@@ -38,7 +38,8 @@ def compress(A, **kw):
 def row_scale(A, x):
     """sum_j |a_ij| |x_j| per row (the cancellation-safe normaliser of the SpMV error)."""
     rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
-    return np.bincount(rows, weights=np.abs(A.val) * np.abs(x[A.col]), minlength=A.n_rows)
+    with np.errstate(invalid="ignore"):  # 0 * inf in the special-value cases
+        return np.bincount(rows, weights=np.abs(A.val) * np.abs(x[A.col]), minlength=A.n_rows)
 
 
 def max_rel_err(A, x, y_gpu, y_ref):
