@@ -147,3 +147,45 @@ def test_spmv_after_reordering(fmt):
     # shell or the adjacent ones
     assert reorder.bandwidth(B) <= 2 * (3 * 23 ** 2 + 3 * 23 + 1)
     assert reorder.bandwidth(B) < reorder.bandwidth(S) // 5
+
+
+def test_full_size_104_scrambled():
+    """The benchmark's case: the 104^3 stencil under a random labelling (seed 0)
+    applied with spmv_permute, then RCM.  Checked by properties that hold at
+    any size: perm is a permutation; the reordered bandwidth is the largest
+    breadth-first shell around the corner the numbering starts from,
+    3 L^2 + 3 L + 1 with L = 103; the first row of the RCM order (the last
+    numbered) is a corner's far shell and the last row is a corner; SpMV of
+    the reordered matrix on sampled rows equals (A x)[perm] computed row by
+    row from the natural stencil."""
+    say("case: rcm full size 104^3")
+    torch = torch_mod()
+    P = lib()
+    g = 104
+    A = stencil27(g, g, g)
+    rp, col, val = to_dev(A)
+    scr = np.random.default_rng(0).permutation(A.n_rows).astype(np.int32)
+    srp, scol, sval = P.permute(rp, col, val, torch.from_numpy(scr).cuda())
+    perm = P.rcm(srp, scol)
+    brp, bcol, bval = P.permute(srp, scol, sval, perm)
+    torch.cuda.synchronize()
+    pn = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(pn), np.arange(A.n_rows))
+    rows = torch.repeat_interleave(torch.arange(A.n_rows, device="cuda"), brp[1:] - brp[:-1])
+    assert int((rows - bcol.long()).abs().max().item()) == 3 * 103 ** 2 + 3 * 103 + 1
+    # natural index of the vertex numbered k: scr maps scrambled -> natural
+    nat = scr.astype(np.int64)[pn]
+    ix, iy, iz = nat % g, (nat // g) % g, nat // (g * g)
+    corner = lambda i: (i == 0) | (i == g - 1)
+    assert corner(ix[-1]) and corner(iy[-1]) and corner(iz[-1])
+    x = uniform_vector(A.n_rows, seed=3)
+    M = P.compress(brp, bcol, bval, n_cols=A.n_cols, fmt="AUTO")
+    xb = torch.from_numpy(x[nat]).cuda()
+    y = M.spmv(xb).cpu().numpy()
+    sample = np.random.default_rng(4).choice(A.n_rows, 4000, replace=False)
+    for k in sample[:4000]:
+        i = int(nat[k])
+        lo, hi = int(A.row_ptr[i]), int(A.row_ptr[i + 1])
+        ref = float(np.dot(A.val[lo:hi], x[A.col[lo:hi]]))
+        scale = float(np.dot(np.abs(A.val[lo:hi]), np.abs(x[A.col[lo:hi]])))
+        assert abs(y[k] - ref) <= 1e-14 * scale
