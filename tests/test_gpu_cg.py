@@ -507,3 +507,19 @@ def test_mg_rejects_bad_hierarchies():
     assert st == 0 and stat["iters"] == 0 and np.all(x == 0)
     st, x, stat = mg_solve(mats, f2c, oracle.spmv(mats[0], np.ones(mats[0].n_rows)))
     assert st == 0 and np.abs(x - 1).max() < 1e-7
+
+
+def test_preconditioned_solves_of_an_empty_system():
+    """n = 0: modes 0 and 2 and the one-level MG solve return at once with
+    status OK and no iteration."""
+    say("case: empty preconditioned")
+    torch = torch_mod()
+    P = lib()
+    E = CSR(0, 0, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0))
+    M = compress(E)
+    b = torch.zeros(0, dtype=torch.float64, device="cuda")
+    for mode in (0, 2):
+        st, _, stats = P.cg_solve(M, b, mode=mode)
+        assert st == 0 and stats[0]["iters"] == 0
+    st, x, stat = P.cg_solve_mg([M], [], b)
+    assert st == 0 and stat["iters"] == 0 and x.numel() == 0
