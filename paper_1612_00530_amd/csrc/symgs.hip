@@ -106,11 +106,23 @@ template <class F> __device__ __forceinline__ void gs_visit(const GsArgs &a, int
     }
 }
 
+// Workgroups go to the 8 XCDs round-robin (block b on XCD b mod 8).  The
+// logical block index below gives each XCD one contiguous run of the color's
+// rows, which lie in a contiguous part of the grid, so the x lines that
+// neighbouring blocks share are fetched into one XCD's L2 rather than several.
+// A bijection of [0, gridDim.x): XCD k holds blocks k, k + 8, ..., and its run
+// starts after the runs of XCDs 0..k-1.
+__device__ inline int64_t xcd_block() {
+    const unsigned nb = gridDim.x, bid = blockIdx.x;
+    const unsigned xcd = bid % 8u, slot = bid / 8u, q = nb / 8u, r = nb % 8u;
+    return static_cast<int64_t>(xcd) * q + (xcd < r ? xcd : r) + slot;
+}
+
 // The rows rows[0..n) of one color: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.
 __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int32_t *__restrict__ rows, int64_t n,
                                                             const double *__restrict__ b, double *x, const int *skip) {
     if (skip && *skip) return;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
+    const int64_t t = xcd_block() * kGsThreads + threadIdx.x;
     if (t >= n) return;
     const int64_t i = rows[t];
     double s = 0.0, d = 0.0;
@@ -133,7 +145,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
                                                           const uint32_t *__restrict__ meta, int64_t n,
                                                           const double *__restrict__ b, double *x, const int *skip) {
     if (skip && *skip) return;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
+    const int64_t t = xcd_block() * kGsThreads + threadIdx.x;
     if (t >= n) return;
     const int64_t i = rows[t];
     // the row's pattern ID and T_i[0], stored in color order: read alongside
