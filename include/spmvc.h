@@ -219,7 +219,10 @@ spmvc_status cg_solve_mg(const spmvc_matrix *levels, const int32_t *const *f2c, 
  *             ascending within each row; the pattern must be structurally
  *             symmetric ((i, j) present iff (j, i) present); the diagonal is
  *             optional and ignored.  Checked on the device: SPMVC_ERANGE,
- *             SPMVC_EUNSORTED, SPMVC_EINVAL (not symmetric).
+ *             SPMVC_EUNSORTED, SPMVC_EINVAL (not symmetric); rows longer than
+ *             1024 entries give SPMVC_EUNSUPPORTED (ordering a row's entries
+ *             takes O(length^2) work in one thread; the same limit holds for
+ *             spmv_permute).
  *   perm:     device int32 [n], caller-owned output: perm[k] = the old index of
  *             the row numbered k.
  * Numbering: each connected component starts at the unnumbered row of least

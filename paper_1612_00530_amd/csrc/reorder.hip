@@ -27,10 +27,15 @@ namespace {
 
 constexpr int kR = 256;
 constexpr int kBadRange = 1, kBadOrder = 2, kBadSym = 4;
+// One thread orders a row's entries (or a vertex's children) by counting, in
+// O(len^2): rows longer than this are refused rather than left to run for
+// minutes in one thread.
+constexpr int64_t kMaxRowLen = 1024;
 
 unsigned rblocks(int64_t n) { return grid_for(std::max<int64_t>(n, 1), kR, 8192); }
 
-// row_ptr monotone from 0 to nnz, columns in [0, n) and strictly ascending
+// row_ptr monotone from 0 to nnz, columns in [0, n) and strictly ascending;
+// flags[1] = longest row
 __global__ __launch_bounds__(kR) void k_ro_validate(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
                                                    int *flags) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * kR + threadIdx.x;
@@ -41,6 +46,7 @@ __global__ __launch_bounds__(kR) void k_ro_validate(int64_t n, int64_t nnz, cons
             atomicOr(flags, kBadRange);
             continue;
         }
+        atomicMax(&flags[1], static_cast<int>(b - a > INT_MAX ? INT_MAX : b - a));
         int64_t prev = -1;
         for (int64_t k = a; k < b; ++k) {
             const int64_t c = col[k];
@@ -237,15 +243,17 @@ int64_t validate_csr(int64_t n, const int64_t *rp, const int32_t *col, bool symm
     if (nnz < 0) throw Error{SPMVC_ERANGE, "row_ptr[n] is negative"};
     if (nnz > 0 && !col) throw Error{SPMVC_EINVAL, "col_idx is null"};
     DevBuf flags;
-    flags.alloc(sizeof(int));
-    SPMVC_HIP(hipMemsetAsync(flags.p, 0, sizeof(int), s));
+    flags.alloc(2 * sizeof(int));
+    SPMVC_HIP(hipMemsetAsync(flags.p, 0, 2 * sizeof(int), s));
     k_ro_validate<<<rblocks(n), kR, 0, s>>>(n, nnz, rp, col, flags.as<int>());
     SPMVC_CHECK_LAUNCH();
-    int f = 0;
-    SPMVC_HIP(hipMemcpyAsync(&f, flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    int fl[2] = {0, 0};
+    SPMVC_HIP(hipMemcpyAsync(fl, flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     SPMVC_HIP(hipStreamSynchronize(s));
+    int f = fl[0];
     if (f & kBadRange) throw Error{SPMVC_ERANGE, "row_ptr not monotone / not ending at nnz, or a column out of range"};
     if (f & kBadOrder) throw Error{SPMVC_EUNSORTED, "column indices must be strictly ascending within each row"};
+    if (fl[1] > kMaxRowLen) throw Error{SPMVC_EUNSUPPORTED, "reordering takes rows of at most 1024 entries"};
     if (symmetric) {
         k_ro_symmetric<<<rblocks(n), kR, 0, s>>>(n, rp, col, flags.as<int>());
         SPMVC_CHECK_LAUNCH();

@@ -189,3 +189,24 @@ def test_full_size_104_scrambled():
         ref = float(np.dot(A.val[lo:hi], x[A.col[lo:hi]]))
         scale = float(np.dot(np.abs(A.val[lo:hi]), np.abs(x[A.col[lo:hi]])))
         assert abs(y[k] - ref) <= 1e-14 * scale
+
+
+def test_rows_beyond_the_length_limit_are_refused():
+    """A row of more than 1024 entries (an arrowhead: vertex 0 coupled to all)
+    is refused with SPMVC_EUNSUPPORTED by both calls before any ordering
+    kernel runs; 1024 entries pass."""
+    say("case: reorder row-length limit")
+    torch = torch_mod()
+    P = lib()
+    for n, ok in ((1025, False), (1024, True)):
+        A = graph(n, [(0, j) for j in range(1, n)])  # row 0: n entries with the diagonal
+        if ok:
+            assert np.array_equal(gpu_rcm(A), reorder.rcm(A))
+            continue
+        with pytest.raises(P.SpmvcError) as e:
+            gpu_rcm(A)
+        assert e.value.status == -8
+        rp, col, val = to_dev(A)
+        with pytest.raises(P.SpmvcError) as e:
+            P.permute(rp, col, val, torch.arange(n, dtype=torch.int32, device="cuda"))
+        assert e.value.status == -8
