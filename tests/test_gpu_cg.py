@@ -561,3 +561,21 @@ def test_mg_levels_in_different_formats():
         assert st == -7 and stat["iters"] == 4
         xs.append(x.cpu().numpy())
     assert np.max(np.abs(xs[0] - xs[1])) <= 1e-11 * np.max(np.abs(xs[0]))
+
+
+@pytest.mark.parametrize("fmt", ["DIT", "ELL"])
+def test_pcg_irregular_matches_oracle(fmt):
+    """Mode 2 on the irregular stencil (escape rows and raw values: the
+    generic sweep kernel): the oracle's iteration count within 2, 1e-10 in
+    the oracle's residual, x = 1."""
+    from oracle import gs
+
+    say("case: pcg irregular", fmt)
+    A = stencil27_irregular(14, 12, 10, seed=4)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    st, x, stats = solve(A, b, fmt=fmt, mode=2)
+    assert st == 0 and stats[0]["status"] == 0
+    assert oracle.relres(A, b, x) <= 1.5e-10
+    assert np.abs(x - 1).max() < 1e-7
+    _, it_ref, _ = gs.pcg(A, b, gs.greedy_coloring(A))
+    assert abs(stats[0]["iters"] - it_ref) <= 2
