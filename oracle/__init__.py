@@ -17,7 +17,9 @@ library (``paper_1612_00530_amd``) and never imports it.
 
 Pin status: ``spmv``/``spmv_block`` are pinned by dense brute force and by the
 stencil's closed forms; ``cg`` by ``numpy.linalg.solve`` on small systems, by
-x* = 1 for b = A*1 and by Krylov iteration-count bounds; ``codec`` by the
+x* = 1 for b = A*1 and by Krylov iteration-count bounds; ``relres`` two-sidedly
+by closed forms (x = 0 gives 1; x = 1 + delta e_k against b = A*1 gives
+delta ||A e_k|| / ||A*1||, counted from the grid) and by the dense definition; ``codec`` by the
 paper's Fig. 1 example, its byte counts, lossless round trip and a
 decoded-walk SpMV; ``gs`` by the stencil's parity coloring and by the
 matrix-splitting form of Gauss-Seidel solved with dense triangular solves,
