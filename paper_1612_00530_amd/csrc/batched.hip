@@ -38,6 +38,7 @@ namespace spmvc {
 namespace {
 
 constexpr int kT = 256;     // threads per block = rows per tile
+constexpr int kMaxRestarts = 4;  // restarts from the true residual per solve (see k_brestart_fin)
 
 struct SysDesc {
     int64_t row0, n;   // first global row, rows
@@ -533,10 +534,12 @@ __global__ __launch_bounds__(kT) void k_bstart_fin(Batch b) {
             b.rho[b.n_sys * b.nrhs + q] = 0.0;
             b.rho0[q] = rr;
             b.iters[q] = 0;
+            // a right-hand side that is not finite (NaN or inf in b) stops its pair at once
+            const bool bad = !(rr == rr) || rr > 1.7e308;
             b.relres[q] = rr > 0.0 ? 1.0 : 0.0;
-            b.status[q] = SPMVC_OK;
-            b.done[q] = rr > 0.0 ? 0 : 1;
-            if (rr > 0.0) {
+            b.status[q] = bad ? SPMVC_EINVAL : SPMVC_OK;
+            b.done[q] = rr > 0.0 && !bad ? 0 : 1;
+            if (rr > 0.0 && !bad) {
                 ++active;
                 atomicAdd(b.n_active, 1);
             }
@@ -692,6 +695,49 @@ __global__ __launch_bounds__(kT) void k_bresid_fin(Batch b, double *out) {
         const double rr = sys_sum(b, d, r);
         if (threadIdx.x == 0) out[s * b.nrhs + r] = rr;
     }
+}
+
+// After the true residuals (rr, per pair; Q = A X): a pair that stopped with
+// SPMVC_OK on its recursive residual while its true one misses the tolerance
+// restarts from the true residual -- flagged in `step`, running again with
+// rho = rr of its current iteration parity (rho0, the ||b||^2 of the stopping
+// test, is kept).  A system runs again when one of its pairs does.
+__global__ __launch_bounds__(kT) void k_brestart_fin(Batch b, const double *rr) {
+    const int s = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const int np = b.n_sys * b.nrhs;
+    int any = 0;
+    for (int r = 0; r < b.nrhs; ++r) {
+        const int q = s * b.nrhs + r;
+        const bool again = b.done[q] && b.status[q] == SPMVC_OK && b.iters[q] < b.max_iter &&
+                           sqrt(rr[q]) > b.rtol * sqrt(b.rho0[q]);
+        b.step[q] = again ? 1 : 0;
+        if (again) {
+            b.done[q] = 0;
+            b.rho[(b.iters[q] & 1) * np + q] = rr[q];
+            b.relres[q] = sqrt(rr[q]) / sqrt(b.rho0[q]);
+            atomicAdd(b.n_active, 1);
+            any = 1;
+        }
+    }
+    b.sys_active[s] = any;
+}
+
+// R = B - Q (Q = A X) and P = R for the restarting pairs
+template <int LPR> __global__ __launch_bounds__(kT) void k_brestart(Batch b) {
+    const int tile = blockIdx.x;
+    const int s = b.tile_sys[tile];
+    if (!b.sys_active[s]) return;
+    const SysDesc &d = b.sys[s];
+    const int nr = b.nrhs;
+    const int rr_ = threadIdx.x % LPR;
+    const int q = s * nr + (rr_ < nr ? rr_ : 0);
+    if (rr_ >= nr || !b.step[q]) return;
+    SPMVC_TILE_SLOTS(if (ok) {
+        const double t = b.B[g] - b.Q[g];
+        b.R[g] = t;
+        b.P[g] = t;
+    })
 }
 
 __global__ void k_set_all(int32_t *p, int32_t v, int n) {
@@ -1012,46 +1058,62 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
 
     const int chunk = std::max(1, o.check_every);
     int it = 0;
+    // iterations in groups of `chunk` until every pair has stopped
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = st;
+    struct GraphFree {
+        hipGraphExec_t *e;
+        hipStream_t *s;
+        hipStream_t owner;
+        ~GraphFree() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*s != owner) (void)hipStreamDestroy(*s);
+        }
+    } gf{&exec, &cs, st};
     if (use_graph) {
-        // `chunk` iterations recorded once, replayed until every pair has stopped
-        hipStream_t cs;
+        // `chunk` iterations recorded once, replayed
         SPMVC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        struct StreamFree {
-            hipStream_t s;
-            ~StreamFree() { (void)hipStreamDestroy(s); }
-        } sf{cs};
         SPMVC_HIP(hipStreamSynchronize(st));
         hipGraph_t graph = nullptr;
         SPMVC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         for (int j = 0; j < chunk; ++j) record_iteration(b, cs);
         SPMVC_HIP(hipStreamEndCapture(cs, &graph));
-        hipGraphExec_t exec = nullptr;
         const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         SPMVC_HIP(ie);
-        struct ExecFree {
-            hipGraphExec_t e;
-            ~ExecFree() { (void)hipGraphExecDestroy(e); }
-        } ef{exec};
-        while (it < o.max_iter && active() > 0) {
-            SPMVC_HIP(hipGraphLaunch(exec, cs));
-            SPMVC_HIP(hipStreamSynchronize(cs));
-            it += chunk;
-        }
-    } else {
-        while (it < o.max_iter && active() > 0) {
-            for (int j = 0; j < chunk; ++j) record_iteration(b, st);
-            SPMVC_CHECK_LAUNCH();
-            it += chunk;
-        }
     }
-
-    // true residuals ||b - A x|| / ||b|| per pair
-    k_set_all<<<static_cast<unsigned>((n_sys + 255) / 256), 256, 0, st>>>(b.sys_active, 1, n_sys);
-    launch_bspmv(b, b.X, b.Q, 0, st);
-    SPMVC_LPR_LAUNCH(k_bresid, static_cast<unsigned>(n_tiles), st, b);
-    k_bresid_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b, rr.as<double>());
-    SPMVC_CHECK_LAUNCH();
+    auto run = [&]() {
+        while (it < o.max_iter && active() > 0) {
+            if (use_graph) {
+                SPMVC_HIP(hipGraphLaunch(exec, cs));
+                SPMVC_HIP(hipStreamSynchronize(cs));
+            } else {
+                for (int j = 0; j < chunk; ++j) record_iteration(b, st);
+                SPMVC_CHECK_LAUNCH();
+            }
+            it += chunk;
+        }
+    };
+    // true residuals ||b - A x||^2 per pair into rr (every system)
+    auto true_residuals = [&]() {
+        k_set_all<<<static_cast<unsigned>((n_sys + 255) / 256), 256, 0, st>>>(b.sys_active, 1, n_sys);
+        launch_bspmv(b, b.X, b.Q, 0, st);
+        SPMVC_LPR_LAUNCH(k_bresid, static_cast<unsigned>(n_tiles), st, b);
+        k_bresid_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b, rr.as<double>());
+        SPMVC_CHECK_LAUNCH();
+    };
+    run();
+    true_residuals();
+    // pairs whose recursive residual met the tolerance but whose true one did
+    // not restart from the true residual
+    for (int k = 0; k < kMaxRestarts && active() == 0; ++k) {
+        k_brestart_fin<<<static_cast<unsigned>(n_sys), kT, 0, st>>>(b, rr.as<double>());
+        SPMVC_LPR_LAUNCH(k_brestart, static_cast<unsigned>(n_tiles), st, b);
+        SPMVC_CHECK_LAUNCH();
+        if (active() == 0) break;
+        run();
+        true_residuals();
+    }
     std::vector<double> h_rr(np), h_rho0(np), h_rel(np);
     std::vector<int32_t> h_it(np), h_st(np), h_done(np);
     SPMVC_HIP(hipMemcpyAsync(h_rr.data(), rr.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
@@ -1072,6 +1134,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         c.status = h_done[q] ? h_st[q] : SPMVC_ENOCONV;
         c.relres_recursive = h_rel[q];
         c.relres_true = h_rho0[q] > 0.0 ? std::sqrt(h_rr[q]) / std::sqrt(h_rho0[q]) : std::sqrt(h_rr[q]);
+        if (c.status == SPMVC_OK && !(c.relres_true <= o.rtol)) c.status = SPMVC_ENOCONV;
         if (c.status != SPMVC_OK && first_bad == SPMVC_OK) first_bad = static_cast<spmvc_status>(c.status);
     }
     return first_bad;

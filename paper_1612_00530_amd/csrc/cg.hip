@@ -112,20 +112,28 @@ inline bool aligned16(const void *a, const void *b, const void *c = nullptr) {
     return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) & 15) == 0;
 }
 
-// x = 0, r = rhs, p = rhs; partials of r.r
+// x = 0, r = rhs / norm, p = r; partials of r.r.  The division (in the
+// precision of rhs, before any conversion) lets the mixed-precision driver
+// hand the FP32 solve a right-hand side of unit norm whatever the scale of
+// the FP64 residual; norm == 1 leaves rhs unchanged.
 template <class Real, class RhsT>
-__global__ __launch_bounds__(kRT) void k_cg_start(int64_t n, const RhsT *__restrict__ rhs, Real *__restrict__ x,
-                                                  Real *__restrict__ r, Real *__restrict__ p, double *partials) {
+__global__ __launch_bounds__(kRT) void k_cg_start(int64_t n, const RhsT *__restrict__ rhs, RhsT norm,
+                                                  Real *__restrict__ x, Real *__restrict__ r, Real *__restrict__ p,
+                                                  double *partials) {
     double acc = 0.0;
+    const bool unit = norm == RhsT(1);
     SPMVC_STREAM4(
         Real v[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) v[u] = static_cast<Real>(rhs[i + u * stride_]);
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            const RhsT w = rhs[i + u * stride_];
+            v[u] = static_cast<Real>(unit ? w : w / norm);
+        }
 _Pragma("unroll") for (int u = 0; u < 4; ++u) {
             x[i + u * stride_] = Real(0); r[i + u * stride_] = v[u]; p[i + u * stride_] = v[u];
             acc += dd(v[u]) * dd(v[u]);
         }
         ,
-        const Real v = static_cast<Real>(rhs[i]);
+        const Real v = static_cast<Real>(unit ? rhs[i] : rhs[i] / norm);
         x[i] = Real(0); r[i] = v; p[i] = v;
         acc += dd(v) * dd(v);
     )
@@ -151,6 +159,27 @@ __global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, in
     if (!(tot == tot) || tot > 1.7e308) {
         st->done = 1;
         st->status = SPMVC_EINVAL;
+    }
+}
+
+// Restart of a finished solve whose recursive residual met the tolerance but
+// whose true FP64 residual b - A x (already in r, squared norm rr) did not:
+// p = r and the scalars of iteration `it` take rho = rr; rho0 (the ||b||^2 of
+// the stopping test) is kept, so the solve continues towards the same target
+// from the true residual.
+__global__ __launch_bounds__(kRT) void k_cg_resume(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                                                   CgScal *st, double rr, int it) {
+    SPMVC_STREAM4(
+_Pragma("unroll") for (int u = 0; u < 4; ++u) p[i + u * stride_] = r[i + u * stride_];
+        ,
+        p[i] = r[i];
+    )
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rho[it & 1] = rr;
+        st->rel = sqrt(rr) / sqrt(st->rho0);
+        st->done = 0;
+        st->status = SPMVC_OK;
+        st->go[0] = st->go[1] = 0;
     }
 }
 
@@ -312,10 +341,22 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
     if (threadIdx.x == 0) rz_part[blockIdx.x] = b;
 }
 
-// rho[0] = r.z (one block)
-__global__ __launch_bounds__(kRT) void k_pcg_init_fin(const double *rz_part, int np, CgScal *st) {
+// rho[slot] = r.z (one block)
+__global__ __launch_bounds__(kRT) void k_pcg_init_fin(const double *rz_part, int np, CgScal *st, int slot) {
     const double tot = sum_partials<kRT>(rz_part, np);
-    if (threadIdx.x == 0 && !st->done) st->rho[0] = tot;
+    if (threadIdx.x == 0 && !st->done) st->rho[slot] = tot;
+}
+
+// Restart of a preconditioned solve from its true residual (see k_cg_resume):
+// the solve is running again from iteration `it`; the preconditioner and
+// k_pcg_init / k_pcg_init_fin (slot it & 1) follow.
+__global__ void k_pcg_resume(CgScal *st, double rr) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rel = sqrt(rr) / sqrt(st->rho0);
+        st->done = 0;
+        st->status = SPMVC_OK;
+        st->go[0] = st->go[1] = 0;
+    }
 }
 
 // sigma = p.q (the SpMV's partials); alpha = rho / sigma; x += alpha p;
@@ -456,11 +497,11 @@ __global__ __launch_bounds__(kRT) void k_residual_fin(const double *rr_part, con
     }
 }
 
-// x += (double) d
-__global__ void k_add_f32(int64_t n, double *__restrict__ x, const float *__restrict__ d) {
+// x += scale * (double) d
+__global__ void k_add_f32(int64_t n, double *__restrict__ x, const float *__restrict__ d, double scale) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-        x[i] += static_cast<double>(d[i]);
+        x[i] += scale * static_cast<double>(d[i]);
 }
 
 // column r of a row-interleaved block <-> contiguous vector
@@ -508,20 +549,18 @@ struct Solver {
     }
 };
 
-// Runs CG on A z = rhs (z overwritten) with vectors of type Real; returns the final scalars.
-template <class Real, class RhsT>
-CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Real *r, Real *p, Real *q, double rtol,
-              int max_iter, int check_every) {
+// CG iterations it0, it0 + 1, ... on the state in (z, r, p) until the solve
+// stops or max_iter; returns the final scalars.
+template <class Real>
+CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p, Real *q, int it0, int max_iter,
+                  int check_every) {
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     const int dt = std::is_same<Real, double>::value ? SPMVC_F64 : SPMVC_F32;
     constexpr int VW = pack_width<Real>();
     const bool vec_u = aligned16(r, q), vec_p = aligned16(z, r, p);
-    k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, z, r, p, sv.part_a.as<double>());
-    k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), rtol, max_iter);
-    SPMVC_CHECK_LAUNCH();
     const int chunk = std::max(1, check_every);
-    int it = 0;
+    int it = it0;
     while (it < max_iter) {
         if (sv.read().done) break;
         for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
@@ -550,6 +589,19 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, Real *z, Rea
     return out;
 }
 
+// Runs CG on A z = rhs / rhs_norm (z overwritten) with vectors of type Real;
+// returns the final scalars.
+template <class Real, class RhsT>
+CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, RhsT rhs_norm, Real *z, Real *r, Real *p,
+              Real *q, double rtol, int max_iter, int check_every) {
+    const int64_t n = M->n_rows;
+    const unsigned g = rgrid(n);
+    k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, rhs_norm, z, r, p, sv.part_a.as<double>());
+    k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), rtol, max_iter);
+    SPMVC_CHECK_LAUNCH();
+    return cg_iterate<Real>(M, sv, z, r, p, q, 0, max_iter, check_every);
+}
+
 // ||b - A x||^2 and ||b||^2 in FP64 (tmp: n doubles; r receives b - Ax when not null)
 void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp, double *r,
               double &rr, double &bb) {
@@ -564,11 +616,19 @@ void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double
     bb = h.aux[1];
 }
 
+double ratio(double rr, double bb) { return bb > 0.0 ? std::sqrt(rr) / std::sqrt(bb) : std::sqrt(rr); }
+
 double true_relres(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp) {
     double rr, bb;
     residual(M, sv, b, x, tmp, nullptr, rr, bb);
-    return bb > 0.0 ? std::sqrt(rr) / std::sqrt(bb) : std::sqrt(rr);
+    return ratio(rr, bb);
 }
+
+// A solve that stopped on its recursive residual is accepted only when its
+// true FP64 residual ||b - A x|| / ||b|| meets the tolerance too; otherwise it
+// restarts from the true residual (at most this many times) and, if still
+// short when it stops again, reports SPMVC_ENOCONV.
+constexpr int kMaxRestarts = 4;
 
 spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
                         spmvc_cg_stat &stat, hipStream_t s) {
@@ -578,13 +638,23 @@ spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, con
     r.alloc(sizeof(double) * std::max<int64_t>(n, 1));
     p.alloc(sizeof(double) * std::max<int64_t>(n, 1));
     q.alloc(sizeof(double) * std::max<int64_t>(n, 1));
-    const CgScal h = run_cg<double, double>(M, sv, b, x, r.as<double>(), p.as<double>(), q.as<double>(), o.rtol,
-                                            o.max_iter, o.check_every);
+    double *pr = r.as<double>(), *pp = p.as<double>(), *pq = q.as<double>();
+    CgScal h = run_cg<double, double>(M, sv, b, 1.0, x, pr, pp, pq, o.rtol, o.max_iter, o.check_every);
+    double rr = 0.0, bb = 0.0;
+    residual(M, sv, b, x, pq, pr, rr, bb);  // r = b - A x
+    for (int k = 0; k < kMaxRestarts && h.status == SPMVC_OK && ratio(rr, bb) > o.rtol && h.iters < o.max_iter;
+         ++k) {
+        k_cg_resume<<<rgrid(n), kRT, 0, s>>>(n, pr, pp, sv.st(), rr, h.iters);
+        SPMVC_CHECK_LAUNCH();
+        h = cg_iterate<double>(M, sv, x, pr, pp, pq, h.iters, o.max_iter, o.check_every);
+        residual(M, sv, b, x, pq, pr, rr, bb);
+    }
+    if (h.status == SPMVC_OK && ratio(rr, bb) > o.rtol) h.status = SPMVC_ENOCONV;
     stat.iters = h.iters;
     stat.outer_iters = 0;
     stat.status = h.status;
     stat.relres_recursive = h.rel;
-    stat.relres_true = true_relres(M, sv, b, x, q.as<double>());
+    stat.relres_true = ratio(rr, bb);
     return static_cast<spmvc_status>(h.status);
 }
 
@@ -606,39 +676,52 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
     double *pr = r.as<double>(), *pz = z.as<double>(), *pp = p.as<double>(), *pq = q.as<double>();
     const int *done = &sv.st()->done;
     // x = 0, r = b, rho0 = b.b; z = M^-1 r; p = z; rho = r.z
-    k_cg_start<double, double><<<g, kRT, 0, s>>>(n, b, x, pr, pp, sv.part_a.as<double>());
+    k_cg_start<double, double><<<g, kRT, 0, s>>>(n, b, 1.0, x, pr, pp, sv.part_a.as<double>());
     k_cg_start_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), o.rtol, o.max_iter);
     SPMVC_CHECK_LAUNCH();
-    prec(pr, pz, sv.st(), done);
-    k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.part_a.as<double>());
-    k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st());
-    SPMVC_CHECK_LAUNCH();
-    const int chunk = std::max(1, o.check_every);
-    int it = 0;
-    while (it < o.max_iter) {
-        if (sv.read().done) break;
-        for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
-            const int par = it & 1;
-            const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.part_sig.as<double>());
-            k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.part_sig.as<double>(), static_cast<int>(ns),
-                                           sv.part_b.as<double>(), sv.st(), par, it);
-            prec(pr, pz, sv.st(), done);
-            k_pcg_rz<<<g, kRT, 0, s>>>(n, pr, pz, sv.part_b.as<double>(), static_cast<int>(g), sv.part_a.as<double>(),
-                                       sv.st(), par, it);
-            k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.part_a.as<double>(), static_cast<int>(g), sv.st(), par);
-        }
+    // z = M^-1 r, p = z, rho[it & 1] = r.z; then iterations it, it + 1, ... until the solve stops
+    auto iterate = [&](int it) {
+        prec(pr, pz, sv.st(), done);
+        k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.part_a.as<double>());
+        k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), it & 1);
         SPMVC_CHECK_LAUNCH();
+        const int chunk = std::max(1, o.check_every);
+        while (it < o.max_iter) {
+            if (sv.read().done) break;
+            for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
+                const int par = it & 1;
+                const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.part_sig.as<double>());
+                k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.part_sig.as<double>(), static_cast<int>(ns),
+                                               sv.part_b.as<double>(), sv.st(), par, it);
+                prec(pr, pz, sv.st(), done);
+                k_pcg_rz<<<g, kRT, 0, s>>>(n, pr, pz, sv.part_b.as<double>(), static_cast<int>(g),
+                                           sv.part_a.as<double>(), sv.st(), par, it);
+                k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.part_a.as<double>(), static_cast<int>(g), sv.st(), par);
+            }
+            SPMVC_CHECK_LAUNCH();
+        }
+        CgScal h = sv.read();
+        if (!h.done) {
+            h.done = 1;
+            h.status = SPMVC_ENOCONV;
+        }
+        return h;
+    };
+    CgScal h = iterate(0);
+    double rr = 0.0, bb = 0.0;
+    residual(M, sv, b, x, pq, pr, rr, bb);  // r = b - A x
+    for (int k = 0; k < kMaxRestarts && h.status == SPMVC_OK && ratio(rr, bb) > o.rtol && h.iters < o.max_iter;
+         ++k) {
+        k_pcg_resume<<<1, 64, 0, s>>>(sv.st(), rr);
+        h = iterate(h.iters);
+        residual(M, sv, b, x, pq, pr, rr, bb);
     }
-    CgScal h = sv.read();
-    if (!h.done) {
-        h.done = 1;
-        h.status = SPMVC_ENOCONV;
-    }
+    if (h.status == SPMVC_OK && ratio(rr, bb) > o.rtol) h.status = SPMVC_ENOCONV;
     stat.iters = h.iters;
     stat.outer_iters = 0;
     stat.status = h.status;
     stat.relres_recursive = h.rel;
-    stat.relres_true = true_relres(M, sv, b, x, pq);
+    stat.relres_true = ratio(rr, bb);
     return static_cast<spmvc_status>(h.status);
 }
 
@@ -746,7 +829,10 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
         if (outer == o.max_outer || inner_total >= o.max_iter) break;
         ++outer;
         const double inner_tol = std::max(o.inner_rtol, 0.9 * o.rtol / rel);
-        const CgScal h = run_cg<float, double>(M, sv, r64.as<double>(), d32.as<float>(), r32.as<float>(),
+        // the FP32 solve takes r / ||r|| (unit norm: no FP32 underflow or
+        // overflow whatever the scale of b) and x advances by ||r|| d
+        const double rnorm = std::sqrt(rr);
+        const CgScal h = run_cg<float, double>(M, sv, r64.as<double>(), rnorm, d32.as<float>(), r32.as<float>(),
                                                p32.as<float>(), q32.as<float>(), std::min(inner_tol, 0.5),
                                                std::max(1, o.max_iter - inner_total), o.check_every);
         inner_total += h.iters;
@@ -754,7 +840,7 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
             st = static_cast<spmvc_status>(h.status);
             break;
         }
-        k_add_f32<<<rgrid(n), kRT, 0, s>>>(n, x, d32.as<float>());
+        k_add_f32<<<rgrid(n), kRT, 0, s>>>(n, x, d32.as<float>(), rnorm);
         SPMVC_CHECK_LAUNCH();
     }
     stat.iters = inner_total;

@@ -1638,8 +1638,11 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     p.n_win = static_cast<int>(win.size());
 
     // register-kernel table: [len, byte offset...] with a zero window after the x windows
+    // (per dtype: a value finite in FP64 can be infinite in FP32, and an
+    // infinite table value times the zero window's 0 would give NaN)
     p.v_finite = true;
-    for (int c = 0; c < M->K; ++c) p.v_finite = p.v_finite && std::isfinite(M->V[c]);
+    for (int c = 0; c < M->K; ++c)
+        p.v_finite = p.v_finite && (dt == SPMVC_F32 ? std::isfinite(M->V32[c]) : std::isfinite(M->V[c]));
     p.v_same_lo = true;
     for (int c = 0; c < M->K; ++c) {
         uint64_t b0, bc;

@@ -94,6 +94,7 @@ def test_stencil104_full_size_parity(fmt):
     # closed form: A*1 = 26 - #neighbours, exact in any summation order
     y1 = gpu_spmv(M, np.ones(A.n_cols))
     assert np.array_equal(y1, oracle.spmv(A, np.ones(A.n_cols)))
+    assert roundtrip_ok(M, A)
 
 
 @pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (1024, 1), (2048, 1), (4096, 1), (1024, 0),
@@ -180,6 +181,63 @@ def test_fp32_within_bound(fmt):
         lens = np.diff(A.row_ptr)
         s = row_scale(A, x.astype(np.float64))
         assert np.all(np.abs(y - yref) <= (lens + 2) * 2.0 ** -24 * s + 1e-300)
+
+
+def _fp32_bound_ok(A, x32, y, yref, scale):
+    """|y - yref| <= (len + 2) 2^-24 sum |a||x| per row: V is exact in FP32 and
+    x is FP32, so every product is exact in FP64 and only the FP32 sums round."""
+    lens = np.diff(A.row_ptr)
+    return bool(np.all(np.abs(y - yref) <= (lens + 2) * 2.0 ** -24 * scale + 1e-300))
+
+
+@pytest.mark.parametrize("grid", [(104, 104, 104), (192, 192, 192)])
+def test_fp32_full_size_every_configuration(grid):
+    """FP32 SpMV element by element against the oracle at the workloads' own
+    sizes (104^3: the SpMV benchmark; 192^3: the inner SpMV of mixed-precision
+    CG) in every FP32 kernel configuration the tuner can pick -- register
+    kernel and plane marching at 256, 512 and 1024 rows per block, the direct
+    gather -- and in the tuned one."""
+    say("case: fp32 full size", grid)
+    torch = torch_mod()
+    A = stencil27(*grid)
+    x32 = uniform_vector(A.n_cols, seed=5).astype(np.float32)
+    x64 = x32.astype(np.float64)
+    yref = oracle.spmv(A, x64)
+    absA = CSR(A.n_rows, A.n_cols, A.row_ptr, A.col, np.abs(A.val))
+    scale = oracle.spmv(absA, np.abs(x64))
+    M = compress(A, fmt="DIT")
+    xt = torch.from_numpy(x32).cuda()
+    for rows, lds in [(256, 1), (512, 1), (1024, 1), (256, 2), (512, 2), (1024, 2), (512, 0), (None, None)]:
+        if rows is None:
+            M.tune(torch.float32)
+        else:
+            M.set_config(rows, lds)
+        say("  config", rows, lds, M.info()["kernel_name_f32"])
+        y = M.spmv(xt)
+        torch.cuda.synchronize()
+        assert _fp32_bound_ok(A, x32, y.double().cpu().numpy(), yref, scale), (rows, lds)
+
+
+def test_fp32_table_value_beyond_float_range():
+    """A table value finite in FP64 but above the FP32 range (1e39) becomes
+    +inf in the FP32 copy of V.  FP32 SpMV must then give +-inf on the rows
+    holding it (the sign of that row's x) and never NaN: a padded slot of a
+    short row must not multiply inf by the zero window."""
+    say("case: fp32 value beyond float range")
+    torch = torch_mod()
+    A = stencil27(40, 37, 23)
+    A.val[A.val == 26.0] = 1e39
+    x32 = uniform_vector(A.n_cols, seed=6).astype(np.float32)
+    x32[x32 == 0] = 0.5
+    M = compress(A, fmt="DIT")
+    assert sorted(M.info()["V"][:2]) == [-1.0, 1e39]
+    for rows, lds in [(512, 1), (512, 2), (512, 0)]:
+        M.set_config(rows, lds)
+        y = M.spmv(torch.from_numpy(x32).cuda())
+        torch.cuda.synchronize()
+        y = y.cpu().numpy()
+        assert not np.isnan(y).any(), (rows, lds)
+        assert np.array_equal(y, np.where(x32 > 0, np.inf, -np.inf).astype(np.float32)), (rows, lds)
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
@@ -357,10 +415,16 @@ def _np(t, dtype):
                                       ("DITV", lambda: stencil27(16, 16, 16)),
                                       ("DITV", lambda: stencil27_irregular(20, 17, 13, seed=1)),
                                       ("DITV", lambda: _scattered_two_values((9, 8, 7), 0.02)),
-                                      ("DITV", _split_alternates)])
+                                      ("DITV", _split_alternates),
+                                      ("DIT", "irregular128"), ("DITV", "irregular128")])
 def test_dit_arrays_equal_reference_codec(fmt, make):
-    say("case: DIT arrays", fmt)
-    A = make()
+    """Every array of the GPU encoding equals the reference codec's: V, IDs, T
+    (or the patterns' T for DITV), the pattern table, the escape CSR and the
+    raw values of every row.  The full irregular 128^3 matrix (53 M entries,
+    20,017 patterns, 17,599 escape rows) exercises candidate ranking, the
+    two-row rule and the escape path at the workload's own size."""
+    say("case: DIT arrays", fmt, make if isinstance(make, str) else "")
+    A = stencil27_irregular(128, 128, 128, seed=0) if make == "irregular128" else make()
     enc = codec.encode_dit(A, fold_values=fmt == "DITV")
     M = compress(A, fmt=fmt)
     inf = M.info()
@@ -383,20 +447,21 @@ def test_dit_arrays_equal_reference_codec(fmt, make):
     pl = _np(M.array("PAT_LEN"), np.uint8).astype(np.int64)
     assert np.array_equal(pl, np.diff(enc.pat_ptr))
     po = _np(M.array("PAT_OFF"), np.int32).reshape(enc.P, W)
-    for p in range(enc.P):
-        assert np.array_equal(po[p, :pl[p]], enc.pat_off[enc.pat_ptr[p]:enc.pat_ptr[p + 1]])
+    used = np.arange(W)[None, :] < pl[:, None]  # row-major: the patterns one after another
+    assert np.array_equal(po[used], enc.pat_off)
     assert np.array_equal(_np(M.array("ESC_ROWS"), np.int64), enc.esc_rows)
     if enc.esc_rows.size:
         assert np.array_equal(_np(M.array("ESC_PTR"), np.int64), enc.esc_ptr)
         assert np.array_equal(_np(M.array("ESC_COL"), np.int32)[:enc.esc_col.size], enc.esc_col)
-    # raw values: slices of 64 rows, column-major inside a slice
+        assert same_bits(_np(M.array("ESC_VAL"), np.float64)[:enc.esc_val.size], enc.esc_val)
+    # raw values of every row: slices of 64 rows, column-major inside a slice
     if enc.raw.size:
         raw = _np(M.array("RAW"), np.float64)
         sl = _np(M.array("RAW_SLICE"), np.int64)
-        for i in range(0, n, max(1, n // 501)):
-            k = enc.raw_ptr[i + 1] - enc.raw_ptr[i]
-            got = raw[sl[i // 64] + (i % 64) + 64 * np.arange(k)]
-            assert same_bits(got, enc.raw[enc.raw_ptr[i]:enc.raw_ptr[i + 1]])
+        k = np.diff(enc.raw_ptr)
+        rows = np.repeat(np.arange(n, dtype=np.int64), k)
+        j = np.arange(enc.raw.size, dtype=np.int64) - enc.raw_ptr[rows]
+        assert same_bits(raw[sl[rows // 64] + rows % 64 + 64 * j], enc.raw)
 
 
 def test_dt_arrays_equal_reference_codec():
