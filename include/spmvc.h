@@ -178,6 +178,30 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs,
                       spmvc_cg_stat *stat, void *stream);
 
 /*
+ * cg_solve's FP64 CG (mode 0, x0 = 0, the same kernels and results) for ONE
+ * system with one right-hand side, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree, hipHostMalloc or other allocating routine.  Its vectors,
+ * reduction partials and scalars live in one static device region of the
+ * library, 48.5 MiB per GPU (held from the first call on that GPU until the
+ * process ends), so the system may have at most 2,097,152 rows (2^21) and the
+ * handle's FP64 SpMV at most 65,536 blocks; larger systems give SPMVC_EINVAL
+ * with a message.  The region keeps the previous call's contents and every
+ * call clears what it needs.  Calls on one GPU share the region: calls that
+ * overlap in time on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.
+ *   A:      square matrix handle (any format).
+ *   b, x:   device FP64 vectors [n_rows]; x is overwritten (the last iterate
+ *           on failure); they must not overlap.
+ *   opts:   rtol, max_iter, check_every as for cg_solve; mode must be 0; the
+ *           other fields are ignored.  NULL = defaults.
+ *   stat:   one host result, as for cg_solve.
+ * Returns SPMVC_OK, SPMVC_ENOCONV, SPMVC_ENOTSPD or SPMVC_EINVAL.  Blocking.
+ */
+spmvc_status cg_solve_noalloc(spmvc_matrix A, const double *b, double *x, const spmvc_cg_opts *opts,
+                              spmvc_cg_stat *stat, void *stream);
+
+/*
  * Solve levels[0] x = b by FP64 CG preconditioned by one multigrid V-cycle
  * per iteration: the HPCG iteration of Table I (Section III), with the
  * V-cycle in that table's order.  On each level l above the coarsest: z = 0,

@@ -31,7 +31,7 @@ ARR = {
 }
 
 EXPORTED = [
-    "spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_mg", "spmv_decompress", "spmv_info",
+    "spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_noalloc", "cg_solve_mg", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
     "spmvc_batched_config", "spmvc_set_allocator", "spmv_rcm", "spmv_permute", "spmv_free", "spmvc_status_string",
     "spmvc_last_error",
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.spmv_block.argtypes = [P, i32, i32, P, i64, P, i64, P]
     lib.cg_solve.argtypes = [ctypes.POINTER(P), i32, i32, ctypes.POINTER(P), ctypes.POINTER(P),
                              ctypes.POINTER(CgOpts), ctypes.POINTER(CgStat), P]
+    lib.cg_solve_noalloc.argtypes = [P, P, P, ctypes.POINTER(CgOpts), ctypes.POINTER(CgStat), P]
     lib.cg_solve_mg.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32, P, P, ctypes.POINTER(CgOpts),
                                 ctypes.POINTER(CgStat), P]
     lib.spmv_decompress.argtypes = [P, P, P, P, P]
@@ -330,6 +331,23 @@ def cg_solve(mats, bs, xs=None, rtol=1e-10, max_iter=10000, mode=0, inner_rtol=1
     out = [{"iters": s.iters, "outer_iters": s.outer_iters, "status": s.status,
             "relres_true": s.relres_true, "relres_recursive": s.relres_recursive} for s in stats]
     return st, xs, out
+
+
+def cg_solve_noalloc(mat, b, x=None, rtol=1e-10, max_iter=10000, check_every=16, stream=None):
+    """FP64 CG of one system through the library's allocation-free entry point
+    (every buffer of the solve in its static device region).  b, x: CUDA
+    float64 vectors; x is allocated here when not given."""
+    import torch
+
+    if x is None:
+        x = torch.empty_like(b)
+    o = CgOpts(rtol, max_iter, 0, 1e-5, 20, check_every, 0)
+    stat = (CgStat * 1)()
+    st = load().cg_solve_noalloc(mat.handle, _dev(b, torch.float64, "b"), _dev(x, torch.float64, "x"),
+                                 ctypes.byref(o), stat, _stream(stream))
+    s = stat[0]
+    return st, x, {"iters": s.iters, "status": s.status, "relres_true": s.relres_true,
+                   "relres_recursive": s.relres_recursive}
 
 
 def cg_solve_mg(levels, f2c, b, x=None, rtol=1e-10, max_iter=10000, check_every=16, stream=None):

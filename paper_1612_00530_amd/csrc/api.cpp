@@ -244,6 +244,28 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs, const 
     });
 }
 
+spmvc_status cg_solve_noalloc(spmvc_matrix A, const double *b, double *x, const spmvc_cg_opts *opts,
+                              spmvc_cg_stat *stat, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !stat) return fail(SPMVC_EINVAL, "null argument");
+        spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16, 0};
+        if (opts) o = *opts;
+        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1) return fail(SPMVC_EINVAL, "invalid cg options");
+        if (o.mode != 0) return fail(SPMVC_EINVAL, "cg_solve_noalloc runs FP64 CG (mode 0) only");
+        if (A->n_rows != A->n_cols) return fail(SPMVC_EINVAL, "CG needs square matrices");
+        if (A->n_rows > cg_noalloc_max_rows())
+            return fail(SPMVC_EINVAL, "cg_solve_noalloc: " + std::to_string(A->n_rows) +
+                                          " rows exceed the scratch limit of " + std::to_string(cg_noalloc_max_rows()));
+        if (A->n_rows > 0 && (!b || !x)) return fail(SPMVC_EINVAL, "b / x is null");
+        if (overlap(b, 8 * A->n_rows, x, 8 * A->n_rows)) return fail(SPMVC_EINVAL, "b and x overlap");
+        *stat = spmvc_cg_stat{};
+        if (A->n_rows == 0) return SPMVC_OK;
+        const spmvc_status st = cg_solve_noalloc_impl(A, b, x, o, *stat, static_cast<hipStream_t>(stream));
+        if (st != SPMVC_OK) set_error(spmvc_status_string(st));
+        return st;
+    });
+}
+
 spmvc_status cg_solve_mg(const spmvc_matrix *levels, const int32_t *const *f2c, int32_t n_levels, const double *b,
                          double *x, const spmvc_cg_opts *opts, spmvc_cg_stat *stat, void *stream) {
     return guarded([&]() -> spmvc_status {

@@ -28,6 +28,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 
 #include "internal.h"
 
@@ -522,32 +524,64 @@ unsigned rgrid(int64_t n) {
     return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(g, kRMaxBlocks)));
 }
 
+// scalars = 0 (a fill kernel rather than a memset node, so that the solver's
+// work can also be recorded into a graph)
+__global__ void k_zero_scal(CgScal *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *st = CgScal{};
+}
+
 struct Pinned {
     CgScal *h = nullptr;
     Pinned() { SPMVC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(CgScal), hipHostMallocDefault)); }
     ~Pinned() {
         if (h) (void)hipHostFree(h);
     }
+    Pinned(const Pinned &) = delete;
+    Pinned &operator=(const Pinned &) = delete;
 };
 
+// Scalars and reduction partials of one solve, on the device, plus the host
+// copy the driver reads.  Either owned (allocated here) or carved from a
+// caller's region (nothing allocated; the host copy is then pageable).
 struct Solver {
     hipStream_t s;
+    CgScal *dscal = nullptr;
+    double *pa = nullptr, *pb = nullptr, *psig = nullptr;  // partials: kRMaxBlocks, kRMaxBlocks, SpMV blocks
+    CgScal *h = nullptr;
     DevBuf scal, part_a, part_b, part_sig;
-    Pinned pin;
+    std::unique_ptr<Pinned> pin;
+    CgScal h_pageable{};
     Solver(hipStream_t st, int64_t sig_blocks) : s(st) {
         scal.alloc(sizeof(CgScal));
-        SPMVC_HIP(hipMemsetAsync(scal.p, 0, sizeof(CgScal), s));
         part_a.alloc(sizeof(double) * kRMaxBlocks);
         part_b.alloc(sizeof(double) * kRMaxBlocks);
         part_sig.alloc(sizeof(double) * std::max<int64_t>(sig_blocks, 1));
+        pin.reset(new Pinned());
+        bind(scal.as<CgScal>(), part_a.as<double>(), part_b.as<double>(), part_sig.as<double>(), pin->h);
     }
-    CgScal *st() { return scal.as<CgScal>(); }
+    // region: kSolverScalBytes of scalars, then 2 * kRMaxBlocks partials, then the SpMV partials
+    Solver(hipStream_t st, char *region) : s(st) {
+        double *parts = reinterpret_cast<double *>(region + kSolverScalBytes);
+        bind(reinterpret_cast<CgScal *>(region), parts, parts + kRMaxBlocks, parts + 2 * kRMaxBlocks, &h_pageable);
+    }
+    static constexpr size_t kSolverScalBytes = 256;
+    void bind(CgScal *d, double *a, double *b, double *sig, CgScal *host) {
+        dscal = d;
+        pa = a;
+        pb = b;
+        psig = sig;
+        h = host;
+        k_zero_scal<<<1, 64, 0, s>>>(dscal);
+        SPMVC_CHECK_LAUNCH();
+    }
+    CgScal *st() { return dscal; }
     const CgScal &read() {
-        SPMVC_HIP(hipMemcpyAsync(pin.h, scal.p, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+        SPMVC_HIP(hipMemcpyAsync(h, dscal, sizeof(CgScal), hipMemcpyDeviceToHost, s));
         SPMVC_HIP(hipStreamSynchronize(s));
-        return *pin.h;
+        return *h;
     }
 };
+static_assert(sizeof(CgScal) <= Solver::kSolverScalBytes, "scalar block of the solver region");
 
 // CG iterations it0, it0 + 1, ... on the state in (z, r, p) until the solve
 // stops or max_iter; returns the final scalars.
@@ -565,18 +599,18 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
         if (sv.read().done) break;
         for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
             const int par = it & 1;
-            const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.part_sig.as<double>());
+            const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.psig);
             if (vec_u)
-                k_cg_update<Real, VW><<<g, kRT, 0, sv.s>>>(n, r, q, sv.part_sig.as<double>(), static_cast<int>(ns),
-                                                           sv.part_b.as<double>(), sv.st(), par, it);
+                k_cg_update<Real, VW><<<g, kRT, 0, sv.s>>>(n, r, q, sv.psig, static_cast<int>(ns),
+                                                           sv.pb, sv.st(), par, it);
             else
-                k_cg_update<Real, 1><<<g, kRT, 0, sv.s>>>(n, r, q, sv.part_sig.as<double>(), static_cast<int>(ns),
-                                                          sv.part_b.as<double>(), sv.st(), par, it);
+                k_cg_update<Real, 1><<<g, kRT, 0, sv.s>>>(n, r, q, sv.psig, static_cast<int>(ns),
+                                                          sv.pb, sv.st(), par, it);
             if (vec_p)
-                k_cg_pupdate<Real, VW><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.part_b.as<double>(), static_cast<int>(g),
+                k_cg_pupdate<Real, VW><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.pb, static_cast<int>(g),
                                                             sv.st(), par, it);
             else
-                k_cg_pupdate<Real, 1><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.part_b.as<double>(), static_cast<int>(g),
+                k_cg_pupdate<Real, 1><<<g, kRT, 0, sv.s>>>(n, z, r, p, sv.pb, static_cast<int>(g),
                                                            sv.st(), par, it);
         }
         SPMVC_CHECK_LAUNCH();
@@ -596,8 +630,8 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, RhsT rhs_nor
               Real *q, double rtol, int max_iter, int check_every) {
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
-    k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, rhs_norm, z, r, p, sv.part_a.as<double>());
-    k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), rtol, max_iter);
+    k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, rhs_norm, z, r, p, sv.pa);
+    k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.pa, static_cast<int>(g), sv.st(), rtol, max_iter);
     SPMVC_CHECK_LAUNCH();
     return cg_iterate<Real>(M, sv, z, r, p, q, 0, max_iter, check_every);
 }
@@ -608,8 +642,8 @@ void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     launch_spmv(M, SPMVC_F64, x, tmp, sv.s);
-    k_residual<<<g, kRT, 0, sv.s>>>(n, b, tmp, r, sv.part_a.as<double>(), sv.part_b.as<double>());
-    k_residual_fin<<<1, kRT, 0, sv.s>>>(sv.part_a.as<double>(), sv.part_b.as<double>(), static_cast<int>(g), sv.st());
+    k_residual<<<g, kRT, 0, sv.s>>>(n, b, tmp, r, sv.pa, sv.pb);
+    k_residual_fin<<<1, kRT, 0, sv.s>>>(sv.pa, sv.pb, static_cast<int>(g), sv.st());
     SPMVC_CHECK_LAUNCH();
     const CgScal &h = sv.read();
     rr = h.aux[0];
@@ -630,15 +664,11 @@ double true_relres(const spmvc_matrix_s *M, Solver &sv, const double *b, const d
 // short when it stops again, reports SPMVC_ENOCONV.
 constexpr int kMaxRestarts = 4;
 
-spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
-                        spmvc_cg_stat &stat, hipStream_t s) {
+// FP64 CG on A x = b with the solver state sv and work vectors r, p, q (n each).
+spmvc_status solve_fp64_in(const spmvc_matrix_s *M, Solver &sv, const double *b, double *x, double *pr, double *pp,
+                           double *pq, const spmvc_cg_opts &o, spmvc_cg_stat &stat) {
     const int64_t n = M->n_rows;
-    Solver sv(s, spmv_dot_blocks(M));
-    DevBuf r, p, q;
-    r.alloc(sizeof(double) * std::max<int64_t>(n, 1));
-    p.alloc(sizeof(double) * std::max<int64_t>(n, 1));
-    q.alloc(sizeof(double) * std::max<int64_t>(n, 1));
-    double *pr = r.as<double>(), *pp = p.as<double>(), *pq = q.as<double>();
+    const hipStream_t s = sv.s;
     CgScal h = run_cg<double, double>(M, sv, b, 1.0, x, pr, pp, pq, o.rtol, o.max_iter, o.check_every);
     double rr = 0.0, bb = 0.0;
     residual(M, sv, b, x, pq, pr, rr, bb);  // r = b - A x
@@ -658,6 +688,74 @@ spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, con
     return static_cast<spmvc_status>(h.status);
 }
 
+spmvc_status solve_fp64(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
+                        spmvc_cg_stat &stat, hipStream_t s) {
+    const int64_t n = M->n_rows;
+    Solver sv(s, spmv_dot_blocks(M));
+    DevBuf r, p, q;
+    r.alloc(sizeof(double) * std::max<int64_t>(n, 1));
+    p.alloc(sizeof(double) * std::max<int64_t>(n, 1));
+    q.alloc(sizeof(double) * std::max<int64_t>(n, 1));
+    return solve_fp64_in(M, sv, b, x, r.as<double>(), p.as<double>(), q.as<double>(), o, stat);
+}
+
+// ---- the same FP64 CG without any allocation ----------------------------------------------
+// For callers that cannot allocate device memory: every buffer of the solve
+// lives in `scratch`, one fixed region per GPU that holds the solver scalars,
+// the reduction partials and the vectors r, p, q.  Host code reaches it only
+// through the address hipGetSymbolAddress gives on each device.
+constexpr int64_t kNaMaxRows = int64_t(1) << 21;       // rows of the largest system (2,097,152)
+constexpr int64_t kNaMaxSpmvBlocks = int64_t(1) << 16;  // p.q partials of one SpMV launch
+constexpr size_t kNaSolverBytes = Solver::kSolverScalBytes + sizeof(double) * (2 * kRMaxBlocks + kNaMaxSpmvBlocks);
+constexpr size_t kNaVecBytes = sizeof(double) * kNaMaxRows;
+constexpr size_t kNaScratchBytes = kNaSolverBytes + 3 * kNaVecBytes;  // 48.5 MiB
+static_assert(kNaSolverBytes % 256 == 0, "vectors start 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+char *g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+char *scratch_on_current_device() {
+    int dev = 0;
+    SPMVC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) throw Error{SPMVC_EUNSUPPORTED, "device index beyond 63"};
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *ptr = nullptr;
+        SPMVC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_na_ptr[dev] = static_cast<char *>(ptr);
+    }
+    return g_na_ptr[dev];
+}
+
+}  // namespace
+
+int64_t cg_noalloc_max_rows() { return kNaMaxRows; }
+
+spmvc_status cg_solve_noalloc_impl(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
+                                   spmvc_cg_stat &stat, hipStream_t s) {
+    const int64_t n = M->n_rows;
+    if (n > kNaMaxRows)
+        throw Error{SPMVC_EINVAL, "cg_solve_noalloc: " + std::to_string(n) + " rows exceed the scratch limit of " +
+                                      std::to_string(kNaMaxRows)};
+    if (spmv_dot_blocks(M) > kNaMaxSpmvBlocks)
+        throw Error{SPMVC_EINVAL, "cg_solve_noalloc: the SpMV configuration launches more than " +
+                                      std::to_string(kNaMaxSpmvBlocks) + " blocks"};
+    char *base = scratch_on_current_device();
+    Solver sv(s, base);
+    double *r = reinterpret_cast<double *>(base + kNaSolverBytes);
+    double *p = reinterpret_cast<double *>(base + kNaSolverBytes + kNaVecBytes);
+    double *q = reinterpret_cast<double *>(base + kNaSolverBytes + 2 * kNaVecBytes);
+    const spmvc_status st = solve_fp64_in(M, sv, b, x, r, p, q, o, stat);
+    SPMVC_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+namespace {
+
 // Preconditioned CG (mode 2): M^-1 r = one multicolor SymGS sweep from zero.
 // prec(r, z, st, done) enqueues z = M^-1 r on s; every launch it makes
 // returns at once once st->done is set.
@@ -676,27 +774,27 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
     double *pr = r.as<double>(), *pz = z.as<double>(), *pp = p.as<double>(), *pq = q.as<double>();
     const int *done = &sv.st()->done;
     // x = 0, r = b, rho0 = b.b; z = M^-1 r; p = z; rho = r.z
-    k_cg_start<double, double><<<g, kRT, 0, s>>>(n, b, 1.0, x, pr, pp, sv.part_a.as<double>());
-    k_cg_start_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), o.rtol, o.max_iter);
+    k_cg_start<double, double><<<g, kRT, 0, s>>>(n, b, 1.0, x, pr, pp, sv.pa);
+    k_cg_start_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), o.rtol, o.max_iter);
     SPMVC_CHECK_LAUNCH();
     // z = M^-1 r, p = z, rho[it & 1] = r.z; then iterations it, it + 1, ... until the solve stops
     auto iterate = [&](int it) {
         prec(pr, pz, sv.st(), done);
-        k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.part_a.as<double>());
-        k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.part_a.as<double>(), static_cast<int>(g), sv.st(), it & 1);
+        k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.pa);
+        k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), it & 1);
         SPMVC_CHECK_LAUNCH();
         const int chunk = std::max(1, o.check_every);
         while (it < o.max_iter) {
             if (sv.read().done) break;
             for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
                 const int par = it & 1;
-                const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.part_sig.as<double>());
-                k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.part_sig.as<double>(), static_cast<int>(ns),
-                                               sv.part_b.as<double>(), sv.st(), par, it);
+                const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.psig);
+                k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.psig, static_cast<int>(ns),
+                                               sv.pb, sv.st(), par, it);
                 prec(pr, pz, sv.st(), done);
-                k_pcg_rz<<<g, kRT, 0, s>>>(n, pr, pz, sv.part_b.as<double>(), static_cast<int>(g),
-                                           sv.part_a.as<double>(), sv.st(), par, it);
-                k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.part_a.as<double>(), static_cast<int>(g), sv.st(), par);
+                k_pcg_rz<<<g, kRT, 0, s>>>(n, pr, pz, sv.pb, static_cast<int>(g),
+                                           sv.pa, sv.st(), par, it);
+                k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.pa, static_cast<int>(g), sv.st(), par);
             }
             SPMVC_CHECK_LAUNCH();
         }

@@ -204,6 +204,11 @@ spmvc_status cg_solve_mg_impl(spmvc_matrix const *levels, const int32_t *const *
 spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                            double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,
                            hipStream_t s);
+// FP64 CG of one system with every buffer in the library's static scratch
+// region (no allocation); blocking; throws Error beyond the region's limits.
+spmvc_status cg_solve_noalloc_impl(const spmvc_matrix_s *M, const double *b, double *x,
+                                   const spmvc_cg_opts &o, spmvc_cg_stat &stat, hipStream_t s);
+int64_t cg_noalloc_max_rows();
 
 // batched.hip
 // Kernel one spmv of dtype dt launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register,
