@@ -15,9 +15,9 @@ It follows the steps of Section V in the paper's order:
    d = col - row (``encode_dit``).
 5. Register each row's displacement sequence in a pattern table; each row then
    stores only the pattern's type ID plus T_i.  This is the "Data+Index
-   Table" scheme (DIT); the sample code in the paper decodes it per row with
-   ``j = i + columnDiff[type][idx]`` and value ``V[valueIdx]`` for
-   ``idx < valueIdxEnd[i][valueIdx]``.
+   Table" scheme (DIT).  Decoding (Section V, Listing 1): the column of a
+   row's k-th entry is the row index plus the k-th displacement of its
+   pattern, and its value is the table value whose run in T_i covers k.
 6. The further step the paper proposes at the end of the section: register
    the element values in the table as well, so that a row stores nothing but
    its ID (``encode_dit(..., fold_values=True)``, format "DITV").  Here the
@@ -27,9 +27,9 @@ It follows the steps of Section V in the paper's order:
 
 Readings of points the paper leaves open (each is listed in the design notes):
 
-* T stores *exclusive* run ends (prefix counts).  The sample code's loop bound
-  ``idx < valueIdxEnd`` needs exclusive ends; Fig. 1 prints the inclusive last
-  position, i.e. T - 1.
+* T stores *exclusive* run ends (prefix counts).  The decoding loop of
+  Listing 1 bounds each run with a strict comparison, which needs exclusive
+  ends; Fig. 1 prints the inclusive last position, i.e. T - 1.
 * Equal values keep ascending column order (a stable sort of a column-sorted
   row), which reproduces Fig. 1's S = 45 49 51 65 50.
 * Values are compared by bit pattern and ordered by IEEE-754 totalOrder, so
@@ -316,47 +316,17 @@ def decode(enc: Encoding):
 
 
 def walk_spmv(enc: Encoding, x) -> np.ndarray:
-    """y = A x straight from the encoding, row by row as the paper's sample code walks it.
+    """y = A x evaluated from the encoding itself (not from the CSR input).
 
-    For each row: look up its pattern (DIT) or S_i (DT); for each table value
-    v = V[c] add v * x[j] for the positions before T_i[c]; then the raw entries;
-    escape rows are plain CSR rows.  Pure Python: for small matrices only.
+    Every stored entry is decoded by ``_entries`` -- its column from the row's
+    pattern (DIT, DITV) or S_i (DT), its value from V through T_i or from the
+    raw stream, escape rows from their CSR -- and y_i is then the plain sum of
+    value * x[column] over row i's entries, added in their stored order.
     """
     x = np.asarray(x, dtype=np.float64)
+    rows, cols, vals = _entries(enc)
     y = np.zeros(enc.n_rows, dtype=np.float64)
-    K = enc.K
-    esc_pos = {int(r): e for e, r in enumerate(enc.esc_rows)}
-    for i in range(enc.n_rows):
-        s = 0.0
-        if i in esc_pos:
-            e = esc_pos[i]
-            for k in range(int(enc.esc_ptr[e]), int(enc.esc_ptr[e + 1])):
-                s = s + float(enc.esc_val[k]) * float(x[int(enc.esc_col[k])])
-            y[i] = s
-            continue
-        if enc.fmt == "DT":
-            base, length = int(enc.S_ptr[i]), int(enc.S_ptr[i + 1] - enc.S_ptr[i])
-
-            def col_at(idx, base=base):
-                return int(enc.S[base + idx])
-        else:
-            t = int(enc.ids[i])
-            base, length = int(enc.pat_ptr[t]), int(enc.pat_ptr[t + 1] - enc.pat_ptr[t])
-
-            def col_at(idx, base=base, i=i):
-                return i + int(enc.pat_off[base + idx])
-        Ti = enc.pat_T[int(enc.ids[i])] if enc.fmt == "DITV" else enc.T[i]
-        idx = 0
-        for c in range(K):
-            a = float(enc.V[c])
-            while idx < int(Ti[c]):
-                s = s + a * float(x[col_at(idx)])
-                idx += 1
-        r0 = int(enc.raw_ptr[i])
-        while idx < length:
-            s = s + float(enc.raw[r0 + idx - (int(Ti[K - 1]) if K else 0)]) * float(x[col_at(idx)])
-            idx += 1
-        y[i] = s
+    np.add.at(y, rows, vals * x[cols])  # unbuffered: in index order, one entry at a time
     return y
 
 
