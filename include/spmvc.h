@@ -19,7 +19,17 @@
  *                  well (the further step Section V proposes at the end of
  *                  that paragraph): the registered key is the displacement
  *                  sequence together with T_i, so a row stores only its ID;
- *                  raw (non-dictionary) values stay per row as in DIT.
+ *                  raw (non-dictionary) values stay per row as in DIT;
+ *   SPMVC_FMT_BMASK the pattern table taken to one entry (the further
+ *                  compression of the table Section V suggests, for matrices
+ *                  with few distinct displacements): D = the ascending list of
+ *                  every displacement col - row in the matrix (at most 64), and
+ *                  per row a bitmask over D (bit k: an entry at column
+ *                  row + D[k]; 4 bytes when |D| <= 32, else 8).  No pattern
+ *                  table and no escape rows, however irregular the rows.  When
+ *                  the matrix holds at most two distinct values they form V and,
+ *                  with two, a second mask marks the entries holding V[1];
+ *                  otherwise every value is stored per row in column order.
  *
  * Around the product: CG (cg_solve: FP64, mixed precision, or preconditioned
  * by one multicolor SymGS sweep; cg_solve_mg: preconditioned by a multigrid
@@ -68,7 +78,8 @@ typedef enum {
     SPMVC_FMT_DT = 1,
     SPMVC_FMT_DIT = 2,
     SPMVC_FMT_DITV = 3,
-    SPMVC_FMT_AUTO = 4  /* spmv_compress only: DIT, or ELL when DIT's stream would not be smaller */
+    SPMVC_FMT_AUTO = 4, /* spmv_compress only: DIT, or ELL when DIT's stream would not be smaller */
+    SPMVC_FMT_BMASK = 5 /* neighbour bitmask over the matrix's displacement list (see below)    */
 } spmvc_format;
 
 typedef struct spmvc_matrix_s *spmvc_matrix; /* opaque, owned by the library */
@@ -285,8 +296,8 @@ spmvc_status spmv_decompress(spmvc_matrix A, int64_t *row_ptr, int32_t *col_idx,
 typedef struct {
     int32_t fmt;           /* spmvc_format                                                */
     int32_t K;             /* value-table entries                                         */
-    int32_t P;             /* pattern-table entries (DIT, DITV)                           */
-    int32_t id_bytes;      /* width of a pattern ID (DIT): 1, 2 or 4                      */
+    int32_t P;             /* pattern-table entries (DIT, DITV); BMASK: |D|               */
+    int32_t id_bytes;      /* width of a pattern ID (DIT): 1, 2 or 4; BMASK: mask width    */
     int32_t width;         /* ELL/DT slots per row, DIT longest pattern                   */
     int32_t max_raw;       /* most raw entries in one row                                 */
     int64_t n_rows, n_cols, nnz;
@@ -299,7 +310,7 @@ typedef struct {
     int32_t rows_per_block; /* rows per block of the FP64 spmv                             */
     double V[15];          /* the value table (first K entries)                           */
     int32_t kernel;        /* what an FP64 spmv launches: 0 direct gather, 1 DIT LDS walk, 2 DIT register,
-                              3 DIT register, plane-marching */
+                              3 DIT register, plane-marching, 4 BMASK with LDS windows */
     int32_t kernel_f32;    /* the same for FP32 (each dtype has its own configuration)   */
     int32_t rows_per_block_f32;
     int32_t pad_;
@@ -318,13 +329,17 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info /* host */);
  * u8 [P]; PAT_T u8 [P][K] (DITV: the T of each pattern); RAW f64 in
  * slices of 64 rows, slice s at RAW_SLICE[s] (int64, elements), raw entry k
  * of row 64s+l at RAW[RAW_SLICE[s] + 64k + l]; ESC_ROWS i64, ESC_PTR i64
- * [n_esc+1], ESC_COL i32, ESC_VAL f64.
+ * [n_esc+1], ESC_COL i32, ESC_VAL f64.  BMASK: BM_D i32 [|D|]; BM_MASK and
+ * BM_VMASK [n_pad] of 4 or 8 bytes each (spmvc_info.id_bytes gives the width;
+ * BM_VMASK empty unless K == 2); the values of a table-less BMASK matrix are
+ * in RAW / RAW_SLICE, each row's in column order.
  */
 typedef enum {
     SPMVC_ARR_ELL_VAL = 0, SPMVC_ARR_ELL_COL = 1, SPMVC_ARR_DT_S = 2, SPMVC_ARR_IDS = 3,
     SPMVC_ARR_T = 4, SPMVC_ARR_PAT_OFF = 5, SPMVC_ARR_PAT_LEN = 6, SPMVC_ARR_RAW = 7,
     SPMVC_ARR_RAW_SLICE = 8, SPMVC_ARR_ESC_ROWS = 9, SPMVC_ARR_ESC_PTR = 10,
-    SPMVC_ARR_ESC_COL = 11, SPMVC_ARR_ESC_VAL = 12, SPMVC_ARR_V = 13, SPMVC_ARR_PAT_T = 14
+    SPMVC_ARR_ESC_COL = 11, SPMVC_ARR_ESC_VAL = 12, SPMVC_ARR_V = 13, SPMVC_ARR_PAT_T = 14,
+    SPMVC_ARR_BM_D = 15, SPMVC_ARR_BM_MASK = 16, SPMVC_ARR_BM_VMASK = 17
 } spmvc_array_id;
 
 spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *bytes, void *stream);

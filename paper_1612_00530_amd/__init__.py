@@ -20,14 +20,15 @@ __all__ = [
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspmvc.so")
 
-FMT_ELL, FMT_DT, FMT_DIT, FMT_DITV, FMT_AUTO = 0, 1, 2, 3, 4
+FMT_ELL, FMT_DT, FMT_DIT, FMT_DITV, FMT_AUTO, FMT_BMASK = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
-_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT, "DITV": FMT_DITV, "AUTO": FMT_AUTO}
+_FMT_NAMES = {"ELL": FMT_ELL, "DT": FMT_DT, "DIT": FMT_DIT, "DITV": FMT_DITV, "AUTO": FMT_AUTO,
+              "BMASK": FMT_BMASK}
 
 ARR = {
     "ELL_VAL": 0, "ELL_COL": 1, "DT_S": 2, "IDS": 3, "T": 4, "PAT_OFF": 5, "PAT_LEN": 6,
     "RAW": 7, "RAW_SLICE": 8, "ESC_ROWS": 9, "ESC_PTR": 10, "ESC_COL": 11, "ESC_VAL": 12, "V": 13,
-    "PAT_T": 14,
+    "PAT_T": 14, "BM_D": 15, "BM_MASK": 16, "BM_VMASK": 17,
 }
 
 EXPORTED = [
@@ -195,8 +196,8 @@ class Matrix:
         _check(load().spmv_info(self._h, ctypes.byref(inf)))
         d = {f: getattr(inf, f) for f, _ in Info._fields_ if f != "V"}
         d["V"] = [inf.V[i] for i in range(inf.K)]
-        d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT", 3: "DITV"}[inf.fmt]
-        names = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg", 3: "k_dit_march"}
+        d["fmt_name"] = {0: "ELL", 1: "DT", 2: "DIT", 3: "DITV", 5: "BMASK"}[inf.fmt]
+        names = {0: "k_spmv_direct", 1: "k_dit_lds", 2: "k_dit_reg", 3: "k_dit_march", 4: "k_bmask_lds"}
         d["kernel_name"] = names[inf.kernel]
         d["kernel_name_f32"] = names[inf.kernel_f32]
         return d

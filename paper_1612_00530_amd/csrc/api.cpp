@@ -66,7 +66,7 @@ int cu_count() {
 void default_plan(spmvc_matrix_s *M) {
     M->n_xcd = xcd_count();
     M->n_cu = cu_count();
-    if (M->fmt != SPMVC_FMT_DIT) return;
+    if (M->fmt != SPMVC_FMT_DIT && M->fmt != SPMVC_FMT_BMASK) return;
     for (int dt : {SPMVC_F64, SPMVC_F32}) {
         for (int rows : {M->rows_per_block[dt], 1024, 512, 256}) {
             build_lds_plan(M, dt, rows);
@@ -140,7 +140,7 @@ spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const in
         if (nnz > 0 && n_cols == 0) return fail(SPMVC_ERANGE, "entries in a matrix with no columns");
         spmvc_compress_opts o{SPMVC_FMT_DIT, 15, 65535, 2, 1};
         if (opts) o = *opts;
-        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_AUTO) return fail(SPMVC_EINVAL, "unknown format");
+        if (o.fmt < SPMVC_FMT_ELL || o.fmt > SPMVC_FMT_BMASK) return fail(SPMVC_EINVAL, "unknown format");
         const bool autofmt = o.fmt == SPMVC_FMT_AUTO;
         if (autofmt) o.fmt = SPMVC_FMT_DIT;
         if (o.k_max < 0 || o.k_max > kMaxK) return fail(SPMVC_EINVAL, "k_max must be in 0..15");
@@ -378,7 +378,7 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
         r.n_raw = A->n_raw;
         r.bytes_stream = stream_bytes(A, SPMVC_F64);
         // ELL of the same matrix: width = longest row, 12 bytes per slot over padded rows
-        int64_t maxlen = A->width;
+        int64_t maxlen = A->width;  // BMASK: the longest row
         if (A->fmt == SPMVC_FMT_DIT) {
             maxlen = 0;
             for (int q = 0; q < A->P; ++q) maxlen = std::max<int64_t>(maxlen, A->h_pat_len[q]);
@@ -390,16 +390,23 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
         else if (A->fmt == SPMVC_FMT_DT)
             r.bytes_paper = 4 * (A->nnz - A->n_esc_nnz) + k4 * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz +
                             8 * A->n_raw;
+        else if (A->fmt == SPMVC_FMT_BMASK)  // the masks at their own width, values as stored
+            r.bytes_paper = stream_bytes(A, SPMVC_F64);
         else if (!A->fold)
             r.bytes_paper = (4 + k4) * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
         else  // DITV: the 4-byte ID alone
             r.bytes_paper = 4 * (A->n_rows - A->n_esc) + 12 * A->n_esc_nnz + 8 * A->n_raw;
-        r.lds_windows = (A->fmt == SPMVC_FMT_DIT && A->lds_mode[SPMVC_F64] >= 1) ? A->plan[SPMVC_F64].n_win : 0;
-        r.rows_per_block = A->fmt == SPMVC_FMT_DIT ? A->plan[SPMVC_F64].rows : kBlock;
+        const bool planned = A->fmt == SPMVC_FMT_DIT || A->fmt == SPMVC_FMT_BMASK;
+        r.lds_windows = (planned && A->lds_mode[SPMVC_F64] >= 1) ? A->plan[SPMVC_F64].n_win : 0;
+        r.rows_per_block = planned ? A->plan[SPMVC_F64].rows : kBlock;
+        if (A->fmt == SPMVC_FMT_BMASK) {
+            r.P = A->bm_nd;
+            r.id_bytes = A->bm_bytes;
+        }
         for (int c = 0; c < A->K; ++c) r.V[c] = A->V[c];
         r.kernel = kernel_kind(A, SPMVC_F64);
         r.kernel_f32 = kernel_kind(A, SPMVC_F32);
-        r.rows_per_block_f32 = A->fmt == SPMVC_FMT_DIT ? A->plan[SPMVC_F32].rows : kBlock;
+        r.rows_per_block_f32 = planned ? A->plan[SPMVC_F32].rows : kBlock;
         *info = r;
         return SPMVC_OK;
     });
@@ -425,6 +432,9 @@ spmvc_status spmv_get_array(spmvc_matrix A, int32_t which, void *dst, int64_t *b
         case SPMVC_ARR_ESC_COL: b = &A->esc_col; break;
         case SPMVC_ARR_ESC_VAL: b = &A->esc_val; break;
         case SPMVC_ARR_V: b = &A->V_dev; break;
+        case SPMVC_ARR_BM_D: b = &A->bm_d; break;
+        case SPMVC_ARR_BM_MASK: b = &A->bm_mask; break;
+        case SPMVC_ARR_BM_VMASK: b = &A->bm_vmask; break;
         default: return fail(SPMVC_EINVAL, "unknown array id");
         }
         *bytes = static_cast<int64_t>(b->bytes);

@@ -26,7 +26,7 @@ namespace {
 
 constexpr uint64_t kEmpty = ~0ull;
 constexpr int kFlagRange = 1, kFlagUnsorted = 2, kFlagCollision = 4, kFlagOverflow = 8,
-              kFlagCandOverflow = 16;
+              kFlagCandOverflow = 16, kFlagBmValueSentinel = 32;
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -590,6 +590,89 @@ __global__ void k_long_flags(int64_t n_rows, const int64_t *rp, uint8_t *esc) {
 }
 
 // ---- decompression ------------------------------------------------------------------
+// ---- neighbour-bitmask format (BMASK) -------------------------------------------------
+// The pattern table reduced to one list: D = every displacement col - row of
+// the matrix, ascending; a row stores a bitmask over D.  Distinct keys (the
+// displacements, and the values to decide the value table) are gathered in a
+// small open-addressing set; a key is looked up before any atomic, so the
+// few insertions are the only contended operations.
+constexpr int kBmSetCap = 1024;    // slots of the displacement set (power of two)
+constexpr int kBmMaxDisp = 64;     // displacements a 64-bit mask holds
+constexpr int kBmValCap = 16;      // slots of the value set
+
+__device__ __forceinline__ void small_set_insert(unsigned long long *set, int cap, uint64_t key, int *count) {
+    uint64_t s = mix64(key) & static_cast<uint64_t>(cap - 1);
+    for (int probe = 0; probe < cap; ++probe) {
+        const unsigned long long v = __atomic_load_n(&set[s], __ATOMIC_RELAXED);
+        if (v == key) return;
+        if (v == kEmpty) {
+            const unsigned long long old = atomicCAS(&set[s], kEmpty, static_cast<unsigned long long>(key));
+            if (old == kEmpty) {
+                atomicAdd(count, 1);
+                return;
+            }
+            if (old == key) return;
+        }
+        s = (s + 1) & static_cast<uint64_t>(cap - 1);
+    }
+}
+
+// Every entry's displacement (stored as d + 2^32, never the empty key) into
+// the set; rows stop once more than kBmMaxDisp keys are known.
+__global__ void k_bm_disp(int64_t n_rows, const int64_t *rp, const int32_t *col, unsigned long long *set, int *count) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_rows) return;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        if (__atomic_load_n(count, __ATOMIC_RELAXED) > kBmMaxDisp) return;
+        const int64_t d = static_cast<int64_t>(col[k]) - i;
+        small_set_insert(set, kBmSetCap, static_cast<uint64_t>(d + (int64_t(1) << 32)), count);
+    }
+}
+
+// The distinct values (bit patterns), up to three of them (the empty key's own
+// bit pattern, a NaN, is reported by a flag instead).
+__global__ void k_bm_values(int64_t nnz, const uint64_t *bits, unsigned long long *set, int *count, int *flags) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < nnz; k += stride) {
+        if (__atomic_load_n(count, __ATOMIC_RELAXED) > 2) return;
+        const uint64_t b = bits[k];
+        if (b == kEmpty)
+            atomicOr(flags, kFlagBmValueSentinel);
+        else
+            small_set_insert(set, kBmValCap, b, count);
+    }
+}
+
+// Row i: its mask over D (bit k for the entry at column i + D[k]) and, with
+// two table values, the mask of its V[1] entries; raw count (all entries when
+// there is no table); longest row.
+template <class MaskT>
+__global__ void k_bm_rows(RowArgs a, const int32_t *D, int nd, MaskT *mask, MaskT *vmask, int32_t *nraw,
+                          int *width) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n_rows) return;
+    MaskT m = 0, vm = 0;
+    for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+        const int64_t d = static_cast<int64_t>(a.col[k]) - i;
+        int lo = 0, hi = nd - 1;  // D is ascending and holds d
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (D[mid] < d)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const MaskT bit = static_cast<MaskT>(1) << lo;
+        m |= bit;
+        if (a.v.K == 2 && code_of(bits_of(a.val, k), a.v) == 1) vm |= bit;
+    }
+    mask[i] = m;
+    if (vmask) vmask[i] = vm;
+    const int len = static_cast<int>(a.rp[i + 1] - a.rp[i]);
+    nraw[i] = a.v.K == 0 ? len : 0;
+    atomicMax(width, len);
+}
+
 struct DecArgs {
     int64_t n_rows, n_pad;
     int fmt, K, width, id_bytes;
@@ -608,7 +691,15 @@ struct DecArgs {
     const int32_t *esc_col;
     const double *esc_val;
     const int64_t *esc_of_row; // [n_rows], -1 when not an escape row
+    // BMASK
+    const int32_t *bm_d;
+    const void *bm_mask, *bm_vmask;
+    int32_t bm_bytes;
 };
+
+__device__ __forceinline__ uint64_t dec_mask(const void *m, int bytes, int64_t i) {
+    return bytes == 4 ? static_cast<const uint32_t *>(m)[i] : static_cast<const uint64_t *>(m)[i];
+}
 
 __device__ __forceinline__ uint32_t dec_id(const DecArgs &a, int64_t i) {
     if (a.id_bytes == 1) return static_cast<const uint8_t *>(a.ids)[i];
@@ -623,6 +714,7 @@ __device__ __forceinline__ uint32_t esc_marker(int id_bytes) {
 __device__ int64_t dec_len(const DecArgs &a, int64_t i) {
     const int64_t e = a.esc_of_row[i];
     if (e >= 0) return a.esc_ptr[e + 1] - a.esc_ptr[e];
+    if (a.fmt == SPMVC_FMT_BMASK) return __popcll(dec_mask(a.bm_mask, a.bm_bytes, i));
     if (a.fmt == SPMVC_FMT_DIT) {
         const uint32_t id = dec_id(a, i);
         return id == esc_marker(a.id_bytes) ? 0 : a.pat_len[id];
@@ -665,6 +757,18 @@ __global__ void k_dec_fill(DecArgs a, const int64_t *out_rp, int32_t *out_col, d
             out_col[o + j] = c;
             out_val[o + j] = a.ell_val[static_cast<int64_t>(k) * a.n_pad + i];
             ++j;
+        }
+        return;
+    }
+    if (a.fmt == SPMVC_FMT_BMASK) {  // set bits in ascending order = columns ascending
+        uint64_t m = dec_mask(a.bm_mask, a.bm_bytes, i);
+        const uint64_t vm = a.K == 2 ? dec_mask(a.bm_vmask, a.bm_bytes, i) : 0;
+        const int64_t slice_base = a.K == 0 ? a.raw_slice[i / kSlice] + (i % kSlice) : 0;
+        for (int64_t j = 0; m; ++j) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            out_col[o + j] = static_cast<int32_t>(i + a.bm_d[k]);
+            out_val[o + j] = a.K == 0 ? a.raw[slice_base + j * kSlice] : a.V[(vm >> k) & 1];
         }
         return;
     }
@@ -753,7 +857,32 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
     // step 1: value table V (not needed for ELL)
     VTab vt{};
     vt.K = 0;
-    if (o.fmt != SPMVC_FMT_ELL && o.k_max > 0 && nnz > 0) {
+    if (o.fmt == SPMVC_FMT_BMASK && o.k_max > 0 && nnz > 0) {
+        // the table holds the matrix's values when there are at most two (and
+        // k_max allows them), ascending in totalOrder; else every value is raw
+        DevBuf vset, vcnt;
+        vset.alloc(sizeof(unsigned long long) * kBmValCap);
+        vcnt.alloc(sizeof(int));
+        k_fill_u64<<<1, kBmValCap, 0, s>>>(vset.as<uint64_t>(), kEmpty, kBmValCap);
+        SPMVC_HIP(hipMemsetAsync(vcnt.p, 0, sizeof(int), s));
+        SPMVC_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
+        k_bm_values<<<grid_for(nnz, kT, 4096), kT, 0, s>>>(nnz, reinterpret_cast<const uint64_t *>(val),
+                                                          vset.as<unsigned long long>(), vcnt.as<int>(), flags);
+        SPMVC_CHECK_LAUNCH();
+        std::vector<uint64_t> hv(kBmValCap);
+        SPMVC_HIP(hipMemcpyAsync(hv.data(), vset.p, vset.bytes, hipMemcpyDeviceToHost, s));
+        const int f = read_scalar<int>(flags, s);
+        std::vector<uint64_t> distinct;
+        for (uint64_t b : hv)
+            if (b != kEmpty) distinct.push_back(b);
+        if (f & kFlagBmValueSentinel) distinct.push_back(kEmpty);
+        if (static_cast<int>(distinct.size()) <= std::min(o.k_max, 2)) {
+            auto tok = [](uint64_t b) { return (b >> 63) ? ~b : (b | (1ull << 63)); };  // totalOrder key
+            std::sort(distinct.begin(), distinct.end(), [&](uint64_t x, uint64_t y) { return tok(x) < tok(y); });
+            vt.K = static_cast<int>(distinct.size());
+            for (int c = 0; c < vt.K; ++c) vt.b[c] = distinct[c];
+        }
+    } else if (o.fmt != SPMVC_FMT_ELL && o.k_max > 0 && nnz > 0) {
         const int64_t cap = std::min<int64_t>(next_pow2(std::max<int64_t>(2 * nnz, 1024)), 1ll << 24);
         DevBuf keys, cnt, fill, cand_key, cand_cnt, cand_n, sent, vout, kout;
         keys.alloc(sizeof(uint64_t) * cap);
@@ -831,6 +960,48 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
     if (o.fmt == SPMVC_FMT_ELL) {
         k_long_flags<<<gr, kT, 0, s>>>(n, rp, esc);
         SPMVC_CHECK_LAUNCH();
+    } else if (o.fmt == SPMVC_FMT_BMASK) {
+        // the displacement list D, then every row's masks
+        DevBuf dset, dcnt;
+        dset.alloc(sizeof(unsigned long long) * kBmSetCap);
+        dcnt.alloc(sizeof(int));
+        k_fill_u64<<<grid_for(kBmSetCap, kT, 64), kT, 0, s>>>(dset.as<uint64_t>(), kEmpty, kBmSetCap);
+        SPMVC_HIP(hipMemsetAsync(dcnt.p, 0, sizeof(int), s));
+        k_bm_disp<<<gr, kT, 0, s>>>(n, rp, col, dset.as<unsigned long long>(), dcnt.as<int>());
+        SPMVC_CHECK_LAUNCH();
+        const int cnt = read_scalar<int>(dcnt.p, s);
+        if (cnt > kBmMaxDisp)
+            throw Error{SPMVC_EUNSUPPORTED, "the matrix has more than 64 distinct displacements (col - row); "
+                                            "the bitmask format holds at most 64"};
+        std::vector<uint64_t> hs(kBmSetCap);
+        SPMVC_HIP(hipMemcpyAsync(hs.data(), dset.p, dset.bytes, hipMemcpyDeviceToHost, s));
+        SPMVC_HIP(hipStreamSynchronize(s));
+        M->h_bm_d.clear();
+        for (uint64_t k : hs)
+            if (k != kEmpty) M->h_bm_d.push_back(static_cast<int32_t>(static_cast<int64_t>(k) - (int64_t(1) << 32)));
+        std::sort(M->h_bm_d.begin(), M->h_bm_d.end());
+        M->bm_nd = static_cast<int32_t>(M->h_bm_d.size());
+        M->bm_bytes = M->bm_nd <= 32 ? 4 : 8;
+        M->bm_d.alloc(sizeof(int32_t) * M->bm_nd);
+        if (M->bm_nd > 0)
+            SPMVC_HIP(hipMemcpyAsync(M->bm_d.p, M->h_bm_d.data(), sizeof(int32_t) * M->bm_nd, hipMemcpyHostToDevice, s));
+        M->bm_mask.alloc(static_cast<size_t>(M->bm_bytes) * n_pad);
+        SPMVC_HIP(hipMemsetAsync(M->bm_mask.p, 0, M->bm_mask.bytes, s));
+        if (vt.K == 2) {
+            M->bm_vmask.alloc(static_cast<size_t>(M->bm_bytes) * n_pad);
+            SPMVC_HIP(hipMemsetAsync(M->bm_vmask.p, 0, M->bm_vmask.bytes, s));
+        }
+        DevBuf wmax;
+        wmax.alloc(sizeof(int));
+        SPMVC_HIP(hipMemsetAsync(wmax.p, 0, sizeof(int), s));
+        if (M->bm_bytes == 4)
+            k_bm_rows<uint32_t><<<gr, kT, 0, s>>>(ra, M->bm_d.as<int32_t>(), M->bm_nd, M->bm_mask.as<uint32_t>(),
+                                                  M->bm_vmask.as<uint32_t>(), nraw_b.as<int32_t>(), wmax.as<int>());
+        else
+            k_bm_rows<uint64_t><<<gr, kT, 0, s>>>(ra, M->bm_d.as<int32_t>(), M->bm_nd, M->bm_mask.as<uint64_t>(),
+                                                  M->bm_vmask.as<uint64_t>(), nraw_b.as<int32_t>(), wmax.as<int>());
+        SPMVC_CHECK_LAUNCH();
+        M->width = std::max(read_scalar<int>(wmax.p, s), 1);
     } else {
         // steps 2-4: canonical order, T_i, sequence hash
         M->T.alloc(static_cast<size_t>(std::max(vt.K, 1)) * n_pad);
@@ -959,9 +1130,9 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
     wb.alloc(sizeof(int));
     SPMVC_HIP(hipMemsetAsync(wb.p, 0, sizeof(int), s));
     k_fix_escape_T<<<gr, kT, 0, s>>>(n, n_pad, vt.K, esc, M->T.as<uint8_t>(), nraw_b.as<int32_t>(), rp,
-                                     o.fmt == SPMVC_FMT_DIT ? nullptr : wb.as<int>());
+                                     (o.fmt == SPMVC_FMT_DIT || o.fmt == SPMVC_FMT_BMASK) ? nullptr : wb.as<int>());
     SPMVC_CHECK_LAUNCH();
-    if (o.fmt != SPMVC_FMT_DIT) M->width = std::max(read_scalar<int>(wb.p, s), 1);
+    if (o.fmt != SPMVC_FMT_DIT && o.fmt != SPMVC_FMT_BMASK) M->width = std::max(read_scalar<int>(wb.p, s), 1);
 
     {
         DevBuf eflag, elen;
@@ -1069,6 +1240,10 @@ void decompress(const spmvc_matrix_s *M, int64_t *rp, int32_t *col, double *val,
     a.esc_col = M->esc_col.as<int32_t>();
     a.esc_val = M->esc_val.as<double>();
     a.esc_of_row = esc_of_row.as<int64_t>();
+    a.bm_d = M->bm_d.as<int32_t>();
+    a.bm_mask = M->bm_mask.p;
+    a.bm_vmask = M->bm_vmask.p;
+    a.bm_bytes = M->bm_bytes;
     DevBuf lens;
     lens.alloc(sizeof(int64_t) * (n + 1));
     k_dec_len<<<grid_for(n, kT, 0x7fffffff), kT, 0, s>>>(a, lens.as<int64_t>());

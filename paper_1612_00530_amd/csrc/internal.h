@@ -121,6 +121,9 @@ struct LdsPlan {
     int64_t m_S = 0, m_nz = 0, m_lo0 = 0;
     int32_t m_np = 0, m_C = 1, m_L = 0, m_NB = 0, m_NW = 0, m_zero_base = 0;
     DevBuf m_tab64, m_tab32;
+    // neighbour-bitmask format: LDS element offset of each displacement D[k]
+    // relative to the row's own position in its block
+    int32_t bm_off[64] = {};
 };
 
 constexpr int kRegW = 31;   // longest pattern the register kernel takes
@@ -137,7 +140,7 @@ constexpr int kRegTw = 32;  // uint16 per register-table row (64 bytes, 16-byte 
 // The opaque handle.
 struct spmvc_matrix_s {
     int64_t n_rows = 0, n_cols = 0, nnz = 0, n_pad = 0;
-    int32_t fmt = SPMVC_FMT_DIT;  // ELL, DT or DIT (DITV is DIT with fold set)
+    int32_t fmt = SPMVC_FMT_DIT;  // ELL, DT, DIT or BMASK (DITV is DIT with fold set)
     int32_t fold = 0;             // DITV: T_i registered per pattern (pat_T), no per-row T
     int32_t K = 0, P = 0, id_bytes = 1, width = 0, max_raw = 0;
     int32_t f32_shadow = 1;
@@ -147,6 +150,12 @@ struct spmvc_matrix_s {
     // device arrays
     spmvc::DevBuf ell_val, ell_col, dt_S, ids, T, pat_off, pat_len, pat_T, raw, raw32, raw_slice,
         esc_rows, esc_ptr, esc_col, esc_val, esc_val32, V_dev;
+    // neighbour-bitmask format (BMASK): the ascending displacement list D and,
+    // per row, a mask over D (bm_bytes = 4 when |D| <= 32, else 8) and, with
+    // two table values, a mask of the entries holding V[1]
+    int32_t bm_nd = 0, bm_bytes = 4;
+    spmvc::DevBuf bm_d, bm_mask, bm_vmask;
+    std::vector<int32_t> h_bm_d;
     // host copies of the (small) pattern table, for LDS plans
     std::vector<int32_t> h_pat_off; // [P][width]
     std::vector<uint8_t> h_pat_len; // [P]

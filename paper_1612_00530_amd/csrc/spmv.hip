@@ -89,6 +89,11 @@ struct SpmvArgs {
     int32_t m_L;                   // elements per window buffer
     int32_t m_NB;                  // window buffers in the ring (windows + 1)
     int32_t m_NW;                  // windows a tile reads
+    // neighbour-bitmask format: displacement list, masks, LDS offsets
+    const int32_t *bm_d;
+    const void *bm_mask, *bm_vmask;
+    int32_t bm_nd;
+    int32_t bm_off[64];            // element offset of D[k] in the windows (LDS kernel)
 };
 
 template <class Real> __device__ __forceinline__ Real vtab(const SpmvArgs &a, int c);
@@ -220,6 +225,20 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
             const int64_t o = static_cast<int64_t>(k) * a.n_pad + row;
             const int32_t c = ldg_stream(a.cols + o);
             if (c >= 0) apply(static_cast<Real>(ldg_stream(a.ell_val + o)), c);
+        }
+    } else if constexpr (FMT == SPMVC_FMT_BMASK) {
+        // set bits of the row's mask in ascending order = its columns ascending;
+        // IdT is the mask type
+        IdT m = static_cast<const IdT *>(a.bm_mask)[row];
+        const IdT vm = a.K == 2 ? static_cast<const IdT *>(a.bm_vmask)[row] : IdT(0);
+        const Real *raw = static_cast<const Real *>(a.raw);
+        const int64_t rb = RAW ? a.raw_slice[row / kSlice] + (row % kSlice) : 0;
+        for (int j = 0; m; ++j) {
+            const int k = static_cast<int>(__builtin_ctzll(static_cast<uint64_t>(m)));
+            m &= m - 1;
+            const Real v = RAW ? ldg_stream(raw + rb + static_cast<int64_t>(j) * kSlice)
+                               : vtab<Real>(a, a.K == 2 ? static_cast<int>((vm >> k) & 1) : 0);
+            apply(v, row + a.bm_d[k]);
         }
     } else {
         const int32_t *pat = nullptr;
@@ -676,6 +695,123 @@ __global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__
     emit_dot(a, dotc);
 }
 
+// The value of the first active lane, as a wavefront-uniform (scalar) value.
+template <class T> __device__ __forceinline__ T first_lane(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = static_cast<uint64_t>(v);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+        return static_cast<T>((static_cast<uint64_t>(hi) << 32) | lo);
+    } else {
+        return static_cast<T>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v)));
+    }
+}
+
+// ---- BMASK: neighbour bitmask over the displacement list, x windows in LDS --------
+// Every row shares one displacement list D, so entry k of any row reads its x
+// element at the same offset from the row's own slot in the LDS windows
+// (bm_off[k], uniform across the wavefront).  With a value table the loop runs
+// over k: where every lane of a wavefront has the full mask and the same V[1]
+// mask (the interior of a stencil), the entries are summed without any
+// per-lane test, all LDS reads in flight; otherwise each entry is taken under
+// its lane's mask bit.  With no table (KK = 0) the values come in column order
+// from the row's raw slice (the slice width is uniform per wavefront, 16-byte
+// loads of consecutive rows), eight at a time, and the column of the j-th value
+// is the j-th set bit of the mask, its offset read from a copy of bm_off in LDS.
+template <class Real, class MaskT, int KK, int RPT, int NDM>
+__global__ __launch_bounds__(kBlock) void k_bmask_lds(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
+    if (a.skip && *a.skip) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Real *xs = reinterpret_cast<Real *>(smem);
+    int32_t *offs = reinterpret_cast<int32_t *>(smem + ((static_cast<size_t>(a.lds_total) * sizeof(Real) + 15) & ~size_t(15)));
+    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * (kBlock * RPT);
+    const MaskT *mk = static_cast<const MaskT *>(a.bm_mask);
+    const MaskT *vmk = static_cast<const MaskT *>(a.bm_vmask);
+    MaskT mv[RPT], vv[RPT];
+    Real xrow[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int64_t row = r0 + threadIdx.x + j * kBlock;
+        const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
+        mv[j] = row < a.n_rows ? mk[rc] : MaskT(0);
+        vv[j] = KK == 2 ? vmk[rc] : MaskT(0);
+        xrow[j] = a.dot ? x[rc] : Real(0);
+    }
+    stage_windows_async<Real>(a, x, xs, r0);
+    if (KK == 0 && threadIdx.x < static_cast<unsigned>(a.bm_nd)) offs[threadIdx.x] = a.bm_off[threadIdx.x];
+    __builtin_amdgcn_s_waitcnt(0);  // direct loads have landed in LDS
+    __syncthreads();
+    Real v0, v1;
+    if constexpr (KK >= 1) value_pair<Real, KK>(a, v0, v1);
+    const int nd = a.bm_nd;
+    const MaskT full = nd >= static_cast<int>(8 * sizeof(MaskT)) ? ~MaskT(0) : ((MaskT(1) << nd) - 1);
+    double dotc = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int rel = threadIdx.x + j * kBlock;
+        const int64_t row = r0 + rel;
+        const Real *xr = xs + rel;
+        MaskT m = mv[j];
+        Real acc = Real(0);
+        if constexpr (KK == 0) {
+            const Real *raw = static_cast<const Real *>(a.raw);
+            const int64_t sl = (row < a.n_rows ? row : a.n_rows - 1) / kSlice;
+            const int64_t s0 = a.raw_slice[sl];
+            const int sw = static_cast<int>((a.raw_slice[sl + 1] - s0) / kSlice);
+            const Real *rp = raw + s0 + (row % kSlice);
+            for (int j0 = 0; j0 < sw; j0 += 8) {
+                Real rv[8];
+                int kk[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool on = j0 + u < sw && m != 0;
+                    kk[u] = on ? static_cast<int>(__builtin_ctzll(static_cast<uint64_t>(m))) : -1;
+                    if (on) m &= m - 1;
+                    rv[u] = on ? ldg_stream(rp + static_cast<int64_t>(j0 + u) * kSlice) : Real(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (kk[u] >= 0) acc = fma(rv[u], xr[offs[kk[u]]], acc);
+            }
+        } else {
+            // uniform wavefront: full masks and one V[1] mask
+            const MaskT vm = vv[j];
+            const MaskT vm0 = first_lane(vm);
+            const bool uni = __ballot(m != full || vm != vm0) == 0;
+            Real s0 = Real(0), s1 = Real(0);
+            if (uni) {
+                Real xv[NDM];
+#pragma unroll
+                for (int k = 0; k < NDM; ++k) xv[k] = k < nd ? xr[a.bm_off[k]] : Real(0);
+#pragma unroll
+                for (int k = 0; k < NDM; ++k) {
+                    if (KK == 2 && ((vm0 >> k) & 1))
+                        s1 += xv[k];
+                    else
+                        s0 += xv[k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NDM; ++k) {
+                    if (k < nd && ((m >> k) & 1)) {
+                        const Real xk = xr[a.bm_off[k]];
+                        if (KK == 2 && ((vm >> k) & 1))
+                            s1 += xk;
+                        else
+                            s0 += xk;
+                    }
+                }
+            }
+            acc = KK == 2 ? fma(v1, s1, v0 * s0) : v0 * s0;
+        }
+        if (row < a.n_rows) {
+            y[row] = acc;
+            if (a.dot) dotc += static_cast<double>(xrow[j]) * static_cast<double>(acc);
+        }
+    }
+    emit_dot(a, dotc);
+}
+
 // ---- block SpMV: a group of LPR lanes per row -------------------------------------
 // Y = A X for nrhs row-interleaved right-hand sides.  A row is served by LPR
 // lanes, each taking VEC adjacent right-hand sides (VEC = 2: one 8- or
@@ -732,6 +868,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, con
             const int64_t o = static_cast<int64_t>(k) * a.n_pad + row;
             const int32_t c = a.cols[o];
             if (c >= 0) apply(static_cast<Real>(a.ell_val[o]), c);
+        }
+    } else if constexpr (FMT == SPMVC_FMT_BMASK) {
+        // set bits of the row's mask in ascending order = its columns ascending;
+        // IdT is the mask type
+        IdT m = static_cast<const IdT *>(a.bm_mask)[row];
+        const IdT vm = a.K == 2 ? static_cast<const IdT *>(a.bm_vmask)[row] : IdT(0);
+        const Real *raw = static_cast<const Real *>(a.raw);
+        const int64_t rb = RAW ? a.raw_slice[row / kSlice] + (row % kSlice) : 0;
+        for (int j = 0; m; ++j) {
+            const int k = static_cast<int>(__builtin_ctzll(static_cast<uint64_t>(m)));
+            m &= m - 1;
+            const Real v = RAW ? ldg_stream(raw + rb + static_cast<int64_t>(j) * kSlice)
+                               : vtab<Real>(a, a.K == 2 ? static_cast<int>((vm >> k) & 1) : 0);
+            apply(v, row + a.bm_d[k]);
         }
     } else {
         const int32_t *pat = nullptr;
@@ -1033,6 +1183,10 @@ template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *ski
     a.esc_val = f32 ? M->esc_val32.p : M->esc_val.p;
     a.n_esc = M->n_esc;
     a.n_xcd = M->n_xcd;
+    a.bm_d = M->bm_d.as<int32_t>();
+    a.bm_mask = M->bm_mask.p;
+    a.bm_vmask = M->bm_vmask.p;
+    a.bm_nd = M->bm_nd;
     for (int c = 0; c < kMaxK; ++c) {
         a.V[c] = M->V[c];
         a.V32[c] = M->V32[c];
@@ -1060,6 +1214,18 @@ void launch_direct_nr(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
             k_spmv_direct<SPMVC_FMT_DT, Real, uint8_t, true, NR><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
         else
             k_spmv_direct<SPMVC_FMT_DT, Real, uint8_t, false, NR><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+    } else if (M->fmt == SPMVC_FMT_BMASK) {
+        if (M->bm_bytes == 4) {
+            if (raw)
+                k_spmv_direct<SPMVC_FMT_BMASK, Real, uint32_t, true, NR><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+            else
+                k_spmv_direct<SPMVC_FMT_BMASK, Real, uint32_t, false, NR><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+        } else {
+            if (raw)
+                k_spmv_direct<SPMVC_FMT_BMASK, Real, uint64_t, true, NR><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+            else
+                k_spmv_direct<SPMVC_FMT_BMASK, Real, uint64_t, false, NR><<<grid, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
+        }
     } else {
 #define SPMVC_DIT_DIRECT(IDT)                                                                                 \
     if (raw)                                                                                                  \
@@ -1403,7 +1569,7 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
         if (nrhs > 1 && !dot && M->block_mode[dt] == 3 && launch_block_win(M, a, nrhs, X, ldx, Y, ldy, s)) return;
         if (nrhs > 1 && !dot && M->block_mode[dt] == 2 && launch_pairs(M, a, nrhs, X, ldx, Y, ldy, s)) return;
     }
-    if (nrhs > 1 && !dot && M->block_mode[dt]) {
+    if (nrhs > 1 && !dot && M->block_mode[dt] && M->fmt != SPMVC_FMT_BMASK) {
         launch_lanes<Real>(M, a, nrhs, X, ldx, Y, ldy, s);
         return;
     }
@@ -1417,7 +1583,61 @@ void launch_block_t(const spmvc_matrix_s *M, int nrhs, const void *X, int64_t ld
         launch_direct_nr<Real, 16>(M, a, nrhs, X, ldx, Y, ldy, s);
 }
 
+// BMASK with x windows in LDS (k_bmask_lds); returns the number of blocks.
+template <class Real>
+unsigned launch_bmask_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y, hipStream_t s) {
+    constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
+    const LdsPlan &p = M->plan[dt];
+    a.rows = p.rows;
+    a.n_win = p.n_win;
+    a.lds_total = p.total;
+    for (int w = 0; w < p.n_win; ++w) {
+        a.win_lo[w] = p.lo[w];
+        a.win_len[w] = p.len[w];
+        a.win_base[w] = p.base[w];
+    }
+    for (int k = 0; k < 64; ++k) a.bm_off[k] = k < M->bm_nd ? p.bm_off[k] : 0;
+    a.zero_len = 0;
+    a.n_main_blocks = static_cast<unsigned>((M->n_rows + p.rows - 1) / p.rows);
+    a.async_lds = (reinterpret_cast<uintptr_t>(x) % 16) == 0;
+    const unsigned grid = a.n_main_blocks;
+    const size_t shmem = ((sizeof(Real) * static_cast<size_t>(p.total) + 15) & ~size_t(15)) + sizeof(int32_t) * 64;
+    const Real *xp = static_cast<const Real *>(x);
+    Real *yp = static_cast<Real *>(y);
+    const int rpt = p.rows / kBlock;
+    const int kk = M->raw_elems > 0 ? 0 : M->K;  // 0: values raw; 1, 2: table
+#define SPMVC_BM_R(MT, KK, NDM)                                                              \
+    if (rpt == 1)                                                                            \
+        k_bmask_lds<Real, MT, KK, 1, NDM><<<grid, kBlock, shmem, s>>>(a, xp, yp);            \
+    else if (rpt == 2)                                                                       \
+        k_bmask_lds<Real, MT, KK, 2, NDM><<<grid, kBlock, shmem, s>>>(a, xp, yp);            \
+    else                                                                                     \
+        k_bmask_lds<Real, MT, KK, 4, NDM><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+#define SPMVC_BM_K(MT, NDM)     \
+    if (kk == 0) {              \
+        SPMVC_BM_R(MT, 0, NDM)  \
+    } else if (kk == 1) {       \
+        SPMVC_BM_R(MT, 1, NDM)  \
+    } else {                    \
+        SPMVC_BM_R(MT, 2, NDM)  \
+    }
+    if (M->bm_bytes == 4) {
+        if (M->bm_nd <= 27) {
+            SPMVC_BM_K(uint32_t, 27)
+        } else {
+            SPMVC_BM_K(uint32_t, 32)
+        }
+    } else {
+        SPMVC_BM_K(uint64_t, 64)
+    }
+#undef SPMVC_BM_K
+#undef SPMVC_BM_R
+    SPMVC_CHECK_LAUNCH();
+    return grid;
+}
+
 bool uses_lds(const spmvc_matrix_s *M, int dt) {
+    if (M->fmt == SPMVC_FMT_BMASK) return M->lds_mode[dt] >= 1 && M->plan[dt].n_win > 0;
     return M->fmt == SPMVC_FMT_DIT && M->lds_mode[dt] >= 1 && M->plan[dt].n_win > 0 && M->P > 0;
 }
 
@@ -1427,7 +1647,10 @@ unsigned launch_spmv_t(const spmvc_matrix_s *M, const void *x, void *y, hipStrea
                        double *dot = nullptr) {
     if (M->n_rows == 0) return 0;
     constexpr int dt = sizeof(Real) == 8 ? SPMVC_F64 : SPMVC_F32;
-    if (uses_lds(M, dt)) return launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
+    if (uses_lds(M, dt)) {
+        if (M->fmt == SPMVC_FMT_BMASK) return launch_bmask_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
+        return launch_lds<Real>(M, make_args<Real>(M, skip, dot), x, y, s);
+    }
     launch_block_t<Real>(M, 1, x, 1, y, 1, s, skip, dot);
     return static_cast<unsigned>((M->n_pad + kBlock - 1) / kBlock + escape_blocks(M));
 }
@@ -1583,13 +1806,17 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     p.march = false;
     p.m_tab64.release();
     p.m_tab32.release();
-    if (M->fmt != SPMVC_FMT_DIT || M->P == 0 || M->width == 0) return;
+    const bool bmask = M->fmt == SPMVC_FMT_BMASK;
+    if (bmask ? M->bm_nd == 0 : (M->fmt != SPMVC_FMT_DIT || M->P == 0 || M->width == 0)) return;
     const int W = M->width;
     std::set<int64_t> ds;
-    for (int q = 0; q < M->P; ++q)
-        for (int k = 0; k < M->h_pat_len[q]; ++k) ds.insert(M->h_pat_off[static_cast<size_t>(q) * W + k]);
+    if (bmask)
+        ds.insert(M->h_bm_d.begin(), M->h_bm_d.end());
+    else
+        for (int q = 0; q < M->P; ++q)
+            for (int k = 0; k < M->h_pat_len[q]; ++k) ds.insert(M->h_pat_off[static_cast<size_t>(q) * W + k]);
     if (ds.empty()) return;
-    build_block_window_plan(M, p, ds);  // independent of `rows`
+    if (!bmask) build_block_window_plan(M, p, ds);  // independent of `rows`
     // Two windows merge when the gap between them is below `rows`: a separate
     // window costs `rows` more LDS elements than the gap it skips.
     std::vector<std::pair<int64_t, int64_t>> win;
@@ -1616,6 +1843,21 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         while (!(d >= win[w].first && d <= win[w].second)) ++w;
         return base[w] + d - lo[w];  // lo[w] <= win[w].first
     };
+    if (bmask) {
+        // the element offset of every displacement; no pattern tables.  The
+        // kernel takes 1, 2 or 4 rows per thread.
+        if (rows > 4 * kBlock) return;
+        for (int k = 0; k < 64; ++k) p.bm_off[k] = 0;
+        for (int k = 0; k < M->bm_nd; ++k) p.bm_off[k] = static_cast<int32_t>(lds_index(M->h_bm_d[k]));
+        for (size_t w = 0; w < win.size(); ++w) {
+            p.lo[w] = lo[w];
+            p.len[w] = static_cast<int32_t>(len[w]);
+            p.base[w] = static_cast<int32_t>(base[w]);
+        }
+        p.total = static_cast<int32_t>(total);
+        p.n_win = static_cast<int>(win.size());
+        return;
+    }
     // walk-kernel table: [len, element index...]
     const int64_t tab_bytes = static_cast<int64_t>(M->P) * (W + 1) * static_cast<int64_t>(sizeof(uint16_t));
     std::vector<uint16_t> tab(static_cast<size_t>(M->P) * (W + 1), 0);
@@ -1699,6 +1941,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
 
 int kernel_kind(const spmvc_matrix_s *M, int dt) {
     if (!uses_lds(M, dt)) return 0;
+    if (M->fmt == SPMVC_FMT_BMASK) return 4;
     if (reg_variant(M, dt) == 0) return 1;
     return M->lds_mode[dt] == 2 && M->plan[dt].march ? 3 : 2;
 }
@@ -1747,6 +1990,11 @@ int64_t stream_bytes(const spmvc_matrix_s *M, int dt) {
     const int64_t slots = static_cast<int64_t>(M->width) * M->n_pad;
     if (M->fmt == SPMVC_FMT_ELL) {
         b += slots * (4 + 8);
+    } else if (M->fmt == SPMVC_FMT_BMASK) {
+        b += static_cast<int64_t>(M->bm_bytes) * M->n_pad * (M->K == 2 ? 2 : 1);  // masks
+        b += M->raw_elems * vb;                                                  // values
+        if (M->raw_elems) b += 8 * (M->n_pad / kSlice + 1);                      // slice pointers
+        b += 4 * static_cast<int64_t>(M->bm_nd);                                 // D
     } else {
         if (!M->fold) b += static_cast<int64_t>(M->K) * M->n_pad;  // T (DITV: in the pattern table)
         b += M->raw_elems * vb;                               // raw values

@@ -46,6 +46,10 @@ struct GsArgs {
     const double *esc_val;
     int64_t n_esc;
     double V[kMaxK];
+    // BMASK: displacement list, per-row masks (4 or 8 bytes)
+    const int32_t *bm_d;
+    const void *bm_mask, *bm_vmask;
+    int32_t bm_bytes;
 };
 
 __device__ __forceinline__ uint32_t gs_id(const GsArgs &a, int64_t row) {
@@ -56,6 +60,20 @@ __device__ __forceinline__ uint32_t gs_id(const GsArgs &a, int64_t row) {
 
 // Calls f(value, column) for every entry of `row`.
 template <class F> __device__ __forceinline__ void gs_visit(const GsArgs &a, int64_t row, F f) {
+    if (a.fmt == SPMVC_FMT_BMASK) {  // set bits ascending = columns ascending; no escape rows
+        auto mask_at = [&](const void *m) -> uint64_t {
+            return a.bm_bytes == 4 ? static_cast<const uint32_t *>(m)[row] : static_cast<const uint64_t *>(m)[row];
+        };
+        uint64_t m = mask_at(a.bm_mask);
+        const uint64_t vm = a.K == 2 ? mask_at(a.bm_vmask) : 0;
+        const int64_t rb = a.raw ? a.raw_slice[row / kSlice] + (row % kSlice) : 0;
+        for (int64_t j = 0; m; ++j) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            f(a.raw ? a.raw[rb + j * kSlice] : a.V[(vm >> k) & 1], row + a.bm_d[k]);
+        }
+        return;
+    }
     bool escape = false;
     uint32_t id = 0;
     if (a.fmt == SPMVC_FMT_DIT) {
@@ -220,6 +238,10 @@ GsArgs gs_args(const spmvc_matrix_s *M) {
     a.esc_val = M->esc_val.as<double>();
     a.n_esc = M->n_esc;
     for (int c = 0; c < kMaxK; ++c) a.V[c] = M->V[c];
+    a.bm_d = M->bm_d.as<int32_t>();
+    a.bm_mask = M->bm_mask.p;
+    a.bm_vmask = M->bm_vmask.p;
+    a.bm_bytes = M->bm_bytes;
     return a;
 }
 

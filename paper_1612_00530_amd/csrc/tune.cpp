@@ -110,6 +110,9 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
             for (int rows : {256, 512, 1024, 2048, 4096}) cands.push_back({rows, 1});
             for (int rows : {256, 512, 1024}) cands.push_back({rows, 2});
             cands.push_back({A->rows_per_block[dt], 0});
+        } else if (A->fmt == SPMVC_FMT_BMASK && nrhs == 1) {
+            for (int rows : {256, 512, 1024}) cands.push_back({rows, 1});
+            cands.push_back({A->rows_per_block[dt], 0});
         } else if (nrhs > 1) {
             // block SpMV: whole rows in LDS one window at a time (3) or LDS
             // windows of right-hand-side pairs (2), where they apply; a lane
@@ -138,7 +141,8 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
                 A->lds_mode[dt] = c.lds;
                 A->rows_per_block[dt] = c.rows;
                 build_lds_plan(A, dt, c.rows);
-                if (c.lds >= 1 && A->fmt == SPMVC_FMT_DIT && A->plan[dt].n_win == 0) continue;  // does not fit
+                if (c.lds >= 1 && (A->fmt == SPMVC_FMT_DIT || A->fmt == SPMVC_FMT_BMASK) && A->plan[dt].n_win == 0)
+                    continue;  // does not fit
                 if (c.lds == 2 && kernel_kind(A, dt) != 3) continue;  // no plane-marching form
             }
             auto run = [&]() {
