@@ -304,6 +304,23 @@ def main():
     log(f"[bench] DITV: {ditv['launch_us_mean']} us, {ditv['gflops']} Gflops, {ditv['bytes_per_row']} B/row")
     del DV
 
+    # BMASK: a bitmask per row over the matrix's 27 displacements, plus the V[1] mask
+    rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
+    DB = P.compress(rp, col, val, n_cols=n, fmt="BMASK")
+    del rp, col, val
+    tuned_b = DB.tune(torch.float64) if not args.no_tune else None
+    binf = DB.info()
+    for _ in range(5):
+        DB.spmv(x, y)
+    bm_mean = time_batch(lambda: DB.spmv(x, y), max(20, args.steps // 2), torch)
+    alg_b = binf["bytes_stream"] + 8 * n + 8 * n
+    bmask = {"launch_us_mean": round(bm_mean * 1000, 3), "gflops": round(2.0 * nnz / (bm_mean * 1e-3) / 1e9, 1),
+             "bytes_per_row": round(binf["bytes_stream"] / n, 3), "bytes_per_launch": alg_b,
+             "GBps": round(alg_b / (bm_mean * 1e-3) / 1e9, 1), "speedup_vs_ell": round(e_mean / bm_mean, 3),
+             "kernel": binf["kernel_name"], "displacements": binf["P"], "tuned": tuned_b}
+    log(f"[bench] BMASK: {bmask['launch_us_mean']} us, {bmask['gflops']} Gflops, {bmask['bytes_per_row']} B/row")
+    del DB
+
     # multicolor symmetric Gauss-Seidel, one sweep (colors forward, then backward): DIT and ELL
     bgs = torch.from_numpy(uniform_vector(n, seed=6)).to(dev)
     xgs = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -426,6 +443,7 @@ def main():
         "block_spmv": block8,
         "dit_f32": {"launch_us_mean": round(f_mean * 1000, 3), "gflops": round(2.0 * nnz / (f_mean * 1e-3) / 1e9, 2)},
         "ditv": ditv,
+        "bmask": bmask,
         "symgs": symgs,
         "irregular": irregular,
         "reorder": reordered,
@@ -445,20 +463,30 @@ def run_irregular(P, torch, dev, steps):
     rp, col, val = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col, A.val))
     D = P.compress(rp, col, val, n_cols=A.n_cols, fmt="DIT")
     E = P.compress(rp, col, val, n_cols=A.n_cols, fmt="ELL")
+    B = P.compress(rp, col, val, n_cols=A.n_cols, fmt="BMASK")
     del rp, col, val
     tuned = D.tune(torch.float64)
+    tuned_b = B.tune(torch.float64)
     x = torch.from_numpy(uniform_vector(A.n_cols, seed=0)).to(dev)
     y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     d_us = time_batch(lambda: D.spmv(x, y), max(20, steps // 2), torch) * 1000
     e_us = time_batch(lambda: E.spmv(x, y), max(20, steps // 2), torch) * 1000
-    di, ei = D.info(), E.info()
+    b_us = time_batch(lambda: B.spmv(x, y), max(20, steps // 2), torch) * 1000
+    di, ei, bi = D.info(), E.info(), B.info()
     res = {"grid": [128, 128, 128], "n": A.n_rows, "nnz": A.nnz, "P": di["P"], "K": di["K"],
            "escape_rows": di["n_escape_rows"], "dit_us": round(d_us, 3), "ell_us": round(e_us, 3),
            "dit_gflops": round(2.0 * A.nnz / (d_us * 1e-6) / 1e9, 2),
            "ell_gflops": round(2.0 * A.nnz / (e_us * 1e-6) / 1e9, 2), "speedup": round(e_us / d_us, 3),
            "dit_bytes": di["bytes_stream"] + 16 * A.n_rows, "ell_bytes": ei["bytes_stream"] + 16 * A.n_rows,
-           "dit_GBps": round((di["bytes_stream"] + 16 * A.n_rows) / (d_us * 1e-6) / 1e9, 1), "tuned": tuned}
-    log(f"[bench] irregular: DIT {d_us:.1f} us vs ELL {e_us:.1f} us")
+           "dit_GBps": round((di["bytes_stream"] + 16 * A.n_rows) / (d_us * 1e-6) / 1e9, 1), "tuned": tuned,
+           "bmask": {"us": round(b_us, 3), "gflops": round(2.0 * A.nnz / (b_us * 1e-6) / 1e9, 2),
+                     "bytes": bi["bytes_stream"] + 16 * A.n_rows,
+                     "GBps": round((bi["bytes_stream"] + 16 * A.n_rows) / (b_us * 1e-6) / 1e9, 1),
+                     "hbm_frac": round((bi["bytes_stream"] + 16 * A.n_rows) / (b_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "speedup_vs_ell": round(e_us / b_us, 3), "speedup_vs_dit": round(d_us / b_us, 3),
+                     "escape_rows": bi["n_escape_rows"], "displacements": bi["P"], "mask_bytes": bi["id_bytes"],
+                     "tuned": tuned_b}}
+    log(f"[bench] irregular: DIT {d_us:.1f} us vs ELL {e_us:.1f} us vs BMASK {b_us:.1f} us")
     return res
 
 

@@ -18,6 +18,7 @@
 // IDs are ranks of the patterns' first rows; nothing depends on the order in
 // which blocks run.
 #include <algorithm>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -273,8 +274,9 @@ __device__ __forceinline__ uint64_t seq_hash_step(uint64_t h, int32_t d) {
     return (h ^ static_cast<uint32_t>(d)) * 0x100000001B3ull;
 }
 
-__device__ __forceinline__ uint64_t seq_hash_final(uint64_t h, int64_t len) {
+__device__ __forceinline__ uint64_t seq_hash_final(uint64_t h, int64_t len, int bits) {
     uint64_t r = mix64(h ^ (static_cast<uint64_t>(len) * 0x9E3779B97F4A7C15ull));
+    if (bits < 64) r &= (1ull << bits) - 1;
     return r == kEmpty ? kEmpty - 1 : r;
 }
 
@@ -285,6 +287,11 @@ struct RowArgs {
     const double *val;
     VTab v;
     int fold;  // DITV: a pattern is (displacement sequence, T_i)
+    // pattern hash: seed (a hash collision between two different sequences
+    // makes the compressor hash again with the next seed) and width in bits
+    // (64; narrower only to exercise that retry in tests)
+    uint64_t hash_seed = 0;
+    int hash_bits = 64;
 };
 
 __global__ void k_canon(RowArgs a, uint8_t *T, int32_t *nraw, uint64_t *hash, uint8_t *is_long) {
@@ -300,7 +307,7 @@ __global__ void k_canon(RowArgs a, uint8_t *T, int32_t *nraw, uint64_t *hash, ui
         return;
     }
     is_long[i] = 0;
-    uint64_t h = 0xCBF29CE484222325ull;
+    uint64_t h = 0xCBF29CE484222325ull ^ mix64(a.hash_seed);
     int pos = 0;
     for (int c = 0; c <= a.v.K; ++c) {
         for (int64_t k = b0; k < b1; ++k) {
@@ -314,7 +321,7 @@ __global__ void k_canon(RowArgs a, uint8_t *T, int32_t *nraw, uint64_t *hash, ui
     nraw[i] = static_cast<int32_t>(len) - coded;
     if (a.fold)  // the registered key includes T_i (with V fixed: the values)
         for (int c = 0; c < a.v.K; ++c) h = seq_hash_step(h, 0x40000000 + T[c * a.n_pad + i]);
-    hash[i] = seq_hash_final(h, len);
+    hash[i] = seq_hash_final(h, len, a.hash_bits);
 }
 
 // Cursor over one row's entries in canonical (code, column) order.
@@ -1018,6 +1025,21 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
             pcnt.alloc(sizeof(uint32_t) * pcap);
             pmin.alloc(sizeof(int64_t) * pcap);
             pfill.alloc(sizeof(int));
+            rowslot.alloc(sizeof(int64_t) * n);
+            keep.alloc(pcap);
+            nkeep.alloc(sizeof(int));
+            // SPMVC_TEST_WEAK_PATTERN_HASH=1 narrows the first attempt's hash to
+            // 4 bits (collisions certain), to exercise the retry with a new seed
+            const char *weak = std::getenv("SPMVC_TEST_WEAK_PATTERN_HASH");
+            const bool weak_first = weak && weak[0] == '1';
+            constexpr int kHashAttempts = 4;
+            for (int attempt = 0;; ++attempt) {  // (loop body not indented)
+            if (attempt > 0 || weak_first) {  // hash the sequences again
+                ra.hash_seed = static_cast<uint64_t>(attempt);
+                ra.hash_bits = (attempt == 0 && weak_first) ? 4 : 64;
+                k_canon<<<gr, kT, 0, s>>>(ra, M->T.as<uint8_t>(), nraw_b.as<int32_t>(), hash_b.as<uint64_t>(), esc);
+                SPMVC_CHECK_LAUNCH();
+            }
             k_fill_u64<<<grid_for(pcap, kT, 0x7fffffff), kT, 0, s>>>(pkeys.as<uint64_t>(), kEmpty, pcap);
             k_fill_i64<<<grid_for(pcap, kT, 0x7fffffff), kT, 0, s>>>(pmin.as<int64_t>(), INT64_MAX, pcap);
             SPMVC_HIP(hipMemsetAsync(pcnt.p, 0, pcnt.bytes, s));
@@ -1028,19 +1050,19 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
             k_aggregate<<<grid_for(n, kAggChunk, 2048), kAggThreads, 0, s>>>(hash_b.as<uint64_t>(), n, pt,
                                                                             1, 0, nullptr);
             SPMVC_CHECK_LAUNCH();
-            rowslot.alloc(sizeof(int64_t) * n);
             k_pattern_lookup<<<gr, kT, 0, s>>>(ra, pt, hash_b.as<uint64_t>(), esc, rowslot.as<int64_t>());
             SPMVC_CHECK_LAUNCH();
-            keep.alloc(pcap);
-            nkeep.alloc(sizeof(int));
             SPMVC_HIP(hipMemsetAsync(nkeep.p, 0, sizeof(int), s));
             k_mark_keep<<<grid_for(pcap, kT, 0x7fffffff), kT, 0, s>>>(pt, pcap, std::max(o.min_pattern_rows, 1),
                                                                     keep.as<uint8_t>(), nkeep.as<int>());
             SPMVC_CHECK_LAUNCH();
             const int f = read_scalar<int>(flags, s);
-            if (f & kFlagCollision)
-                throw Error{SPMVC_EUNSUPPORTED, "64-bit pattern-hash collision between different displacement sequences"};
             if (f & kFlagOverflow) throw Error{SPMVC_EUNSUPPORTED, "pattern hash table overflow"};
+            if (!(f & kFlagCollision)) break;
+            if (attempt + 1 == kHashAttempts)
+                throw Error{SPMVC_EUNSUPPORTED, "pattern-hash collisions between different displacement sequences "
+                                                "with every hash seed tried"};
+            }
             int n_keep = read_scalar<int>(nkeep.p, s);
             if (n_keep > o.p_max) {
                 // rank the qualifying patterns by (count desc, first row asc), keep p_max

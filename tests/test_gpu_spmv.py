@@ -464,6 +464,23 @@ def test_dit_arrays_equal_reference_codec(fmt, make):
         assert same_bits(raw[sl[rows // 64] + rows % 64 + 64 * j], enc.raw)
 
 
+@pytest.mark.parametrize("fmt", ["DIT", "DITV"])
+def test_pattern_hash_collisions_are_resolved(fmt, monkeypatch):
+    """With the first attempt's pattern hash narrowed to 4 bits (a test switch
+    of the compressor), different displacement sequences collide; the
+    compressor must detect it and hash again with a new seed, giving the very
+    arrays of the reference codec and a bit-exact round trip."""
+    say("case: pattern hash collisions", fmt)
+    monkeypatch.setenv("SPMVC_TEST_WEAK_PATTERN_HASH", "1")
+    for make in (lambda: stencil27(16, 16, 16), lambda: stencil27_irregular(20, 17, 13, seed=1)):
+        test_dit_arrays_equal_reference_codec(fmt, make)
+        A = make()
+        M = compress(A, fmt=fmt)
+        assert roundtrip_ok(M, A)
+        x = uniform_vector(A.n_cols, seed=2)
+        assert max_rel_err(A, x, gpu_spmv(M, x), oracle.spmv(A, x)) <= 1e-14
+
+
 def test_dt_arrays_equal_reference_codec():
     say("case: DT arrays")
     A = stencil27(12, 10, 9)
