@@ -554,8 +554,9 @@ template <class Real, int KK> __device__ __forceinline__ void value_pair(const S
 // blocks fit a CU; asking for seven waves per SIMD keeps registers from being
 // the tighter limit (at most 72 VGPRs instead of 80, no spills).
 template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
-__global__ __launch_bounds__(kBlock, RPT <= 2 ? 7 : 1) void k_dit_reg(SpmvArgs a, const Real *__restrict__ x,
-                                                                      Real *__restrict__ y) {
+__global__ __launch_bounds__(kBlock, RPT <= 2 ? 7 : (RPT == 3 ? 6 : 1)) void k_dit_reg(SpmvArgs a,
+                                                                                      const Real *__restrict__ x,
+                                                                                      Real *__restrict__ y) {
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
         emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
@@ -1348,6 +1349,8 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
         SPMVC_REG_W(KK, TL, 1)   \
     } else if (rpt == 2) {       \
         SPMVC_REG_W(KK, TL, 2)   \
+    } else if (rpt == 3) {       \
+        SPMVC_REG_W(KK, TL, 3)   \
     } else if (rpt == 4) {       \
         SPMVC_REG_W(KK, TL, 4)   \
     } else {                     \
@@ -1451,7 +1454,7 @@ bool launch_pairs(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, 
     if (nrhs % 2 || ldx % 2 || ldy % 2 || reinterpret_cast<uintptr_t>(X) % 16 || reinterpret_cast<uintptr_t>(Y) % 16)
         return false;
     const int rpt = p.rows / kBlock;
-    if (rpt > 4) return false;
+    if (rpt != 1 && rpt != 2 && rpt != 4) return false;  // instances for 1, 2 and 4 rows per thread
     a.rows = p.rows;
     a.n_win = p.n_win;
     for (int w = 0; w < p.n_win; ++w) {
@@ -1674,7 +1677,7 @@ static uint16_t reg_row_head(const spmvc_matrix_s *M, int q) {
 // that the grid about fills the device once.
 static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<std::pair<int64_t, int64_t>> &win,
                       const int64_t *lo, const int64_t *len, int rows) {
-    if (!p.reg || p.n_win < 2) return;
+    if (!p.reg || p.n_win < 2 || !(rows == 256 || rows == 512 || rows == 1024)) return;
     const int NW = p.n_win, NB = NW + 1;
     const int64_t S = lo[1] - lo[0];
     if (S <= 0 || S % 4 != 0) return;
@@ -1846,7 +1849,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     if (bmask) {
         // the element offset of every displacement; no pattern tables.  The
         // kernel takes 1, 2 or 4 rows per thread.
-        if (rows > 4 * kBlock) return;
+        if (rows != kBlock && rows != 2 * kBlock && rows != 4 * kBlock) return;
         for (int k = 0; k < 64; ++k) p.bm_off[k] = 0;
         for (int k = 0; k < M->bm_nd; ++k) p.bm_off[k] = static_cast<int32_t>(lds_index(M->h_bm_d[k]));
         for (size_t w = 0; w < win.size(); ++w) {
@@ -1894,7 +1897,7 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     }
     const int64_t x_elems = total + rows;  // windows + zero window
     const int64_t x_bytes64 = ((x_elems * 8) + 15) & ~int64_t(15);
-    const bool rows_ok = rows == 256 || rows == 512 || rows == 1024 || rows == 2048;
+    const bool rows_ok = rows == 256 || rows == 512 || rows == 768 || rows == 1024 || rows == 2048;
     if (rows_ok && W <= kRegW && x_bytes64 <= kLdsBudgetBytes && x_elems * 8 <= 65535) {
         const int64_t reg_tab_bytes = static_cast<int64_t>(M->P) * kRegTw * 2;
         p.zero_base = static_cast<int32_t>(total);
@@ -1919,8 +1922,9 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         p.reg_tab_in_lds = reg_tab_bytes <= 16 * 1024 && x_bytes64 + reg_tab_bytes <= kLdsBudgetBytes;
         p.reg = true;
         // the same windows as 16-byte elements (pairs of FP64 right-hand sides)
-        const int64_t x_bytes128 = x_elems * 16;
-        if (x_bytes128 + reg_tab_bytes <= kLdsBudgetBytes && x_elems * 16 <= 65535 && M->K >= 1) {
+        const int64_t x_elems128 = total + rows;  // windows + zero window
+        const int64_t x_bytes128 = x_elems128 * 16;
+        if (x_bytes128 + reg_tab_bytes <= kLdsBudgetBytes && x_elems128 * 16 <= 65535 && M->K >= 1) {
             std::vector<uint16_t> rt(static_cast<size_t>(M->P) * kRegTw, 0);
             for (int q = 0; q < M->P; ++q) {
                 const int L = M->h_pat_len[q];

@@ -107,7 +107,7 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         }
         std::vector<Cand> cands;
         if (A->fmt == SPMVC_FMT_DIT && nrhs == 1) {
-            for (int rows : {256, 512, 1024, 2048, 4096}) cands.push_back({rows, 1});
+            for (int rows : {256, 512, 768, 1024, 2048, 4096}) cands.push_back({rows, 1});
             for (int rows : {256, 512, 1024}) cands.push_back({rows, 2});
             cands.push_back({A->rows_per_block[dt], 0});
         } else if (A->fmt == SPMVC_FMT_BMASK && nrhs == 1) {

@@ -97,7 +97,7 @@ def test_stencil104_full_size_parity(fmt):
     assert roundtrip_ok(M, A)
 
 
-@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (1024, 1), (2048, 1), (4096, 1), (1024, 0),
+@pytest.mark.parametrize("rows,lds", [(256, 1), (512, 1), (768, 1), (1024, 1), (2048, 1), (4096, 1), (1024, 0),
                                       (256, 2), (512, 2), (1024, 2)])
 def test_dit_kernel_configs_agree(rows, lds):
     say("case: DIT config", rows, lds)
@@ -207,7 +207,8 @@ def test_fp32_full_size_every_configuration(grid):
     scale = oracle.spmv(absA, np.abs(x64))
     M = compress(A, fmt="DIT")
     xt = torch.from_numpy(x32).cuda()
-    for rows, lds in [(256, 1), (512, 1), (1024, 1), (256, 2), (512, 2), (1024, 2), (512, 0), (None, None)]:
+    for rows, lds in [(256, 1), (512, 1), (768, 1), (1024, 1), (256, 2), (512, 2), (1024, 2), (512, 0),
+                      (None, None)]:
         if rows is None:
             M.tune(torch.float32)
         else:
