@@ -474,10 +474,23 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
 }
 
 // Sum of the tiles' partials of system s for rhs r (fixed order), in every thread.
-__device__ __forceinline__ double sys_sum(const Batch &b, const SysDesc &d, int r) {
-    double acc = 0.0;
-    for (int t = threadIdx.x; t < d.ntiles; t += kT) acc += b.part[(d.tile0 + t) * b.nrhs + r];
-    return block_sum(acc);
+// Sums of the system's tile partials for every right-hand side, in a fixed
+// order (out[r], valid in every thread).  A tile's partials of all right-hand
+// sides are adjacent, so each step issues all of them at once; one pass over
+// the tiles serves every right-hand side.
+__device__ __forceinline__ void sys_sums(const Batch &b, const SysDesc &d, double (&out)[16]) {
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    for (int t = threadIdx.x; t < d.ntiles; t += kT) {
+        const double *p = b.part + (d.tile0 + t) * b.nrhs;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (r < b.nrhs) acc[r] += p[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (r < b.nrhs) out[r] = block_sum(acc[r]);
 }
 
 // Element loop of a tile: f(global element index, rhs) for the tile's rows.
@@ -526,8 +539,10 @@ __global__ __launch_bounds__(kT) void k_bstart_fin(Batch b) {
     const int s = blockIdx.x;
     const SysDesc &d = b.sys[s];
     int active = 0;
+    double sums[16];
+    sys_sums(b, d, sums);
     for (int r = 0; r < b.nrhs; ++r) {
-        const double rr = sys_sum(b, d, r);
+        const double rr = sums[r];
         if (threadIdx.x == 0) {
             const int q = s * b.nrhs + r;
             b.rho[q] = rr;
@@ -559,8 +574,10 @@ __global__ __launch_bounds__(kT) void k_bfin_alpha(Batch b) {
     }
     const SysDesc &d = b.sys[s];
     int any = 0;
+    double sums[16];
+    sys_sums(b, d, sums);
     for (int r = 0; r < b.nrhs; ++r) {
-        const double sigma = sys_sum(b, d, r);
+        const double sigma = sums[r];
         if (threadIdx.x == 0) {
             const int q = s * b.nrhs + r;
             b.step[q] = 0;
@@ -614,8 +631,10 @@ __global__ __launch_bounds__(kT) void k_bfin_beta(Batch b) {
     const SysDesc &d = b.sys[s];
     const int np = b.n_sys * b.nrhs;
     int still = 0;
+    double sums[16];
+    sys_sums(b, d, sums);
     for (int r = 0; r < b.nrhs; ++r) {
-        const double rho_new = sys_sum(b, d, r);
+        const double rho_new = sums[r];
         if (threadIdx.x == 0) {
             const int q = s * b.nrhs + r;
             if (b.done[q]) continue;
@@ -691,8 +710,10 @@ template <int LPR> __global__ __launch_bounds__(kT) void k_bresid(Batch b) {
 __global__ __launch_bounds__(kT) void k_bresid_fin(Batch b, double *out) {
     const int s = blockIdx.x;
     const SysDesc &d = b.sys[s];
+    double sums[16];
+    sys_sums(b, d, sums);
     for (int r = 0; r < b.nrhs; ++r) {
-        const double rr = sys_sum(b, d, r);
+        const double rr = sums[r];
         if (threadIdx.x == 0) out[s * b.nrhs + r] = rr;
     }
 }

@@ -67,10 +67,21 @@ template <int NT> __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-// Sum of partials[0..np) in a fixed order; identical in every block.
+// Sum of partials[0..np) in a fixed order; identical in every block.  Each
+// thread loads eight of its partials at a time (independent loads in flight)
+// before adding them in order: an SpMV leaves thousands of partials, and one
+// dependent load per partial would make this sum a chain of cache round trips.
 template <int NT> __device__ __forceinline__ double sum_partials(const double *partials, int np) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += NT) s += partials[i];
+    int i = threadIdx.x;
+    for (; i + 7 * NT < np; i += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partials[i + u * NT];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < np; i += NT) s += partials[i];
     return block_sum<NT>(s);
 }
 
@@ -531,8 +542,8 @@ __global__ void k_zero_scal(CgScal *st) {
 }
 
 struct Pinned {
-    CgScal *h = nullptr;
-    Pinned() { SPMVC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(CgScal), hipHostMallocDefault)); }
+    CgScal *h = nullptr;  // three host copies: the synchronous read and the two pipelined slots
+    Pinned() { SPMVC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), 3 * sizeof(CgScal), hipHostMallocDefault)); }
     ~Pinned() {
         if (h) (void)hipHostFree(h);
     }
@@ -551,14 +562,22 @@ struct Solver {
     DevBuf scal, part_a, part_b, part_sig;
     std::unique_ptr<Pinned> pin;
     CgScal h_pageable{};
+    hipEvent_t ev[2] = {nullptr, nullptr};  // pipelined status reads (owned solvers only)
     Solver(hipStream_t st, int64_t sig_blocks) : s(st) {
         scal.alloc(sizeof(CgScal));
         part_a.alloc(sizeof(double) * kRMaxBlocks);
         part_b.alloc(sizeof(double) * kRMaxBlocks);
         part_sig.alloc(sizeof(double) * std::max<int64_t>(sig_blocks, 1));
         pin.reset(new Pinned());
+        for (hipEvent_t &e : ev) SPMVC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         bind(scal.as<CgScal>(), part_a.as<double>(), part_b.as<double>(), part_sig.as<double>(), pin->h);
     }
+    ~Solver() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    Solver(const Solver &) = delete;
+    Solver &operator=(const Solver &) = delete;
     // region: kSolverScalBytes of scalars, then 2 * kRMaxBlocks partials, then the SpMV partials
     Solver(hipStream_t st, char *region) : s(st) {
         double *parts = reinterpret_cast<double *>(region + kSolverScalBytes);
@@ -580,6 +599,32 @@ struct Solver {
         SPMVC_HIP(hipStreamSynchronize(s));
         return *h;
     }
+    // Enqueues chunks of iterations (launch_chunk() returns false when there
+    // is nothing left to enqueue) until the solve reports done.  The host reads
+    // the scalars after chunk k while chunk k + 1 is already queued, so the
+    // device does not idle during the read; a chunk queued after the solve
+    // finished runs as no-ops (every kernel of an iteration returns at once
+    // when `done` is set).  Without events (the allocation-free solver) each
+    // read waits for the stream.
+    template <class F> void iterate_chunks(F &&launch_chunk) {
+        if (!ev[0]) {
+            while (!read().done && launch_chunk()) {
+            }
+            return;
+        }
+        auto post = [&](int slot) {
+            SPMVC_HIP(hipMemcpyAsync(pin->h + 1 + slot, dscal, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+            SPMVC_HIP(hipEventRecord(ev[slot], s));
+        };
+        if (!launch_chunk()) return;
+        post(0);
+        for (int slot = 0;; slot ^= 1) {
+            const bool more = launch_chunk();
+            if (more) post(slot ^ 1);
+            SPMVC_HIP(hipEventSynchronize(ev[slot]));
+            if (pin->h[1 + slot].done || !more) return;
+        }
+    }
 };
 static_assert(sizeof(CgScal) <= Solver::kSolverScalBytes, "scalar block of the solver region");
 
@@ -595,8 +640,8 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
     const bool vec_u = aligned16(r, q), vec_p = aligned16(z, r, p);
     const int chunk = std::max(1, check_every);
     int it = it0;
-    while (it < max_iter) {
-        if (sv.read().done) break;
+    sv.iterate_chunks([&]() -> bool {
+        if (it >= max_iter) return false;
         for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
             const int par = it & 1;
             const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.psig);
@@ -614,7 +659,8 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
                                                            sv.st(), par, it);
         }
         SPMVC_CHECK_LAUNCH();
-    }
+        return true;
+    });
     CgScal out = sv.read();
     if (!out.done) {
         out.done = 1;
@@ -784,8 +830,8 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
         k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), it & 1);
         SPMVC_CHECK_LAUNCH();
         const int chunk = std::max(1, o.check_every);
-        while (it < o.max_iter) {
-            if (sv.read().done) break;
+        sv.iterate_chunks([&]() -> bool {
+            if (it >= o.max_iter) return false;
             for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
                 const int par = it & 1;
                 const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.psig);
@@ -797,7 +843,8 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
                 k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.pa, static_cast<int>(g), sv.st(), par);
             }
             SPMVC_CHECK_LAUNCH();
-        }
+            return true;
+        });
         CgScal h = sv.read();
         if (!h.done) {
             h.done = 1;
