@@ -313,7 +313,9 @@ typedef struct {
                               3 DIT register, plane-marching, 4 BMASK with LDS windows */
     int32_t kernel_f32;    /* the same for FP32 (each dtype has its own configuration)   */
     int32_t rows_per_block_f32;
-    int32_t pad_;
+    int32_t block_split;   /* window-phased block SpMV (spmv_block mode 3): 1 when every pattern's
+                              rows share their V[0]/V[1] split, so each window's entries are
+                              summed per value run and scaled once; 0 = a weight per entry */
 } spmvc_info;
 
 spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info /* host */);

@@ -76,7 +76,7 @@ class Info(ctypes.Structure):
                 ("bytes_ell", ctypes.c_int64), ("bytes_paper", ctypes.c_int64),
                 ("lds_windows", ctypes.c_int32), ("rows_per_block", ctypes.c_int32),
                 ("V", ctypes.c_double * 15), ("kernel", ctypes.c_int32), ("kernel_f32", ctypes.c_int32),
-                ("rows_per_block_f32", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("rows_per_block_f32", ctypes.c_int32), ("block_split", ctypes.c_int32)]
 
 
 _lib = None

@@ -407,6 +407,7 @@ spmvc_status spmv_info(spmvc_matrix A, spmvc_info *info) {
         r.kernel = kernel_kind(A, SPMVC_F64);
         r.kernel_f32 = kernel_kind(A, SPMVC_F32);
         r.rows_per_block_f32 = planned ? A->plan[SPMVC_F32].rows : kBlock;
+        r.block_split = A->plan[SPMVC_F64].bw && A->plan[SPMVC_F64].bw_split ? 1 : 0;
         *info = r;
         return SPMVC_OK;
     });

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "lds_window.h"
 
 namespace spmvc {
 namespace {
@@ -57,7 +58,7 @@ struct SysDesc {
     double V[2];
     // window-phased SpMV: the system's x windows for 256-row tiles and its
     // per-(pattern, window) entry lists (see the FP64 plan of the handle)
-    int32_t bw_nw;
+    int32_t bw_nw, bw_split;  // bw_split: records split into value runs
     int64_t bw_lo[kMaxWindows];
     int32_t bw_len[kMaxWindows];
     const uint32_t *bw_tab;
@@ -312,18 +313,6 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
     }
 }
 
-// One 16-byte direct global-to-LDS load per lane: the wavefront's 64 chunks
-// land contiguously at lds (a wavefront-uniform address).  The builtin exists
-// only for the GPU target; the host compilation pass sees an empty body.
-__device__ __forceinline__ void lds_load16(const void *g, void *lds) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
-#else
-    (void)g;
-    (void)lds;
-#endif
-}
-
 // Four entries of a row's (pattern, window) record against the x window: four
 // 16-byte x reads in flight, then four weighted FMAs (value V[0] for
 // canonical index < t0, else V[1]).
@@ -415,6 +404,11 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
             if (r0 + rel >= d.n || idv[ps] == esc) continue;
             const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
             const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
+            if (d.bw_split) {
+                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, v0, v1, acc[ps][0],
+                                      acc[ps][1]);
+                continue;
+            }
             const int cnt = static_cast<int>(rec[0].x);
             int k0 = 0;
             for (; k0 + 4 <= cnt; k0 += 4)
@@ -949,6 +943,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
         d.V[1] = M->V[1];
         const LdsPlan &pl = M->plan[SPMVC_F64];
         d.bw_nw = pl.bw ? pl.bw_nw : 0;
+        d.bw_split = pl.bw && pl.bw_split ? 1 : 0;
         for (int w = 0; w < kMaxWindows; ++w) {
             d.bw_lo[w] = pl.bw_lo[w];
             d.bw_len[w] = pl.bw_len[w];

@@ -107,6 +107,7 @@ struct LdsPlan {
     // a kWinSt-word record: the count and the entries
     // ((canonical index << 16) | element in window)
     bool bw = false;
+    bool bw_split = false;        // records split into value runs (see build_block_window_plan)
     int32_t bw_nw = 0, bw_maxlen = 0;
     int64_t bw_lo[kMaxWindows] = {};
     int32_t bw_len[kMaxWindows] = {};
@@ -160,6 +161,10 @@ struct spmvc_matrix_s {
     std::vector<int32_t> h_pat_off; // [P][width]
     std::vector<uint8_t> h_pat_len; // [P]
     std::vector<uint8_t> h_pat_T;   // [P][K], DITV only
+    // per pattern, the T_i[0] every row using it shares, or -1 when its rows
+    // differ (DIT with two table values; computed on first use)
+    std::vector<int32_t> h_pat_t0;
+    bool pat_t0_ready = false;
     // kernel configuration
     int32_t rows_per_block[2] = {512, 512};  // per dtype (index SPMVC_F64 / SPMVC_F32)
     int32_t lds_mode[2] = {1, 1};          // per dtype: 1 = stage in LDS when a plan fits,

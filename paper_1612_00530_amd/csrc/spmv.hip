@@ -43,6 +43,7 @@
 #include <set>
 
 #include "internal.h"
+#include "lds_window.h"
 
 namespace spmvc {
 namespace {
@@ -80,6 +81,7 @@ struct SpmvArgs {
     int32_t lds_x_bytes;           // bytes of windows + zero window (16-byte multiple)
     int32_t n_xcd;                 // XCDs the blocks are spread over (tile mapping)
     int32_t async_lds;             // x is 16-byte aligned: stage windows with direct LDS loads
+    int32_t bw_split;              // window-phased block SpMV: records split into value runs
     // plane-marching kernel (k_dit_march)
     int64_t m_S;                   // row distance between consecutive windows (one plane)
     int64_t m_nz;                  // planes: ceil(n_rows / m_S)
@@ -290,18 +292,6 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
 // register path with clamped indices (a window slot outside [0, n_cols) is
 // never read by a stored entry).  Window starts and lengths are multiples of
 // four elements, so each 16-byte chunk lies wholly inside its window.
-// One 16-byte direct global-to-LDS load per lane: the wavefront's 64 chunks
-// land contiguously at lds (a wavefront-uniform address).  The builtin exists
-// only for the GPU target; the host compilation pass sees an empty body.
-__device__ __forceinline__ void lds_load16(const void *g, void *lds) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
-#else
-    (void)g;
-    (void)lds;
-#endif
-}
-
 // Issues the copies of the block's x windows for rows [r0, r0 + rows) into xs.
 // Direct loads are left in flight (the caller waits for them); the register
 // path (edge windows, unaligned x) has completed its LDS stores on return.
@@ -1144,8 +1134,11 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
             const int64_t row = r0 + rel;
             if (row >= a.n_rows || idv[ps] == esc) continue;
             const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
-            win_row<NR * 8>(rec, reinterpret_cast<const unsigned char *>(xs + rel * NR + rp), t0v[ps], v0, v1,
-                            acc[ps][0], acc[ps][1]);
+            const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
+            if (a.bw_split)
+                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, v0, v1, acc[ps][0], acc[ps][1]);
+            else
+                win_row<NR * 8>(rec, xrow, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
         }
     }
 #pragma unroll
@@ -1422,6 +1415,7 @@ bool launch_block_win(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
         a.win_len[w] = p.bw_len[w];
     }
     a.async_lds = 1;
+    a.bw_split = p.bw_split ? 1 : 0;
     a.lds_x_bytes = static_cast<int32_t>(xb);
     a.reg_tab = reinterpret_cast<const uint16_t *>(p.bw_tab.p);
     const size_t shmem = static_cast<size_t>(xb + tb);
@@ -1741,6 +1735,53 @@ static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<st
 // (canonical index << 16 | element offset in the window).  Applies to DIT
 // matrices with a value table of 1 or 2 entries and no raw values, when no
 // pattern has more than kWinMaxPw entries in one window.
+// T_i[0] of every row using pattern q, when they all agree (DIT with two
+// table values): the range over the rows, taken once per handle.
+__global__ void k_pattern_t0_range(int64_t n_rows, const void *ids, int id_bytes, const uint8_t *T, int *tmin,
+                                   int *tmax) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_rows) return;
+    const uint32_t id = load_id(ids, id_bytes, i);
+    const uint32_t esc = id_bytes == 1 ? 0xFFu : (id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
+    if (id == esc) return;
+    const int t = T[i];
+    atomicMin(&tmin[id], t);
+    atomicMax(&tmax[id], t);
+}
+
+static void pattern_t0(spmvc_matrix_s *M) {
+    if (M->pat_t0_ready) return;
+    M->h_pat_t0.assign(static_cast<size_t>(M->P), -1);
+    if (M->fold) {
+        for (int q = 0; q < M->P; ++q) M->h_pat_t0[q] = M->h_pat_T[static_cast<size_t>(q) * M->K];
+    } else if (M->P > 0 && M->n_rows > 0) {
+        DevBuf tmin, tmax;
+        tmin.alloc(sizeof(int) * M->P);
+        tmax.alloc(sizeof(int) * M->P);
+        std::vector<int> hmin(M->P, 1 << 30), hmax(M->P, -1);
+        SPMVC_HIP(hipMemcpy(tmin.p, hmin.data(), tmin.bytes, hipMemcpyHostToDevice));
+        SPMVC_HIP(hipMemcpy(tmax.p, hmax.data(), tmax.bytes, hipMemcpyHostToDevice));
+        k_pattern_t0_range<<<grid_for(M->n_rows, kBlock), kBlock>>>(M->n_rows, M->ids.p, M->id_bytes,
+                                                                   M->T.as<uint8_t>(), tmin.as<int>(), tmax.as<int>());
+        SPMVC_CHECK_LAUNCH();
+        SPMVC_HIP(hipMemcpy(hmin.data(), tmin.p, tmin.bytes, hipMemcpyDeviceToHost));
+        SPMVC_HIP(hipMemcpy(hmax.data(), tmax.p, tmax.bytes, hipMemcpyDeviceToHost));
+        for (int q = 0; q < M->P; ++q) M->h_pat_t0[q] = hmin[q] == hmax[q] ? hmin[q] : -1;
+    }
+    M->pat_t0_ready = true;
+}
+
+// Plan of the window-phased block SpMV (k_dit_block_win, and per system the
+// batched k_bspmv_win): windows for kWinRows-row tiles and, per (pattern,
+// window), a record of the entries of the pattern in that window.  When every
+// row of each pattern shares its split between the V[0] and V[1] runs (one
+// table value; DITV, whose T is the pattern's; DIT where the rows agree, as
+// on a stencil), the record is split into the two runs (word 0: V[0] count,
+// word 1: V[1] count, word 2: slot where the V[1] run starts, 4-aligned;
+// entries are window element indices) and the kernels sum each run and scale
+// it once.  Otherwise the record lists the entries in canonical order (word
+// 0: count; entries (canonical index << 16) | window element) and each entry
+// takes its weight by comparing its index with the row's T_i[0].
 static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p, const std::set<int64_t> &ds) {
     if (!(M->K == 1 || M->K == 2) || M->raw_elems > 0 || ds.empty()) return;
     // windows for kWinRows-row tiles: clusters closer than a tile merge
@@ -1763,18 +1804,60 @@ static void build_block_window_plan(spmvc_matrix_s *M, LdsPlan &p, const std::se
     }
     const int W = M->width;
     const int stride = kWinSt;
+    auto window_of = [&](int64_t d) {
+        int w = 0;
+        while (!(d >= win[w].first && d <= win[w].second)) ++w;
+        return w;
+    };
     std::vector<uint32_t> tab(static_cast<size_t>(M->P) * NW * stride, 0);
     for (int q = 0; q < M->P; ++q) {
         const int L = M->h_pat_len[q];
         for (int k = 0; k < L; ++k) {
             const int64_t d = M->h_pat_off[static_cast<size_t>(q) * W + k];
-            int w = 0;
-            while (!(d >= win[w].first && d <= win[w].second)) ++w;
+            const int w = window_of(d);
             uint32_t *t = tab.data() + (static_cast<size_t>(q) * NW + w) * stride;
             if (t[0] >= static_cast<uint32_t>(kWinMaxPw)) return;  // too many entries in one window
             t[4 + t[0]] = (static_cast<uint32_t>(k) << 16) | static_cast<uint32_t>(d - lo[w]);
             ++t[0];
         }
+    }
+    // the split form, where every pattern's rows share T_i[0] and the two
+    // runs fit a record with the V[1] run moved to a 4-aligned slot
+    p.bw_split = false;
+    if (M->K == 2) pattern_t0(M);
+    bool split = true;
+    for (int q = 0; q < M->P && split; ++q) split = M->K == 1 || M->h_pat_t0[q] >= 0;
+    std::vector<uint32_t> stab(static_cast<size_t>(M->P) * NW * stride, 0);
+    for (int q = 0; q < M->P && split; ++q) {
+        const int L = M->h_pat_len[q];
+        const int t0 = M->K == 1 ? L : M->h_pat_t0[q];
+        for (int w = 0; w < NW && split; ++w) {
+            const uint32_t *g = tab.data() + (static_cast<size_t>(q) * NW + w) * stride;
+            uint32_t *t = stab.data() + (static_cast<size_t>(q) * NW + w) * stride;
+            uint32_t c0 = 0, c1 = 0;
+            for (uint32_t e = 0; e < g[0]; ++e)
+                ((static_cast<int>(g[4 + e] >> 16) < t0) ? c0 : c1) += 1;
+            const uint32_t o1 = (c0 + 3) / 4 * 4;
+            if (o1 + c1 > static_cast<uint32_t>(kWinMaxPw)) {
+                split = false;
+                break;
+            }
+            t[0] = c0;
+            t[1] = c1;
+            t[2] = o1;
+            uint32_t j0 = 0, j1 = 0;
+            for (uint32_t e = 0; e < g[0]; ++e) {
+                const uint32_t elem = g[4 + e] & 0xFFFFu;
+                if (static_cast<int>(g[4 + e] >> 16) < t0)
+                    t[4 + j0++] = elem;
+                else
+                    t[4 + o1 + j1++] = elem;
+            }
+        }
+    }
+    if (split) {
+        tab.swap(stab);
+        p.bw_split = true;
     }
     p.bw_tab.alloc(sizeof(uint32_t) * tab.size());
     SPMVC_HIP(hipMemcpy(p.bw_tab.p, tab.data(), p.bw_tab.bytes, hipMemcpyHostToDevice));
