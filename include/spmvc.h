@@ -430,6 +430,27 @@ spmvc_status spmv_symgs(spmvc_matrix A, const double *b, double *x, int32_t swee
 spmvc_status spmv_colors(spmvc_matrix A, int32_t *n_colors, int32_t *color, void *stream);
 
 /*
+ * The matrix in the color order of its SymGS coloring: B = P A P^T, where P
+ * lists the rows color by color (colors ascending, each color's rows
+ * ascending), so that each color is one contiguous range of B's rows.  B is a
+ * new handle (release with spmv_free), compressed with A's options; its
+ * coloring is the one induced from A's (spmv_colors on B gives color c to rows
+ * n_0 + ... + n_{c-1} .. n_0 + ... + n_c - 1), not a coloring of B's own, so
+ * spmv_symgs on B with b' = b[perm], x' = x[perm] performs the same updates as
+ * on A and returns x' = x[perm] (up to the order of each row's sum).  With
+ * every color contiguous, a sweep's color steps read b and write x with
+ * coalesced accesses.  perm: device int32 [n], caller-owned output (may be NULL):
+ * perm[k] = the row of A that is row k of B.  A must be square with a non-zero
+ * diagonal in every row (SPMVC_EINVAL); SPMVC_EUNSUPPORTED when B cannot be
+ * compressed in A's format (e.g. BMASK with more than 64 displacements after
+ * the reordering).  Blocking.  (On the 27-point stencil the sweep gains little
+ * from the contiguous colors -- each color step is bound by its chain of
+ * dependent loads -- while B's SpMV loses the few dense x windows of A's
+ * natural order, so cg_solve keeps A's order.)
+ */
+spmvc_status spmv_color_order(spmvc_matrix A, spmvc_matrix *B, int32_t *perm, void *stream);
+
+/*
  * Device memory of the library (handle arrays, solver vectors, scratch):
  * from now on allocated with alloc_fn(bytes, stream, ctx) and released with
  * free_fn(ptr, stream, ctx) -- e.g. a framework's caching allocator -- instead

@@ -34,6 +34,7 @@ ARR = {
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_noalloc", "cg_solve_mg", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
+    "spmv_color_order",
     "spmvc_batched_config", "spmvc_set_allocator", "spmv_rcm", "spmv_permute", "spmv_free", "spmvc_status_string",
     "spmvc_last_error",
 ]
@@ -114,6 +115,7 @@ def load(path: str = LIB_PATH):
                               ctypes.POINTER(ctypes.c_double)]
     lib.spmv_symgs.argtypes = [P, P, P, i32, P]
     lib.spmv_colors.argtypes = [P, ctypes.POINTER(i32), P, P]
+    lib.spmv_color_order.argtypes = [P, ctypes.POINTER(P), P, P]
     lib.spmvc_batched_config.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.spmvc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
     lib.spmv_free.argtypes = [P]
@@ -254,6 +256,17 @@ class Matrix:
         col = torch.empty(max(self.n_rows, 1), dtype=torch.int32, device="cuda")
         _check(load().spmv_colors(self._h, ctypes.byref(nc), ctypes.c_void_p(col.data_ptr()), _stream()))
         return nc.value, col[: self.n_rows]
+
+    def color_order(self):
+        """(B, perm): B = P A P^T with the rows of each SymGS color contiguous (a new
+        Matrix; its coloring is the one induced from this matrix's), perm an int32
+        CUDA tensor with perm[k] = the row of this matrix that is row k of B."""
+        import torch
+
+        perm = torch.empty(max(self.n_rows, 1), dtype=torch.int32, device="cuda")
+        h = ctypes.c_void_p()
+        _check(load().spmv_color_order(self._h, ctypes.byref(h), ctypes.c_void_p(perm.data_ptr()), _stream()))
+        return Matrix(h, self.n_rows, self.n_cols, self.nnz), perm[: self.n_rows]
 
     def decompress(self):
         import torch

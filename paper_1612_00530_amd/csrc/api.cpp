@@ -63,7 +63,9 @@ int cu_count() {
     return n;
 }
 
-void default_plan(spmvc_matrix_s *M) {
+}  // namespace
+
+void prepare_handle(spmvc_matrix_s *M) {
     M->n_xcd = xcd_count();
     M->n_cu = cu_count();
     if (M->fmt != SPMVC_FMT_DIT && M->fmt != SPMVC_FMT_BMASK) return;
@@ -78,7 +80,6 @@ void default_plan(spmvc_matrix_s *M) {
     }
 }
 
-}  // namespace
 }  // namespace spmvc
 
 using namespace spmvc;
@@ -174,7 +175,7 @@ spmvc_status spmv_compress(int64_t n_rows, int64_t n_cols, int64_t nnz, const in
                     M = E;
                 }
             }
-            default_plan(M);
+            prepare_handle(M);
         } catch (...) {
             delete M;
             throw;
@@ -471,6 +472,16 @@ spmvc_status spmv_set_config(spmvc_matrix A, int32_t rows_per_block, int32_t lds
                 build_lds_plan(A, dt, rows_per_block);
             }
         }
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmv_color_order(spmvc_matrix A, spmvc_matrix *B, int32_t *perm, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!A || !B) return fail(SPMVC_EINVAL, "null argument");
+        *B = nullptr;
+        if (A->n_rows != A->n_cols) return fail(SPMVC_EINVAL, "the color order needs a square matrix");
+        *B = color_order_copy(A, perm, static_cast<hipStream_t>(stream));
         return SPMVC_OK;
     });
 }

@@ -832,6 +832,7 @@ void compress(spmvc_matrix_s *M, const int64_t *rp, const int32_t *col, const do
     const int64_t n_pad = M->n_pad;
     // DITV is DIT whose pattern key also holds T_i; the row's T is dropped at the end
     spmvc_compress_opts o = o_in;
+    M->copts = o_in;
     M->fold = o.fmt == SPMVC_FMT_DITV ? 1 : 0;
     if (M->fold) o.fmt = SPMVC_FMT_DIT;
     M->fmt = o.fmt;

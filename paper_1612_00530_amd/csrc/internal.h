@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -175,8 +176,12 @@ struct spmvc_matrix_s {
                                            // of right-hand-side pairs in LDS (3 and 2 where they
                                            // apply, else 1); 1 = a lane group per row; 0 = one lane
                                            // per row (all rhs)
+    spmvc_compress_opts copts{};          // the options the handle was compressed with
     // multicolor Gauss-Seidel (symgs.hip): greedy coloring, built on first use
     int32_t gs_ready = 0, gs_n_colors = 0;
+    int32_t gs_contig = 0;                // the rows of each color are one contiguous range
+                                          // (a color-ordered twin): no row lists
+
     std::vector<int64_t> gs_off;          // rows of color c: gs_rows[gs_off[c] .. gs_off[c+1])
     spmvc::DevBuf gs_rows, gs_color;      // int32 [n]: rows by color (ascending); color of each row
     spmvc::DevBuf gs_meta;                // DIT: uint32 [n] per entry of gs_rows: (T_i[0] << 24) | pattern ID
@@ -186,6 +191,9 @@ struct spmvc_matrix_s {
 };
 
 namespace spmvc {
+
+// api.cpp: kernel plans and device properties of a freshly compressed handle
+void prepare_handle(spmvc_matrix_s *M);
 
 // compress.hip
 void compress(spmvc_matrix_s *M, const int64_t *row_ptr, const int32_t *col, const double *val,
@@ -236,6 +244,13 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
 
 // symgs.hip
 void build_coloring(spmvc_matrix_s *M, hipStream_t s);  // blocking; throws Error on a bad matrix
+// A new handle (owned by the caller, blocking) holding B = P A P^T, P listing
+// M's rows color by color (each color's rows ascending: M->gs_rows),
+// compressed with M's options, with the coloring induced from M's (color c =
+// rows gs_off[c] .. gs_off[c+1] of B): a sweep on B computes the same updates
+// as a sweep on M, in its own numbering.  perm (device int32 [n], may be
+// null) receives P's row list.
+spmvc_matrix_s *color_order_copy(spmvc_matrix_s *M, int32_t *perm, hipStream_t s);
 // `skip` (device int, may be null): when *skip != 0 the sweep's kernels return at once.
 void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s,
                   const int *skip = nullptr, bool reverse = false);

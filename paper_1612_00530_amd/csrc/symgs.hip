@@ -136,13 +136,15 @@ __device__ inline int64_t xcd_block() {
     return static_cast<int64_t>(xcd) * q + (xcd < r ? xcd : r) + slot;
 }
 
-// The rows rows[0..n) of one color: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.
-__global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int32_t *__restrict__ rows, int64_t n,
-                                                            const double *__restrict__ b, double *x, const int *skip) {
+// The rows rows[0..n) of one color -- or, for a color-ordered matrix (rows
+// null), the contiguous rows r0 .. r0 + n: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.
+__global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int32_t *__restrict__ rows, int64_t r0,
+                                                            int64_t n, const double *__restrict__ b, double *x,
+                                                            const int *skip) {
     if (skip && *skip) return;
     const int64_t t = xcd_block() * kGsThreads + threadIdx.x;
     if (t >= n) return;
-    const int64_t i = rows[t];
+    const int64_t i = rows ? rows[t] : r0 + t;
     double s = 0.0, d = 0.0;
     gs_visit(a, i, [&](double v, int64_t j) {
         if (j == i)
@@ -159,13 +161,13 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int3
 // the row's length read x_i and take weight 0), then the FMAs.  The generic
 // loop above waits for each pattern offset and each gather in turn.
 template <int MAXW>
-__global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows,
+__global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows, int64_t r0,
                                                           const uint32_t *__restrict__ meta, int64_t n,
                                                           const double *__restrict__ b, double *x, const int *skip) {
     if (skip && *skip) return;
     const int64_t t = xcd_block() * kGsThreads + threadIdx.x;
     if (t >= n) return;
-    const int64_t i = rows[t];
+    const int64_t i = rows ? rows[t] : r0 + t;
     // the row's pattern ID and T_i[0], stored in color order: read alongside
     // the row index rather than after it
     const uint32_t mw = meta[t];
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
 __global__ void k_gs_meta(GsArgs a, const int32_t *__restrict__ rows, int64_t n, uint32_t *meta) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kGsThreads + threadIdx.x;
     if (t >= n) return;
-    const int64_t i = rows[t];
+    const int64_t i = rows ? rows[t] : t;
     const uint32_t id = gs_id(a, i);
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     if (id == esc) {
@@ -341,7 +343,7 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
                   bool reverse) {
     const GsArgs a = gs_args(M);
     const int C = M->gs_n_colors;
-    const int32_t *rows = M->gs_rows.as<int32_t>();
+    const int32_t *rows = M->gs_contig ? nullptr : M->gs_rows.as<int32_t>();
     const bool dit27 = gs_dit27(M);
     int last = -1;  // color of the previous launch
     for (int sw = 0; sw < sweeps; ++sw)
@@ -356,12 +358,83 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
             const int64_t r0 = M->gs_off[c], cnt = M->gs_off[c + 1] - r0;
             if (cnt == 0) continue;
             const unsigned g = grid_for(cnt, kGsThreads, 0x7fffffff);
+            const int32_t *rc = rows ? rows + r0 : nullptr;
             if (dit27)
-                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rows + r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x, skip);
+                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rc, r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x, skip);
             else
-                k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rows + r0, cnt, b, x, skip);
+                k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rc, r0, cnt, b, x, skip);
             SPMVC_CHECK_LAUNCH();
         }
+}
+
+namespace {
+
+// color[i] for the rows of color c: the ranges gs_off[c] .. gs_off[c+1]
+__global__ void k_range_colors(const int64_t *off, int n_colors, int64_t n, int32_t *color) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    while (c + 1 < n_colors && off[c + 1] <= i) ++c;
+    color[i] = c;
+}
+
+// B = P A P^T with P = M's rows color by color, compressed with M's options,
+// its coloring the ranges of M's colors.
+std::unique_ptr<spmvc_matrix_s> make_color_twin(spmvc_matrix_s *M, hipStream_t s) {
+    build_coloring(M, s);
+    const int64_t n = M->n_rows, nnz = M->nnz;
+    DevBuf rp, col, val, prp, pcol, pval;
+    rp.alloc(sizeof(int64_t) * (n + 1));
+    col.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    val.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+    prp.alloc(sizeof(int64_t) * (n + 1));
+    pcol.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    pval.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+    decompress(M, rp.as<int64_t>(), col.as<int32_t>(), val.as<double>(), s);
+    permute_csr(n, rp.as<int64_t>(), col.as<int32_t>(), val.as<double>(), M->gs_rows.as<int32_t>(),
+                prp.as<int64_t>(), pcol.as<int32_t>(), pval.as<double>(), s);
+    rp.release();
+    col.release();
+    val.release();
+    std::unique_ptr<spmvc_matrix_s> T(new spmvc_matrix_s());
+    T->n_rows = n;
+    T->n_cols = n;
+    T->nnz = nnz;
+    compress(T.get(), prp.as<int64_t>(), pcol.as<int32_t>(), pval.as<double>(), M->copts, s);
+    prepare_handle(T.get());
+    // the induced coloring: color c is the contiguous range of M's color c
+    T->gs_off = M->gs_off;
+    T->gs_n_colors = M->gs_n_colors;
+    T->gs_contig = 1;
+    if (n > 0) {
+        DevBuf off;
+        off.alloc(sizeof(int64_t) * T->gs_off.size());
+        SPMVC_HIP(hipMemcpyAsync(off.p, T->gs_off.data(), off.bytes, hipMemcpyHostToDevice, s));
+        T->gs_color.alloc(sizeof(int32_t) * n);
+        k_range_colors<<<grid_for(n, kGsThreads, 0x7fffffff), kGsThreads, 0, s>>>(
+            off.as<int64_t>(), T->gs_n_colors, n, T->gs_color.as<int32_t>());
+        SPMVC_CHECK_LAUNCH();
+        if (gs_dit27(T.get())) {
+            T->gs_meta.alloc(sizeof(uint32_t) * n);
+            k_gs_meta<<<grid_for(n, kGsThreads, 0x7fffffff), kGsThreads, 0, s>>>(gs_args(T.get()), nullptr, n,
+                                                                                T->gs_meta.as<uint32_t>());
+            SPMVC_CHECK_LAUNCH();
+        }
+        SPMVC_HIP(hipStreamSynchronize(s));
+    }
+    T->gs_ready = 1;
+    return T;
+}
+
+}  // namespace
+
+spmvc_matrix_s *color_order_copy(spmvc_matrix_s *M, int32_t *perm, hipStream_t s) {
+    std::unique_ptr<spmvc_matrix_s> T = make_color_twin(M, s);
+    if (perm && M->n_rows > 0) {
+        SPMVC_HIP(hipMemcpyAsync(perm, M->gs_rows.p, sizeof(int32_t) * M->n_rows, hipMemcpyDeviceToDevice, s));
+        SPMVC_HIP(hipStreamSynchronize(s));
+    }
+    return T.release();
 }
 
 }  // namespace spmvc

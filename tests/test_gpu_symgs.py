@@ -123,3 +123,58 @@ def test_bad_inputs_are_rejected():
     M2 = compress(A, fmt="DIT")
     with pytest.raises(P.SpmvcError):
         M2.symgs(z, z.clone(), sweeps=-1)
+
+
+@pytest.mark.parametrize("fmt", FORMATS + ["BMASK"])
+@pytest.mark.parametrize("make", [lambda: stencil27(12, 10, 9), lambda: stencil27_irregular(10, 9, 8, seed=3)])
+def test_color_order(make, fmt):
+    """spmv_color_order: B = P A P^T with P the rows color by color -- the
+    oracle's greedy coloring sorted stably by color -- equal entry for entry
+    to the oracle's permutation of A; B's coloring is the induced one (color
+    ranges); sweeps on B with b[perm], x0[perm] give the oracle's sweep on A,
+    permuted."""
+    say("case: color order", fmt)
+    from oracle import reorder
+
+    torch = torch_mod()
+    P = lib()
+    A = make()
+    M = compress(A, fmt=fmt)
+    try:
+        B, perm = M.color_order()
+    except P.SpmvcError as e:  # BMASK: the reordered matrix has more than 64 displacements
+        assert fmt == "BMASK" and e.status == -8
+        return
+    color = gs.greedy_coloring(A)
+    ref_perm = np.argsort(color, kind="stable")
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(perm, ref_perm)
+    R = reorder.permute(A, perm)
+    rp, col, val = B.decompress()
+    assert np.array_equal(rp.cpu().numpy(), R.row_ptr) and np.array_equal(col.cpu().numpy(), R.col)
+    assert np.array_equal(val.cpu().numpy().view(np.uint64), np.asarray(R.val).view(np.uint64))
+    nc, bcol = B.colors()
+    assert nc == int(color.max()) + 1
+    assert np.array_equal(bcol.cpu().numpy().astype(np.int64), color[perm])
+    b = uniform_vector(A.n_rows, seed=5)
+    x0 = uniform_vector(A.n_rows, seed=6)
+    ref = gs.symgs(A, b, x0, color, sweeps=2)
+    got = run(B, b[perm], x0[perm], sweeps=2)
+    assert close(got, ref[perm], b, x0)
+
+
+def test_color_order_full_size_104():
+    """The 104^3 stencil's color-ordered twin: 8 colors of 140,608 rows, the
+    permutation of the parity coloring, and a sweep equal to the oracle's."""
+    say("case: color order 104^3")
+    A = stencil27(104, 104, 104)
+    M = compress(A, fmt="DIT")
+    B, perm = M.color_order()
+    color = parity_coloring(104, 104, 104)
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(perm, np.argsort(color, kind="stable"))
+    b = uniform_vector(A.n_rows, seed=7)
+    x0 = np.zeros(A.n_rows)
+    ref = gs.symgs(A, b, x0, color, sweeps=1)
+    got = run(B, b[perm], x0[perm], sweeps=1)
+    assert close(got, ref[perm], b)
