@@ -578,7 +578,8 @@ def run_batched(P, torch, dev, n_sys):
 
 
 def run_cg(g, P, torch, dev):
-    """CG to 1e-10 on the g^3 stencil with b = A*1: FP64 DIT, mixed-precision DIT, FP64 ELL."""
+    """CG to 1e-10 on the g^3 stencil with b = A*1: FP64 DIT, mixed precision DIT (iterative
+    refinement; reliable updates), FP64 ELL."""
     from synthetic import stencil27, stencil_hierarchy
 
     log(f"[bench] CG: generating {g}^3")
@@ -593,11 +594,12 @@ def run_cg(g, P, torch, dev):
     ones = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
     b = D.spmv(ones)
     res = {"grid": [g, g, g], "n": A.n_rows, "nnz": A.nnz, "rtol": 1e-10, "tuned": res_tune}
-    for name, M, mode in (("fp64_dit", D, 0), ("mixed_dit", D, 1), ("fp64_ell", E, 0)):
-        P.cg_solve(M, b, mode=mode, max_iter=20)  # warm-up of the code path
+    for name, M, mode, inner in (("fp64_dit", D, 0, 1e-5), ("mixed_dit", D, 1, 1e-5),
+                                 ("mixed_reliable_dit", D, 3, 1e-2), ("fp64_ell", E, 0, 1e-5)):
+        P.cg_solve(M, b, mode=mode, inner_rtol=inner, max_iter=20)  # warm-up of the code path
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, xs, stats = P.cg_solve(M, b, mode=mode, max_iter=5000)
+        st, xs, stats = P.cg_solve(M, b, mode=mode, inner_rtol=inner, max_iter=5000)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         err = float((xs[0] - 1.0).abs().max().item())
@@ -605,6 +607,8 @@ def run_cg(g, P, torch, dev):
                      "outer_iters": stats[0]["outer_iters"], "relres_true_fp64": stats[0]["relres_true"],
                      "max_abs_err_vs_ones": err}
         log(f"[bench] CG {name}: {t * 1000:.2f} ms, {stats[0]['iters']} iters, relres {stats[0]['relres_true']:.2e}")
+    for name in ("mixed_dit", "mixed_reliable_dit"):
+        res[name]["speedup_vs_fp64_dit"] = round(res["fp64_dit"]["seconds"] / res[name]["seconds"], 3)
     # preconditioned: one SymGS sweep (mode 2); one V-cycle over the grid hierarchy
     levels = [D] + [P.compress(*(torch.from_numpy(a).to(dev) for a in (m.row_ptr, m.col, m.val)),
                                n_cols=m.n_cols, fmt="DIT") for m in mats[1:]]

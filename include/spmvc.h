@@ -144,9 +144,11 @@ typedef struct {
     double rtol;         /* stop when ||r|| <= rtol * ||b||, default 1e-10                 */
     int32_t max_iter;    /* SpMV cap per (system, rhs) [FP64 mode; inner total in MIXED], 10000 */
     int32_t mode;        /* 0 = FP64 CG, 1 = mixed precision with iterative refinement,
-                            2 = FP64 CG preconditioned by one SymGS sweep                 */
-    double inner_rtol;   /* MIXED: inner FP32 solve tolerance relative to ||r||, 1e-5      */
-    int32_t max_outer;   /* MIXED: refinement steps cap, default 20                        */
+                            2 = FP64 CG preconditioned by one SymGS sweep,
+                            3 = mixed precision with reliable updates                     */
+    double inner_rtol;   /* MIXED: inner FP32 solve tolerance relative to ||r||, 1e-5;     */
+                         /* RELIABLE: fall of the recursive residual between replacements */
+    int32_t max_outer;   /* MIXED: refinement steps cap; RELIABLE: replacements cap; 20   */
     int32_t check_every; /* iterations between host convergence checks, default 16         */
     int32_t batched;     /* several systems or right-hand sides (FP64 mode): 0 = one solve  */
                          /* after another, 1 = all pairs advanced together by batched       */
@@ -158,8 +160,8 @@ typedef struct {
 
 /* Per (system, rhs) result (host struct). */
 typedef struct {
-    int32_t iters;           /* SpMVs inside the CG loop (MIXED: total FP32 inner iterations) */
-    int32_t outer_iters;     /* MIXED: refinement steps; FP64 mode: 0                      */
+    int32_t iters;           /* SpMVs inside the CG loop (MIXED, RELIABLE: FP32 iterations) */
+    int32_t outer_iters;     /* MIXED: refinement steps; RELIABLE: FP32 segments; else 0   */
     int32_t status;          /* spmvc_status of this solve                                 */
     int32_t pad_;
     double relres_true;      /* ||b - A x|| / ||b|| recomputed in FP64 at exit             */
@@ -178,6 +180,12 @@ typedef struct {
  * failing pair's status (SPMVC_ENOTSPD, SPMVC_ENOCONV).  Blocking.
  * mode 1 (MIXED): outer FP64 residual r = b - A x, inner FP32 CG on A d = r
  * with FP64 dot products, FP64 update x += d; requires nrhs == 1, n_sys == 1.
+ * mode 3 (RELIABLE): one CG run in FP32 (FP32 SpMV and vectors, FP64 dot
+ * products) whose residual is replaced by the FP64 b - A x, with the FP32
+ * update folded into the FP64 x, whenever the recursive residual has fallen
+ * by inner_rtol since the last replacement; the search direction is kept
+ * across replacements (reliable updates; the same stopping rule on the true
+ * FP64 residual); requires nrhs == 1, n_sys == 1.
  * mode 2 (PCG): FP64 CG preconditioned by one multicolor symmetric
  * Gauss-Seidel sweep (z = M^-1 r: the sweep of spmv_symgs on A z = r from
  * z = 0; the coloring is built on first use) -- the iteration of Table I with
@@ -466,6 +474,28 @@ spmvc_status spmv_color_order(spmvc_matrix A, spmvc_matrix *B, int32_t *perm, vo
  */
 spmvc_status spmvc_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
                                  void (*free_fn)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/*
+ * Debug aid.  A library built with -DSPMVC_CHECK (the package's build with
+ * check=True: libspmvc_check.so) bounds-checks every gathered column and
+ * every LDS index in its SpMV, block SpMV, batched and SymGS kernels; an
+ * index out of range is recorded and the access redirected in bounds, so a
+ * wrong index is reported here rather than read out of bounds.  *count
+ * (host): nonzero when a kernel met an index out of range since the last
+ * call (then reset; it counts the kernel sources that did, not the
+ * accesses); waits for the device first.  *checked (host): 1 in a checked
+ * build, else 0 (and *count is always 0).
+ */
+spmvc_status spmvc_check_violations(int64_t *count, int32_t *checked);
+
+/*
+ * Debug aid, checked builds only: one kernel passes the index i against the
+ * range [0, n) through the kernels' bounds check (and nothing else), so that
+ * a test can see that an index out of range is recorded and reported by
+ * spmvc_check_violations.  Blocking (on stream).  The release library
+ * returns SPMVC_EUNSUPPORTED.
+ */
+spmvc_status spmvc_check_probe(int64_t i, int64_t n, void *stream);
 
 void spmv_free(spmvc_matrix A);
 

@@ -18,7 +18,10 @@ __all__ = [
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libspmvc.so")
+# SPMVC_LIBRARY names another build of the library to load instead (the
+# bounds-checked libspmvc_check.so, for instance)
+LIB_PATH = os.environ.get("SPMVC_LIBRARY") or os.path.join(HERE, "libspmvc.so")
+CHECK_LIB_PATH = os.path.join(HERE, "libspmvc_check.so")
 
 FMT_ELL, FMT_DT, FMT_DIT, FMT_DITV, FMT_AUTO, FMT_BMASK = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
@@ -34,7 +37,7 @@ ARR = {
 EXPORTED = [
     "spmv_compress", "spmv", "spmv_block", "cg_solve", "cg_solve_noalloc", "cg_solve_mg", "spmv_decompress", "spmv_info",
     "spmv_get_array", "spmv_set_config", "spmv_set_block_mode", "spmv_tune", "spmv_symgs", "spmv_colors",
-    "spmv_color_order",
+    "spmv_color_order", "spmvc_check_violations", "spmvc_check_probe",
     "spmvc_batched_config", "spmvc_set_allocator", "spmv_rcm", "spmv_permute", "spmv_free", "spmvc_status_string",
     "spmvc_last_error",
 ]
@@ -116,6 +119,8 @@ def load(path: str = LIB_PATH):
     lib.spmv_symgs.argtypes = [P, P, P, i32, P]
     lib.spmv_colors.argtypes = [P, ctypes.POINTER(i32), P, P]
     lib.spmv_color_order.argtypes = [P, ctypes.POINTER(P), P, P]
+    lib.spmvc_check_violations.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.spmvc_check_probe.argtypes = [i64, i64, P]
     lib.spmvc_batched_config.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.spmvc_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
     lib.spmv_free.argtypes = [P]
@@ -419,6 +424,20 @@ def batched_config():
     f, c, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(load().spmvc_batched_config(ctypes.byref(f), ctypes.byref(c), ctypes.byref(us)))
     return {"form": f.value, "chunk": c.value, "us": us.value}
+
+
+def check_violations():
+    """(violations recorded since the last call, whether this library is the
+    bounds-checked build)."""
+    n, checked = ctypes.c_int64(), ctypes.c_int32()
+    _check(load().spmvc_check_violations(ctypes.byref(n), ctypes.byref(checked)))
+    return n.value, bool(checked.value)
+
+
+def check_probe(i, n):
+    """Checked builds: pass index i against [0, n) through the kernels' bounds
+    check on the device (a violation is then reported by check_violations)."""
+    _check(load().spmvc_check_probe(int(i), int(n), _stream()))
 
 
 def use_torch_allocator(enable=True):

@@ -30,30 +30,44 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+CHECK_BUILD = os.path.join(HERE, "_build_check")
+CHECK_LIB = os.path.join(HERE, "libspmvc_check.so")
+
+
+def _compile(src: str, check: bool = False) -> str:
+    obj = os.path.join(CHECK_BUILD if check else BUILD, os.path.splitext(src)[0] + ".o")
+    flags = FLAGS
+    if check:
+        # -O1: the bounds checks add a branch to every gather of the unrolled
+        # kernel templates, which makes -O3 code generation take many times
+        # longer; the checked build exists to test index arithmetic, which
+        # does not depend on the optimisation level
+        flags = [f if f != "-O3" else "-O1" for f in FLAGS] + ["-DSPMVC_CHECK"]
+    cmd = [_hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(jobs: int = 6, verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libspmvc.so next to this file."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int = 6, verbose: bool = False, check: bool = False) -> str:
+    """Compile every source for gfx950 and link libspmvc.so next to this file
+    (check=True: the bounds-checked debug build, -DSPMVC_CHECK, as
+    libspmvc_check.so)."""
+    os.makedirs(CHECK_BUILD if check else BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, check), SOURCES))
+    lib = CHECK_LIB if check else LIB
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-mcode-object-version=5", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True, jobs=int(sys.argv[1]) if len(sys.argv) > 1 else 6)
+    build(verbose=True, jobs=int(sys.argv[1]) if len(sys.argv) > 1 else 6, check="check" in sys.argv[2:])

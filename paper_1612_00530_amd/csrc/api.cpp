@@ -222,21 +222,23 @@ spmvc_status cg_solve(const spmvc_matrix *A, int32_t n_sys, int32_t nrhs, const 
         if (nrhs < 1 || nrhs > 16) return fail(SPMVC_EINVAL, "nrhs must be in 1..16");
         spmvc_cg_opts o{1e-10, 10000, 0, 1e-5, 20, 16, 2};
         if (opts) o = *opts;
-        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || o.mode < 0 || o.mode > 2 ||
+        if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 || o.mode < 0 || o.mode > 3 ||
             o.batched < 0 || o.batched > 2)
             return fail(SPMVC_EINVAL, "invalid cg options");
-        if (o.mode == 1 && (n_sys != 1 || nrhs != 1))
-            return fail(SPMVC_EUNSUPPORTED, "mixed-precision mode takes one system with one right-hand side");
+        if ((o.mode == 1 || o.mode == 3) && (n_sys != 1 || nrhs != 1))
+            return fail(SPMVC_EUNSUPPORTED, "mixed-precision modes take one system with one right-hand side");
         if (o.mode == 2 && (n_sys != 1 || nrhs != 1))
             return fail(SPMVC_EUNSUPPORTED, "preconditioned mode takes one system with one right-hand side");
-        if (o.mode == 1 && (!(o.inner_rtol > 0.0) || o.max_outer < 0)) return fail(SPMVC_EINVAL, "invalid inner options");
+        if ((o.mode == 1 || o.mode == 3) && (!(o.inner_rtol > 0.0) || o.max_outer < 0))
+            return fail(SPMVC_EINVAL, "invalid inner options");
         for (int s = 0; s < n_sys; ++s) {
             if (!A[s]) return fail(SPMVC_EINVAL, "matrix handle is null");
             if (A[s]->n_rows != A[s]->n_cols) return fail(SPMVC_EINVAL, "CG needs square matrices");
             if (A[s]->n_rows > 0 && (!b[s] || !x[s])) return fail(SPMVC_EINVAL, "b / x is null");
             if (overlap(b[s], 8 * A[s]->n_rows * nrhs, x[s], 8 * A[s]->n_rows * nrhs))
                 return fail(SPMVC_EINVAL, "b and x overlap");
-            if (o.mode == 1 && !f32_ready(A[s])) return fail(SPMVC_EUNSUPPORTED, "mixed mode needs f32_shadow");
+            if ((o.mode == 1 || o.mode == 3) && !f32_ready(A[s]))
+                return fail(SPMVC_EUNSUPPORTED, "mixed modes need f32_shadow");
         }
         for (int i = 0; i < n_sys * nrhs; ++i) stat[i] = spmvc_cg_stat{};
         const spmvc_status st = cg_solve_impl(A, n_sys, nrhs, b, x, o, stat, static_cast<hipStream_t>(stream));
@@ -482,6 +484,28 @@ spmvc_status spmv_color_order(spmvc_matrix A, spmvc_matrix *B, int32_t *perm, vo
         *B = nullptr;
         if (A->n_rows != A->n_cols) return fail(SPMVC_EINVAL, "the color order needs a square matrix");
         *B = color_order_copy(A, perm, static_cast<hipStream_t>(stream));
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmvc_check_violations(int64_t *count, int32_t *checked) {
+    return guarded([&]() -> spmvc_status {
+        if (!count || !checked) return fail(SPMVC_EINVAL, "null argument");
+#ifdef SPMVC_CHECK
+        *checked = 1;
+#else
+        *checked = 0;
+#endif
+        SPMVC_HIP(hipDeviceSynchronize());
+        *count = static_cast<int64_t>(check_violations_spmv() + check_violations_batched() + check_violations_symgs());
+        return SPMVC_OK;
+    });
+}
+
+spmvc_status spmvc_check_probe(int64_t i, int64_t n, void *stream) {
+    return guarded([&]() -> spmvc_status {
+        if (!check_probe(i, n, static_cast<hipStream_t>(stream)))
+            return fail(SPMVC_EUNSUPPORTED, "not a bounds-checked build");
         return SPMVC_OK;
     });
 }

@@ -32,6 +32,7 @@
 #include <mutex>
 #include <vector>
 
+#include "check.h"
 #include "internal.h"
 #include "lds_window.h"
 
@@ -158,13 +159,13 @@ template <> struct VecT<2> {
 
 template <int MAXW, int VEC>
 __device__ __forceinline__ void gather_row(const int32_t *__restrict__ pat, int len, int t0, const double *pr,
-                                           int64_t lrow, int nr, double (&s0)[VEC], double (&s1)[VEC]) {
+                                           int64_t lrow, int64_t n, int nr, double (&s0)[VEC], double (&s1)[VEC]) {
     int32_t off[MAXW];
 #pragma unroll
     for (int k = 0; k < MAXW; ++k) off[k] = k < len ? pat[k] : 0;
     VecT<VEC> xv[MAXW];
 #pragma unroll
-    for (int k = 0; k < MAXW; ++k) xv[k] = VecT<VEC>::load(pr + (lrow + off[k]) * nr);
+    for (int k = 0; k < MAXW; ++k) xv[k] = VecT<VEC>::load(pr + in_bounds<int64_t>(lrow + off[k], n) * nr);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         s0[v] = 0.0;
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
                 const int len = lenv[pass], t0 = t0v[pass];
                 double s0[VEC], s1[VEC];
                 if (len <= MAXW) {
-                    gather_row<MAXW, VEC>(pat, len, t0, pr, lrow, nr, s0, s1);
+                    gather_row<MAXW, VEC>(pat, len, t0, pr, lrow, d.n, nr, s0, s1);
                 } else {
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) {
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
                         s1[v] = 0.0;
                     }
                     for (int k = 0; k < len; ++k) {
-                        const VecT<VEC> xv = VecT<VEC>::load(pr + (lrow + pat[k]) * nr);
+                        const VecT<VEC> xv = VecT<VEC>::load(pr + in_bounds<int64_t>(lrow + pat[k], d.n) * nr);
 #pragma unroll
                         for (int v = 0; v < VEC; ++v) {
                             if (k < t0)
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
                 if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
             }
             for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) {
-                const VecT<VEC> xv = VecT<VEC>::load(pr + static_cast<int64_t>(d.esc_col[e]) * nr);
+                const VecT<VEC> xv = VecT<VEC>::load(pr + in_bounds<int64_t>(d.esc_col[e], d.n) * nr);
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) acc[v] = fma(d.esc_val[e], xv.v[v], acc[v]);
             }
@@ -317,12 +318,13 @@ __global__ __launch_bounds__(kT) void k_bspmv(Batch b, const double *__restrict_
 // 16-byte x reads in flight, then four weighted FMAs (value V[0] for
 // canonical index < t0, else V[1]).
 template <int NRB>
-__device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, int t0, double v0, double v1,
-                                           double &a0, double &a1) {
+__device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, uint32_t lim, int t0, double v0,
+                                           double v1, double &a0, double &a1) {
     const uint32_t ent[4] = {e.x, e.y, e.z, e.w};
     double2 xv[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const double2 *>(xrow + (ent[j] & 0xFFFFu) * NRB);
+    for (int j = 0; j < 4; ++j)
+        xv[j] = *reinterpret_cast<const double2 *>(xrow + in_bounds<uint32_t>(ent[j] & 0xFFFFu, lim) * NRB);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
@@ -404,20 +406,22 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
             if (r0 + rel >= d.n || idv[ps] == esc) continue;
             const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
             const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
+            const uint32_t lim = static_cast<uint32_t>(d.bw_len[w] - rel);  // window rows from this row on
             if (d.bw_split) {
-                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, v0, v1, acc[ps][0],
+                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps][0],
                                       acc[ps][1]);
                 continue;
             }
             const int cnt = static_cast<int>(rec[0].x);
             int k0 = 0;
             for (; k0 + 4 <= cnt; k0 += 4)
-                bwin_group<NR * 8>(rec[1 + (k0 >> 2)], xrow, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
+                bwin_group<NR * 8>(rec[1 + (k0 >> 2)], xrow, lim, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
             // the last cnt mod 4 entries one at a time (no padded work)
             const uint32_t *recw = reinterpret_cast<const uint32_t *>(rec) + 4;
             for (; k0 < cnt; ++k0) {
                 const uint32_t e = recw[k0];
-                const double2 xv = *reinterpret_cast<const double2 *>(xrow + (e & 0xFFFFu) * (NR * 8));
+                const double2 xv =
+                    *reinterpret_cast<const double2 *>(xrow + in_bounds<uint32_t>(e & 0xFFFFu, lim) * (NR * 8));
                 const double wgt = static_cast<int>(e >> 16) < t0v[ps] ? v0 : v1;
                 acc[ps][0] = fma(wgt, xv.x, acc[ps][0]);
                 acc[ps][1] = fma(wgt, xv.y, acc[ps][1]);
@@ -443,7 +447,8 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
             q0 = 0.0;
             q1 = 0.0;
             for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) {
-                const double2 xv = *reinterpret_cast<const double2 *>(sysP + static_cast<int64_t>(d.esc_col[e]) * NR + rp);
+                const double2 xv =
+                    *reinterpret_cast<const double2 *>(sysP + in_bounds<int64_t>(d.esc_col[e], d.n) * NR + rp);
                 q0 = fma(d.esc_val[e], xv.x, q0);
                 q1 = fma(d.esc_val[e], xv.y, q1);
             }
@@ -1155,5 +1160,8 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     }
     return first_bad;
 }
+
+// bounds violations the kernels of this file recorded (checked builds)
+SPMVC_CHECK_READER(check_violations_batched)
 
 }  // namespace spmvc

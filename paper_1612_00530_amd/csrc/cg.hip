@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <limits>
 #include <memory>
 #include <mutex>
 
@@ -508,6 +509,35 @@ __global__ __launch_bounds__(kRT) void k_residual_fin(const double *rr_part, con
         st->aux[0] = a;
         st->aux[1] = b;
     }
+}
+
+// Start of a reliable-update segment: r = r64 / s (the FP64 true residual in
+// units of its norm s), p = r + beta p (beta = 0: p = r; otherwise p keeps the
+// previous segment's direction, rescaled into the new units by the caller's
+// beta), xl = 0; partials of r.r.
+__global__ __launch_bounds__(kRT) void k_rel_start(int64_t n, const double *__restrict__ r64, double s, float beta,
+                                                   float *__restrict__ xl, float *__restrict__ r,
+                                                   float *__restrict__ p, double *partials) {
+    double acc = 0.0;
+    const bool fresh = beta == 0.0f;
+    SPMVC_STREAM4(
+        float v[4]; float pv[4];
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            v[u] = static_cast<float>(r64[i + u * stride_] / s);
+            pv[u] = fresh ? 0.0f : p[i + u * stride_];
+        }
+_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+            xl[i + u * stride_] = 0.0f; r[i + u * stride_] = v[u]; p[i + u * stride_] = v[u] + beta * pv[u];
+            acc += dd(v[u]) * dd(v[u]);
+        }
+        ,
+        const float v = static_cast<float>(r64[i] / s);
+        p[i] = v + beta * (fresh ? 0.0f : p[i]);
+        xl[i] = 0.0f; r[i] = v;
+        acc += dd(v) * dd(v);
+    )
+    const double b = block_sum<kRT>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
 // x += scale * (double) d
@@ -996,6 +1026,84 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
     return st;
 }
 
+// Mixed precision with reliable updates (mode 3): one CG whose iterations
+// all run in FP32 (SpMV over the FP32 shadow, FP32 vectors, FP64 dot
+// products), with the FP64 residual put back in place of the recursive one
+// whenever the latter has fallen by inner_rtol since the last replacement.  A
+// segment solves A d = r / ||r|| in FP32 from d = 0; at its end x += ||r|| d in
+// FP64, r = b - A x is recomputed in FP64, and the next segment starts from
+// that residual but keeps the search direction p (rescaled to the new units,
+// with beta = ||r_new||^2 / ||r_k||^2), so the Krylov space is not thrown away
+// as at a refinement restart.  Stops when the true FP64 residual meets rtol.
+spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
+                            spmvc_cg_stat &stat, hipStream_t s) {
+    const int64_t n = M->n_rows;
+    const int64_t nn = std::max<int64_t>(n, 1);
+    const unsigned g = rgrid(n);
+    Solver sv(s, spmv_dot_blocks(M));
+    DevBuf r64, q64, r32, p32, q32, xl32;
+    r64.alloc(sizeof(double) * nn);
+    q64.alloc(sizeof(double) * nn);
+    r32.alloc(sizeof(float) * nn);
+    p32.alloc(sizeof(float) * nn);
+    q32.alloc(sizeof(float) * nn);
+    xl32.alloc(sizeof(float) * nn);
+    SPMVC_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn, s));
+    double rr, bb;
+    residual(M, sv, b, x, q64.as<double>(), r64.as<double>(), rr, bb);
+    const double bnorm = std::sqrt(bb);
+    int total = 0, segs = 0;
+    spmvc_status st = SPMVC_ENOCONV;
+    if (!std::isfinite(bb) || !std::isfinite(rr)) {  // NaN or Inf in b
+        stat = spmvc_cg_stat{};
+        stat.status = SPMVC_EINVAL;
+        stat.relres_true = stat.relres_recursive = std::numeric_limits<double>::quiet_NaN();
+        return SPMVC_EINVAL;
+    }
+    double rel = bnorm > 0.0 ? std::sqrt(rr) / bnorm : 0.0, rel_rec = rel;
+    double s_prev = 0.0, rho_k = 0.0;  // the last segment's scale and r.r before its last step
+    while (true) {
+        if (rel <= o.rtol) {
+            st = SPMVC_OK;
+            break;
+        }
+        if (segs > o.max_outer || total >= o.max_iter) break;
+        const double sn = std::sqrt(rr);
+        // ||R_true||^2 / ||R_k||^2 with R_k = s_prev r_k, and p into units of sn
+        const double beta = (segs == 0 || !(rho_k > 0.0)) ? 0.0 : sn / (s_prev * rho_k);
+        const double seg_tol = std::min(std::max(o.inner_rtol, 0.9 * o.rtol / rel), 0.5);
+        k_rel_start<<<g, kRT, 0, s>>>(n, r64.as<double>(), sn, static_cast<float>(beta), xl32.as<float>(),
+                                      r32.as<float>(), p32.as<float>(), sv.pa);
+        k_cg_start_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), seg_tol, o.max_iter - total);
+        SPMVC_CHECK_LAUNCH();
+        const CgScal h = cg_iterate<float>(M, sv, xl32.as<float>(), r32.as<float>(), p32.as<float>(),
+                                           q32.as<float>(), 0, o.max_iter - total, o.check_every);
+        total += h.iters;
+        ++segs;
+        if (h.status == SPMVC_ENOTSPD || h.status == SPMVC_EINVAL) {
+            st = static_cast<spmvc_status>(h.status);
+            break;
+        }
+        rel_rec = h.rel * sn / bnorm;
+        rho_k = h.iters > 0 ? h.rho[(h.iters - 1) & 1] : 0.0;
+        s_prev = sn;
+        k_add_f32<<<rgrid(n), kRT, 0, s>>>(n, x, xl32.as<float>(), sn);
+        SPMVC_CHECK_LAUNCH();
+        residual(M, sv, b, x, q64.as<double>(), r64.as<double>(), rr, bb);
+        rel = std::sqrt(rr) / bnorm;
+        if (!std::isfinite(rel)) {
+            st = SPMVC_ENOTSPD;
+            break;
+        }
+    }
+    stat.iters = total;
+    stat.outer_iters = segs;
+    stat.status = st;
+    stat.relres_recursive = rel_rec;
+    stat.relres_true = rel;
+    return st;
+}
+
 }  // namespace
 
 spmvc_status cg_solve_mg_impl(spmvc_matrix const *levels, const int32_t *const *f2c, int n_levels, const double *b,
@@ -1043,6 +1151,11 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
     spmvc_status first_bad = SPMVC_OK;
     if (o.mode == 1) {
         const spmvc_status st = solve_mixed(A[0], b[0], x[0], o, stat[0], s);
+        SPMVC_HIP(hipStreamSynchronize(s));
+        return st;
+    }
+    if (o.mode == 3) {
+        const spmvc_status st = solve_reliable(A[0], b[0], x[0], o, stat[0], s);
         SPMVC_HIP(hipStreamSynchronize(s));
         return st;
     }

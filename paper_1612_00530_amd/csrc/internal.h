@@ -255,6 +255,15 @@ spmvc_matrix_s *color_order_copy(spmvc_matrix_s *M, int32_t *perm, hipStream_t s
 void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweeps, hipStream_t s,
                   const int *skip = nullptr, bool reverse = false);
 
+// Bounds violations recorded by the kernels of spmv.hip, batched.hip and
+// symgs.hip since the last read (always 0 unless built with -DSPMVC_CHECK).
+unsigned long long check_violations_spmv();
+unsigned long long check_violations_batched();
+unsigned long long check_violations_symgs();
+// Checked builds: one kernel passes index i against [0, n) through the kernels'
+// bounds check (so a test can see a violation recorded); false otherwise.
+bool check_probe(int64_t i, int64_t n, hipStream_t s);
+
 // scan.hip: exclusive prefix sum of n int64 values (in may equal out); returns the total.
 int64_t exclusive_scan(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 

@@ -42,6 +42,7 @@
 #include <cstring>
 #include <set>
 
+#include "check.h"
 #include "internal.h"
 #include "lds_window.h"
 
@@ -146,7 +147,7 @@ __device__ __forceinline__ double escape_row(const SpmvArgs &a, int64_t e, int n
     for (int r = 0; r < NR; ++r) acc[r] = Real(0);
     for (int64_t k = a.esc_ptr[e]; k < a.esc_ptr[e + 1]; ++k) {
         const Real v = ev[k];
-        const Real *xp = x + static_cast<int64_t>(a.esc_col[k]) * ldx;
+        const Real *xp = x + in_bounds<int64_t>(a.esc_col[k], a.n_cols) * ldx;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (NR == 1 || r < nrhs) acc[r] = fma(v, xp[r], acc[r]);
@@ -199,7 +200,7 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
     for (int r = 0; r < NR; ++r) acc[r] = Real(0);
 
     auto apply = [&](Real v, int64_t j) {
-        const Real *xp = x + j * ldx;
+        const Real *xp = x + in_bounds<int64_t>(j, a.n_cols) * ldx;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (NR == 1 || r < nrhs) acc[r] = fma(v, xp[r], acc[r]);
@@ -356,19 +357,20 @@ __global__ __launch_bounds__(kBlock) void k_dit_lds(SpmvArgs a, const Real *__re
         const IdT id = static_cast<const IdT *>(a.ids)[row];
         if (id == esc_id<IdT>()) continue;
         const uint16_t *t = tab + static_cast<int64_t>(id) * tw + 1;
-        const Real *xr = xs + rel;
         Real acc = Real(0);
         int k = 0;
         for (int c = 0; c < a.K; ++c) {
             const int tend = row_T(a, c, row, id);
             const Real v = vtab<Real>(a, c);
-            for (; k < tend; ++k) acc = fma(v, xr[t[k]], acc);
+            for (; k < tend; ++k) acc = fma(v, xs[in_bounds<int>(rel + t[k], a.lds_total)], acc);
         }
         if constexpr (RAW) {
             const int len = t[-1];
             const Real *raw = static_cast<const Real *>(a.raw);
             const int64_t rb = a.raw_slice[row / kSlice] + (row % kSlice) - static_cast<int64_t>(k) * kSlice;
-            for (; k < len; ++k) acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice), xr[t[k]], acc);
+            for (; k < len; ++k)
+                acc = fma(ldg_stream(raw + rb + static_cast<int64_t>(k) * kSlice),
+                          xs[in_bounds<int>(rel + t[k], a.lds_total)], acc);
         }
         y[row] = acc;
         if (a.dot) dotc += static_cast<double>(x[row]) * static_cast<double>(acc);
@@ -490,7 +492,7 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
         auto xat = [&](int k) -> Real {
             const uint32_t word = w[(k + 1) >> 1];
             const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
-            return *reinterpret_cast<const Real *>(buf + relb + off);
+            return *reinterpret_cast<const Real *>(buf + in_bounds<uint32_t>(relb + off, a.lds_x_bytes));
         };
         if constexpr (KK == 0) {
             // Raw values up to the width of the row's 64-row slice (the same for
@@ -741,7 +743,6 @@ __global__ __launch_bounds__(kBlock) void k_bmask_lds(SpmvArgs a, const Real *__
     for (int j = 0; j < RPT; ++j) {
         const int rel = threadIdx.x + j * kBlock;
         const int64_t row = r0 + rel;
-        const Real *xr = xs + rel;
         MaskT m = mv[j];
         Real acc = Real(0);
         if constexpr (KK == 0) {
@@ -762,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_bmask_lds(SpmvArgs a, const Real *__
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    if (kk[u] >= 0) acc = fma(rv[u], xr[offs[kk[u]]], acc);
+                    if (kk[u] >= 0) acc = fma(rv[u], xs[in_bounds<int>(rel + offs[kk[u]], a.lds_total)], acc);
             }
         } else {
             // uniform wavefront: full masks and one V[1] mask
@@ -773,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void k_bmask_lds(SpmvArgs a, const Real *__
             if (uni) {
                 Real xv[NDM];
 #pragma unroll
-                for (int k = 0; k < NDM; ++k) xv[k] = k < nd ? xr[a.bm_off[k]] : Real(0);
+                for (int k = 0; k < NDM; ++k) xv[k] = k < nd ? xs[in_bounds<int>(rel + a.bm_off[k], a.lds_total)] : Real(0);
 #pragma unroll
                 for (int k = 0; k < NDM; ++k) {
                     if (KK == 2 && ((vm0 >> k) & 1))
@@ -785,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_bmask_lds(SpmvArgs a, const Real *__
 #pragma unroll
                 for (int k = 0; k < NDM; ++k) {
                     if (k < nd && ((m >> k) & 1)) {
-                        const Real xk = xr[a.bm_off[k]];
+                        const Real xk = xs[in_bounds<int>(rel + a.bm_off[k], a.lds_total)];
                         if (KK == 2 && ((vm >> k) & 1))
                             s1 += xk;
                         else
@@ -849,7 +850,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_lanes(SpmvArgs a, int nrhs, con
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = Real(0);
     auto apply = [&](Real val, int64_t j) {
-        const LaneVec<Real, VEC> xv = LaneVec<Real, VEC>::load(xr + j * ldx);
+        const LaneVec<Real, VEC> xv = LaneVec<Real, VEC>::load(xr + in_bounds<int64_t>(j, a.n_cols) * ldx);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[v] = fma(val, xv.v[v], acc[v]);
     };
@@ -1009,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
         auto xat = [&](int k) -> D2 {
             const uint32_t word = wv[(k + 1) >> 1];
             const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
-            const double2 t = *reinterpret_cast<const double2 *>(smem + relb + off);
+            const double2 t = *reinterpret_cast<const double2 *>(smem + in_bounds<uint32_t>(relb + off, a.lds_x_bytes));
             return D2{t.x, t.y};
         };
         D2 acc{0.0, 0.0};
@@ -1031,12 +1032,13 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
 // 16-byte x reads in flight, then four weighted FMAs (value V[0] for
 // canonical index < t0, else V[1]).
 template <int NRB>
-__device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, int t0, double v0, double v1,
-                                          double &a0, double &a1) {
+__device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, uint32_t lim, int t0, double v0,
+                                          double v1, double &a0, double &a1) {
     const uint32_t ent[4] = {e.x, e.y, e.z, e.w};
     double2 xv[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xv[j] = *reinterpret_cast<const double2 *>(xrow + (ent[j] & 0xFFFFu) * NRB);
+    for (int j = 0; j < 4; ++j)
+        xv[j] = *reinterpret_cast<const double2 *>(xrow + in_bounds<uint32_t>(ent[j] & 0xFFFFu, lim) * NRB);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const double wgt = static_cast<int>(ent[j] >> 16) < t0 ? v0 : v1;
@@ -1051,15 +1053,15 @@ __device__ __forceinline__ void win_group(uint4 e, const unsigned char *xrow, in
 // pair in window row 0, NRB the bytes of a window row.  One 16-byte table
 // read per four entries; the last cnt mod 4 entries one at a time.
 template <int NRB>
-__device__ __forceinline__ void win_row(const uint4 *rec, const unsigned char *xrow, int t0, double v0, double v1,
-                                        double &a0, double &a1) {
+__device__ __forceinline__ void win_row(const uint4 *rec, const unsigned char *xrow, uint32_t lim, int t0, double v0,
+                                        double v1, double &a0, double &a1) {
     const int cnt = static_cast<int>(rec[0].x);
     int k0 = 0;
-    for (; k0 + 4 <= cnt; k0 += 4) win_group<NRB>(rec[1 + (k0 >> 2)], xrow, t0, v0, v1, a0, a1);
+    for (; k0 + 4 <= cnt; k0 += 4) win_group<NRB>(rec[1 + (k0 >> 2)], xrow, lim, t0, v0, v1, a0, a1);
     const uint32_t *recw = reinterpret_cast<const uint32_t *>(rec) + 4;
     for (; k0 < cnt; ++k0) {
         const uint32_t e = recw[k0];
-        const double2 xv = *reinterpret_cast<const double2 *>(xrow + (e & 0xFFFFu) * NRB);
+        const double2 xv = *reinterpret_cast<const double2 *>(xrow + in_bounds<uint32_t>(e & 0xFFFFu, lim) * NRB);
         const double wgt = static_cast<int>(e >> 16) < t0 ? v0 : v1;
         a0 = ::fma(wgt, xv.x, a0);
         a1 = ::fma(wgt, xv.y, a1);
@@ -1135,10 +1137,12 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
             if (row >= a.n_rows || idv[ps] == esc) continue;
             const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
             const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
+            const uint32_t lim = static_cast<uint32_t>(a.win_len[w] - rel);  // window rows from this row on
             if (a.bw_split)
-                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, v0, v1, acc[ps][0], acc[ps][1]);
+                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps][0],
+                                      acc[ps][1]);
             else
-                win_row<NR * 8>(rec, xrow, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
+                win_row<NR * 8>(rec, xrow, lim, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
         }
     }
 #pragma unroll
@@ -2094,6 +2098,29 @@ int64_t stream_bytes(const spmvc_matrix_s *M, int dt) {
     }
     b += M->n_esc_nnz * (4 + vb) + M->n_esc * 16;
     return b;
+}
+
+// bounds violations the kernels of this file recorded (checked builds)
+SPMVC_CHECK_READER(check_violations_spmv)
+
+namespace {
+__global__ void k_check_probe(int64_t i, int64_t n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) (void)in_bounds<int64_t>(i, n);
+}
+}  // namespace
+
+bool check_probe(int64_t i, int64_t n, hipStream_t s) {
+#ifdef SPMVC_CHECK
+    k_check_probe<<<1, 64, 0, s>>>(i, n);
+    SPMVC_CHECK_LAUNCH();
+    SPMVC_HIP(hipStreamSynchronize(s));
+    return true;
+#else
+    (void)i;
+    (void)n;
+    (void)s;
+    return false;
+#endif
 }
 
 }  // namespace spmvc

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "check.h"
 #include "internal.h"
 
 namespace spmvc {
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int3
         if (j == i)
             d = v;
         else
-            s = fma(v, x[j], s);
+            s = fma(v, x[in_bounds<int64_t>(j, a.n_rows)], s);
     });
     x[i] = (b[i] - s) / d;
 }
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
             if (j == i)
                 d = v;
             else
-                s = fma(v, x[j], s);
+                s = fma(v, x[in_bounds<int64_t>(j, a.n_rows)], s);
         });
     } else {
         const int32_t *pr = a.pat_off + static_cast<int64_t>(id) * a.width;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
         for (int k = 0; k < MAXW; ++k) off[k] = k < a.width ? pr[k] : 0;
         double xv[MAXW];
 #pragma unroll
-        for (int k = 0; k < MAXW; ++k) xv[k] = x[i + (k < len ? off[k] : 0)];
+        for (int k = 0; k < MAXW; ++k) xv[k] = x[in_bounds<int64_t>(i + (k < len ? off[k] : 0), a.n_rows)];
 #pragma unroll
         for (int k = 0; k < MAXW; ++k) {
             const double v = k < len ? (k < t0 ? a.V[0] : a.V[1]) : 0.0;
@@ -436,5 +437,8 @@ spmvc_matrix_s *color_order_copy(spmvc_matrix_s *M, int32_t *perm, hipStream_t s
     }
     return T.release();
 }
+
+// bounds violations the kernels of this file recorded (checked builds)
+SPMVC_CHECK_READER(check_violations_symgs)
 
 }  // namespace spmvc

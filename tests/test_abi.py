@@ -29,12 +29,24 @@ def test_header_declares_the_boundary():
     assert len(names) >= 12
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libspmvc.so not built")
-def test_library_exports_every_declared_symbol():
-    lib = ctypes.CDLL(LIB)
+CHECK_LIB = os.path.join(ROOT, "paper_1612_00530_amd", "libspmvc_check.so")
+
+
+@pytest.mark.parametrize("path", [LIB, CHECK_LIB], ids=["release", "bounds_checked"])
+def test_library_exports_every_declared_symbol(path):
+    """The release library and the bounds-checked debug build (-DSPMVC_CHECK)
+    export the same boundary."""
+    if not os.path.exists(path):
+        pytest.skip(os.path.basename(path) + " not built")
+    lib = ctypes.CDLL(path)
     for name in declared_functions():
         assert hasattr(lib, name), name
-    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    lib.spmvc_check_violations.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.spmvc_check_violations(None, None) == -1  # rejected on the host
+    if path == LIB:  # the probe exists in checked builds only
+        lib.spmvc_check_probe.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+        assert lib.spmvc_check_probe(3, 3, None) == -8
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
     exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
 
