@@ -140,9 +140,9 @@ def main():
                          "launches of the roofline (each after a 1 GiB fill), and exit")
     ap.add_argument("--pmc-configs", action="store_true",
                     help="with --cold-only: before the roofline launches, also launch the FP64 DIT kernel "
-                         "cold in each tuner candidate configuration (register and plane-marching kernels, "
-                         "256/512/1024 rows per block) so that one counter run covers whichever the tuner "
-                         "picks")
+                         "cold in each tuner candidate configuration (register kernel at 256/512/768/1024 "
+                         "rows per block, plane-marching kernel at 256/512/1024) so that one counter run "
+                         "covers whichever the tuner picks")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -195,10 +195,12 @@ def main():
             D.set_config(512, 1)
         keep = D.info()
         if args.pmc_configs:
-            for lds in (1, 2):
-                for rows in (256, 512, 1024):
+            time_cold(lambda: D.spmv(x, y), 5, torch, flush)  # first-use costs out of the first config
+            for lds, rows_list in ((1, (256, 512, 768, 1024)), (2, (256, 512, 1024))):
+                for rows in rows_list:
                     D.set_config(rows, lds)
-                    time_cold(lambda: D.spmv(x, y), COLD_REPS, torch, flush)
+                    cm, _ = time_cold(lambda: D.spmv(x, y), COLD_REPS, torch, flush)
+                    log(f"[bench] cold {D.info()['kernel_name']} {rows} rows: kernel {cm * 1000:.3f} us")
             D.set_config(keep["rows_per_block"], {0: 0, 1: 1, 2: 1, 3: 2}[keep["kernel"]])
         c_mean, c_med = time_cold(lambda: D.spmv(x, y), COLD_REPS, torch, flush)
         log(f"[bench] cold-only: {keep['kernel_name']} {keep['rows_per_block']} rows, {2 * COLD_REPS} cold "

@@ -634,8 +634,11 @@ struct Solver {
     // the scalars after chunk k while chunk k + 1 is already queued, so the
     // device does not idle during the read; a chunk queued after the solve
     // finished runs as no-ops (every kernel of an iteration returns at once
-    // when `done` is set).  Without events (the allocation-free solver) each
-    // read waits for the stream.
+    // when `done` is set, but each launch still costs a few microseconds).
+    // So when the residuals read after the last two chunks, continued
+    // geometrically, reach the tolerance within the chunk in flight, the next
+    // chunk is queued only after that chunk's status has been read.  Without
+    // events (the allocation-free solver) each read waits for the stream.
     template <class F> void iterate_chunks(F &&launch_chunk) {
         if (!ev[0]) {
             while (!read().done && launch_chunk()) {
@@ -648,11 +651,25 @@ struct Solver {
         };
         if (!launch_chunk()) return;
         post(0);
+        double rel_prev = -1.0, rel_last = -1.0;  // residuals read after the last two chunks
         for (int slot = 0;; slot ^= 1) {
-            const bool more = launch_chunk();
-            if (more) post(slot ^ 1);
+            const bool near_end = rel_prev > 0.0 && rel_last > 0.0 && rel_last < rel_prev &&
+                                  rel_last * (rel_last / rel_prev) <= pin->h[1 + (slot ^ 1)].rtol;
+            bool more = false;
+            if (!near_end) {
+                more = launch_chunk();
+                if (more) post(slot ^ 1);
+            }
             SPMVC_HIP(hipEventSynchronize(ev[slot]));
-            if (pin->h[1 + slot].done || !more) return;
+            const CgScal &h = pin->h[1 + slot];
+            if (h.done) return;
+            if (near_end) {
+                more = launch_chunk();
+                if (more) post(slot ^ 1);
+            }
+            if (!more) return;
+            rel_prev = rel_last;
+            rel_last = h.rel;
         }
     }
 };

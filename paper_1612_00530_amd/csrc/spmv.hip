@@ -97,6 +97,8 @@ struct SpmvArgs {
     const void *bm_mask, *bm_vmask;
     int32_t bm_nd;
     int32_t bm_off[64];            // element offset of D[k] in the windows (LDS kernel)
+    int32_t self_off;              // register kernel: byte offset (from the row's slot) of the
+                                   // row's own x in the windows, -1 when no window holds it
 };
 
 template <class Real> __device__ __forceinline__ Real vtab(const SpmvArgs &a, int c);
@@ -435,8 +437,9 @@ template <int LO, int HI, class F> __device__ __forceinline__ auto sum_entries(F
     return g[0];
 }
 
-// Row metadata of one tile (IDs, T[0], x at the row) for the RPT rows of this thread.
-template <class Real, int KK, int RPT>
+// Row metadata of one tile (IDs, T[0], and with EARLY_X x at the row) for the
+// RPT rows of this thread.
+template <class Real, int KK, int RPT, bool EARLY_X = true>
 __device__ __forceinline__ void load_tile_meta(const SpmvArgs &a, const Real *__restrict__ x, int64_t r0,
                                                uint32_t (&idv)[RPT], int (&t0v)[RPT], Real (&xrow)[RPT]) {
 #pragma unroll
@@ -445,17 +448,20 @@ __device__ __forceinline__ void load_tile_meta(const SpmvArgs &a, const Real *__
         const int64_t rc = row < a.n_rows ? row : a.n_rows - 1;
         idv[j] = load_id(a.ids, a.id_bytes, rc);
         t0v[j] = (KK >= 1 && !a.pat_T) ? static_cast<int>(a.T[rc]) : 0;  // DITV: from the pattern row
-        xrow[j] = a.dot ? x[rc] : Real(0);
+        if constexpr (EARLY_X) xrow[j] = a.dot ? x[rc] : Real(0);
     }
 }
 
 // The rows of one tile, x windows already in LDS at `buf` (byte base of the
-// windows + zero window), pattern rows at `tab`.  Adds the tile's x.y to dotc.
-template <class Real, int KK, int RPT, int MAXW>
+// windows + zero window), pattern rows at `tab`.  Adds the tile's x.y to dotc:
+// with EARLY_X the row's x comes from xrow (loaded with the metadata),
+// otherwise it is read when needed -- from the windows at self_off when one
+// holds it, else from x -- so that no register holds it through the tile.
+template <class Real, int KK, int RPT, int MAXW, bool EARLY_X = true>
 __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char *buf, const uint4 *tab, int64_t r0,
                                          int rel_end, const uint32_t (&idv)[RPT], const int (&t0v)[RPT],
                                          const Real (&xrow)[RPT], Real v0, Real v1, Real *__restrict__ y,
-                                         double &dotc) {
+                                         double &dotc, const Real *__restrict__ x = nullptr) {
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -527,7 +533,17 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
             for (int k = 0; k < MAXW; ++k) acc = fma(k < m ? v1 : v0, xat(k), acc);
         }
         y[row] = acc;
-        if (a.dot) dotc += static_cast<double>(xrow[j]) * static_cast<double>(acc);
+        if (a.dot) {
+            Real xr;
+            if constexpr (EARLY_X)
+                xr = xrow[j];
+            else
+                xr = a.self_off >= 0
+                         ? *reinterpret_cast<const Real *>(
+                               buf + in_bounds<uint32_t>(relb + static_cast<uint32_t>(a.self_off), a.lds_x_bytes))
+                         : x[row];
+            dotc += static_cast<double>(xr) * static_cast<double>(acc);
+        }
     }
 }
 
@@ -544,9 +560,11 @@ template <class Real, int KK> __device__ __forceinline__ void value_pair(const S
 // With one or two rows per thread a block of the 27-point stencil takes about
 // 23 KB of LDS (three plane windows, the zero window, the table), so seven
 // blocks fit a CU; asking for seven waves per SIMD keeps registers from being
-// the tighter limit (at most 72 VGPRs instead of 80, no spills).
+// the tighter limit (at most 72 VGPRs instead of 80, no spills).  With raw
+// values (KK = 0) a row also holds its values in registers: six waves (80
+// VGPRs) keep those from spilling, and six blocks is what the LDS allows there.
 template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
-__global__ __launch_bounds__(kBlock, RPT <= 2 ? 7 : (RPT == 3 ? 6 : 1)) void k_dit_reg(SpmvArgs a,
+__global__ __launch_bounds__(kBlock, (KK == 0 && RPT <= 3) ? 6 : (RPT <= 2 ? 7 : (RPT == 3 ? 6 : 1))) void k_dit_reg(SpmvArgs a,
                                                                                       const Real *__restrict__ x,
                                                                                       Real *__restrict__ y) {
     if (a.skip && *a.skip) return;
@@ -561,8 +579,8 @@ __global__ __launch_bounds__(kBlock, RPT <= 2 ? 7 : (RPT == 3 ? 6 : 1)) void k_d
     double dotc = 0.0;
     uint32_t idv[RPT];
     int t0v[RPT];
-    Real xrow[RPT];  // x at the row itself, for the optional dot product
-    load_tile_meta<Real, KK, RPT>(a, x, r0, idv, t0v, xrow);
+    Real xrow[RPT];  // unused: the row's x is read after the staging (reg_tile, EARLY_X false)
+    load_tile_meta<Real, KK, RPT, false>(a, x, r0, idv, t0v, xrow);
     stage_windows<Real>(a, x, xs, r0);
     uint4 *tab_s = reinterpret_cast<uint4 *>(smem + a.lds_x_bytes);
     if constexpr (TAB_LDS) {
@@ -574,7 +592,7 @@ __global__ __launch_bounds__(kBlock, RPT <= 2 ? 7 : (RPT == 3 ? 6 : 1)) void k_d
     const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
     Real v0, v1;
     value_pair<Real, KK>(a, v0, v1);
-    reg_tile<Real, KK, RPT, MAXW>(a, smem, tab, r0, kBlock * RPT, idv, t0v, xrow, v0, v1, y, dotc);
+    reg_tile<Real, KK, RPT, MAXW, false>(a, smem, tab, r0, kBlock * RPT, idv, t0v, xrow, v0, v1, y, dotc, x);
     emit_dot(a, dotc);
 }
 
@@ -1157,6 +1175,7 @@ template <class Real> SpmvArgs make_args(const spmvc_matrix_s *M, const int *ski
     SpmvArgs a{};
     a.skip = skip;
     a.dot = dot;
+    a.self_off = -1;
     a.n_rows = M->n_rows;
     a.n_cols = M->n_cols;
     a.n_pad = M->n_pad;
@@ -1336,6 +1355,13 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
         }
         size_t shmem = a.lds_x_bytes;
         if (p.reg_tab_in_lds) shmem += static_cast<size_t>(M->P) * kRegTw * 2;
+        // the window that holds every row of the block (displacement 0), if any
+        a.self_off = -1;
+        for (int w = 0; w < p.n_win; ++w)
+            if (p.lo[w] <= 0 && p.lo[w] + p.len[w] >= p.rows) {
+                a.self_off = static_cast<int32_t>((p.base[w] - p.lo[w]) * static_cast<int64_t>(sizeof(Real)));
+                break;
+            }
 #define SPMVC_REG_W(KK, TL, R)                                                                                  \
     if (w27)                                                                                                    \
         k_dit_reg<Real, KK, TL, R, 27><<<grid, kBlock, shmem, s>>>(a, xp, yp);                                  \
@@ -1741,16 +1767,45 @@ static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<st
 // pattern has more than kWinMaxPw entries in one window.
 // T_i[0] of every row using pattern q, when they all agree (DIT with two
 // table values): the range over the rows, taken once per handle.
-__global__ void k_pattern_t0_range(int64_t n_rows, const void *ids, int id_bytes, const uint8_t *T, int *tmin,
+// With at most kT0LdsMax patterns each block first reduces its rows in LDS
+// and then adds one global min and max per pattern it holds (a few patterns
+// and millions of rows would otherwise serialize millions of global atomics
+// on a handful of addresses); with more patterns the rows go to global memory
+// directly.  The grid strides over the rows.
+constexpr int kT0LdsMax = 4096;
+__global__ void k_pattern_t0_range(int64_t n_rows, const void *ids, int id_bytes, const uint8_t *T, int P, int *tmin,
                                    int *tmax) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n_rows) return;
-    const uint32_t id = load_id(ids, id_bytes, i);
+    __shared__ int smin[kT0LdsMax], smax[kT0LdsMax];
+    const bool local = P <= kT0LdsMax;
+    if (local) {
+        for (int q = threadIdx.x; q < P; q += blockDim.x) {
+            smin[q] = 1 << 30;
+            smax[q] = -1;
+        }
+        __syncthreads();
+    }
     const uint32_t esc = id_bytes == 1 ? 0xFFu : (id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
-    if (id == esc) return;
-    const int t = T[i];
-    atomicMin(&tmin[id], t);
-    atomicMax(&tmax[id], t);
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n_rows; i += stride) {
+        const uint32_t id = load_id(ids, id_bytes, i);
+        if (id == esc || id >= static_cast<uint32_t>(P)) continue;
+        const int t = T[i];
+        if (local) {
+            atomicMin(&smin[id], t);
+            atomicMax(&smax[id], t);
+        } else {
+            atomicMin(&tmin[id], t);
+            atomicMax(&tmax[id], t);
+        }
+    }
+    if (local) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < P; q += blockDim.x)
+            if (smax[q] >= 0) {
+                atomicMin(&tmin[q], smin[q]);
+                atomicMax(&tmax[q], smax[q]);
+            }
+    }
 }
 
 static void pattern_t0(spmvc_matrix_s *M) {
@@ -1765,8 +1820,9 @@ static void pattern_t0(spmvc_matrix_s *M) {
         std::vector<int> hmin(M->P, 1 << 30), hmax(M->P, -1);
         SPMVC_HIP(hipMemcpy(tmin.p, hmin.data(), tmin.bytes, hipMemcpyHostToDevice));
         SPMVC_HIP(hipMemcpy(tmax.p, hmax.data(), tmax.bytes, hipMemcpyHostToDevice));
-        k_pattern_t0_range<<<grid_for(M->n_rows, kBlock), kBlock>>>(M->n_rows, M->ids.p, M->id_bytes,
-                                                                   M->T.as<uint8_t>(), tmin.as<int>(), tmax.as<int>());
+        const unsigned g = static_cast<unsigned>(std::min<int64_t>((M->n_rows + kBlock - 1) / kBlock, 1024));
+        k_pattern_t0_range<<<g, kBlock>>>(M->n_rows, M->ids.p, M->id_bytes, M->T.as<uint8_t>(), M->P, tmin.as<int>(),
+                                          tmax.as<int>());
         SPMVC_CHECK_LAUNCH();
         SPMVC_HIP(hipMemcpy(hmin.data(), tmin.p, tmin.bytes, hipMemcpyDeviceToHost));
         SPMVC_HIP(hipMemcpy(hmax.data(), tmax.p, tmax.bytes, hipMemcpyDeviceToHost));
