@@ -408,7 +408,10 @@ spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void *stream,
  * solves of one batch sum in the same order.  The environment variable
  * SPMVC_BATCHED_SPMV="form,chunk" fixes the configuration instead (a form
  * that does not apply falls back to the next).  *form = -1 before any
- * batched solve.
+ * batched solve; *form = -2 when the last cg_solve that asked for batched
+ * kernels (batched 1 or 2, several systems or right-hand sides) solved its
+ * pairs one after another instead, because a matrix is outside what the
+ * batched kernels take (see spmvc_cg_opts.batched).
  */
 spmvc_status spmvc_batched_config(int32_t *form, int32_t *chunk, double *us_per_spmv);
 

@@ -420,7 +420,8 @@ def permute(row_ptr, col, val, perm, stream=None):
 
 def batched_config():
     """The SpMV configuration the last batched cg_solve chose: {"form", "chunk", "us"}
-    (form 0 window-phased, 1 lane groups with rhs pairs, 2 lane groups; -1 before any)."""
+    (form 0 window-phased, 1 lane groups with rhs pairs, 2 lane groups; -1 before any;
+    -2 when that solve took the one-after-another path instead)."""
     f, c, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(load().spmvc_batched_config(ctypes.byref(f), ctypes.byref(c), ctypes.byref(us)))
     return {"form": f.value, "chunk": c.value, "us": us.value}

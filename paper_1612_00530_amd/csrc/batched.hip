@@ -35,6 +35,7 @@
 #include "check.h"
 #include "internal.h"
 #include "lds_window.h"
+#include "reduce.h"
 
 namespace spmvc {
 namespace {
@@ -126,18 +127,6 @@ template <int LPR> __device__ __forceinline__ double rhs_sum(double v) {
     return s;
 }
 
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[kT / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kT / 64; ++i) s += sh[i];
-    return s;
-}
 
 // Sum over a row's pattern entries with value V[0] (k < t0) and with V[1]
 // (t0 <= k < len) of x at the entries' columns.  All MAXW pattern offsets are
@@ -489,7 +478,7 @@ __device__ __forceinline__ void sys_sums(const Batch &b, const SysDesc &d, doubl
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        if (r < b.nrhs) out[r] = block_sum(acc[r]);
+        if (r < b.nrhs) out[r] = block_sum<kT>(acc[r]);
 }
 
 // Element loop of a tile: f(global element index, rhs) for the tile's rows.
@@ -904,6 +893,13 @@ void batched_last_tune(int32_t *form, int32_t *chunk, double *us) {
     *form = g_last_tune.form;
     *chunk = g_last_tune.chunk;
     *us = g_last_tune.us;
+}
+
+// A solve that asked for batched kernels took the one-after-another path
+// instead (form -2 in spmvc_batched_config).
+void batched_note_fallback() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_last_tune = BatchTune{-2, 0, 0.0};
 }
 
 // Is the batched solver able to take these matrices (DIT, value table <= 2, no raw values)?

@@ -33,6 +33,7 @@
 #include <mutex>
 
 #include "internal.h"
+#include "reduce.h"
 
 namespace spmvc {
 namespace {
@@ -47,26 +48,6 @@ struct CgScal {
     int32_t go[2];    // the update step of the iteration (by parity) ran: the p-update must run
     double aux[4];
 };
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum over a block of NT threads; the result is returned to every thread.
-template <int NT> __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[NT / 64];
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < NT / 64; ++i) s += sh[i];
-    return s;
-}
 
 // Sum of partials[0..np) in a fixed order; identical in every block.  Each
 // thread loads eight of its partials at a time (independent loads in flight)
@@ -1189,10 +1170,13 @@ spmvc_status cg_solve_impl(const spmvc_matrix *A, int n_sys, int nrhs, const dou
         SPMVC_HIP(hipStreamSynchronize(s));
         return st;
     }
-    if ((n_sys > 1 || nrhs > 1) && o.batched != 0 && batched_supported(A, n_sys)) {
-        const spmvc_status st = cg_solve_batched(A, n_sys, nrhs, b, x, o, stat, s, o.batched != 1);
-        SPMVC_HIP(hipStreamSynchronize(s));
-        return st;
+    if ((n_sys > 1 || nrhs > 1) && o.batched != 0) {
+        if (batched_supported(A, n_sys)) {
+            const spmvc_status st = cg_solve_batched(A, n_sys, nrhs, b, x, o, stat, s, o.batched != 1);
+            SPMVC_HIP(hipStreamSynchronize(s));
+            return st;
+        }
+        batched_note_fallback();  // reported by spmvc_batched_config (form -2)
     }
     for (int sy = 0; sy < n_sys; ++sy) {
         const spmvc_matrix_s *M = A[sy];

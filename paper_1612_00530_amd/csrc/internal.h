@@ -237,6 +237,7 @@ int64_t cg_noalloc_max_rows();
 // 3 DIT register, plane-marching.
 int kernel_kind(const spmvc_matrix_s *M, int dt);
 bool batched_supported(const spmvc_matrix *A, int n_sys);
+void batched_note_fallback();
 void batched_last_tune(int32_t *form, int32_t *chunk, double *us);
 spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const double *const *b,
                               double *const *x, const spmvc_cg_opts &o, spmvc_cg_stat *stat,

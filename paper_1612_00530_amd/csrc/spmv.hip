@@ -45,6 +45,7 @@
 #include "check.h"
 #include "internal.h"
 #include "lds_window.h"
+#include "reduce.h"
 
 namespace spmvc {
 namespace {
@@ -115,24 +116,10 @@ template <class T> __device__ __forceinline__ T ldg_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
-// Sum over the kBlock threads of a block, in a fixed order; valid in every thread.
-__device__ __forceinline__ double block_sum_256(double v) {
-    __shared__ double sh[kBlock / 64];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
-    return s;
-}
-
 // Writes the block's partial of x.y when the launch asks for it (all threads call).
 __device__ __forceinline__ void emit_dot(const SpmvArgs &a, double part) {
     if (!a.dot) return;
-    const double b = block_sum_256(part);
+    const double b = block_sum<kBlock>(part);
     if (threadIdx.x == 0) a.dot[blockIdx.x] = b;
 }
 

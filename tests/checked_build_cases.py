@@ -62,7 +62,7 @@ def main():
                     for r in range(nrhs):
                         assert rel_err(A, X[:, r], Y[:, r], Yref[:, r]) <= 1e-14, (fmt, mode, nrhs)
             b = oracle.spmv(A, np.ones(A.n_cols))
-            for mode in (0, 1, 2):
+            for mode in (0, 1, 2, 3):
                 st, xs, _ = P.cg_solve(M, torch.from_numpy(b).to(dev), mode=mode)
                 assert st == 0 and oracle.relres(A, b, xs[0].cpu().numpy()) <= 1e-10, (fmt, mode)
             color = gs.greedy_coloring(A)
@@ -70,6 +70,8 @@ def main():
             M.symgs(torch.from_numpy(b).to(dev), xg)
             ref = gs.symgs(A, b, np.zeros(A.n_rows), color)
             assert np.abs(xg.cpu().numpy() - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), fmt
+            st, xn, _ = P.cg_solve_noalloc(M, torch.from_numpy(b).to(dev))
+            assert st == 0 and oracle.relres(A, b, xn.cpu().numpy()) <= 1e-10, fmt
             print("ok", fmt, A.n_rows, flush=True)
     # batched pairs (window-phased and lane-group SpMV forms)
     grids = batched_grids(5, 8, 20, seed=3)

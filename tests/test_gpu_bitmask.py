@@ -188,6 +188,7 @@ def test_cg_every_mode():
     st, xs, stats = P.cg_solve([M], [torch.from_numpy(B).cuda()], nrhs=3)
     torch.cuda.synchronize()
     assert st == 0
+    assert P.batched_config()["form"] == -2  # reported: solved one pair after another
     X = xs[0].cpu().numpy()
     for r in range(3):
         assert oracle.relres(A, B[:, r], X[:, r]) <= 1e-10
