@@ -31,19 +31,22 @@
  *                  with two, a second mask marks the entries holding V[1];
  *                  otherwise every value is stored per row in column order.
  *
- * Around the product: CG (cg_solve: FP64, mixed precision, or preconditioned
- * by one multicolor SymGS sweep; cg_solve_mg: preconditioned by a multigrid
- * V-cycle, the iteration of Table I), SymGS itself (spmv_symgs), and reverse
- * Cuthill-McKee reordering with the matching symmetric permutation
- * (spmv_rcm, spmv_permute; Section V, after Table II).
+ * Around the product: CG (cg_solve: FP64, mixed precision by iterative
+ * refinement or by reliable updates, or preconditioned by one multicolor SymGS
+ * sweep; cg_solve_noalloc: the FP64 CG without any allocation; cg_solve_mg:
+ * preconditioned by a multigrid V-cycle, the iteration of Table I), SymGS
+ * itself (spmv_symgs, spmv_color_order), and reverse Cuthill-McKee
+ * reordering with the matching symmetric permutation (spmv_rcm,
+ * spmv_permute; Section V, after Table II).
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers unless the comment says "host".
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is ordered
  *     on that stream.  spmv, spmv_block and spmv_symgs (after its first
  *     call on a handle, which builds the coloring) are asynchronous;
- *     spmv_compress, spmv_decompress, cg_solve, cg_solve_mg, spmv_rcm and
- *     spmv_permute synchronise `stream` before returning.
+ *     spmv_compress, spmv_decompress, cg_solve, cg_solve_noalloc,
+ *     cg_solve_mg, spmv_color_order, spmv_rcm and spmv_permute synchronise
+ *     `stream` before returning.
  *   - Every call returns an spmvc_status; no C++ exception crosses the ABI.
  *     After a failure spmvc_last_error() gives a thread-local message.
  *   - Indices: rows and columns are 0-based, < 2^31; row_ptr is int64.
