@@ -182,11 +182,30 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) p[i + u * stride_] = r[i + u * str
 // r -= alpha q; partials of r.r.  A breakdown (sigma <= 0 or not finite) stops
 // the solve.  Block 0 records sigma and whether the step ran (go), which the
 // p-update reads: it must not read `done`, which its own block 0 may set.
+// Each thread's first group of r and q is loaded before the scalars and the
+// partial sums are read (it does not depend on alpha), so that the latency of
+// those loads overlaps the latency of the sums; the elements and the order of
+// the r.r sum are those of the plain grid-stride loop (SPMVC_STREAM4N).
 template <class Real, int W>
 __global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__ r, const Real *__restrict__ q,
                                                    const double *sig_part, int n_sig, double *rr_part, CgScal *st,
                                                    int par, int it) {
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    using T = typename Pack<Real, W>::T;
+    T *__restrict__ rw = reinterpret_cast<T *>(r);
+    const T *__restrict__ qw = reinterpret_cast<const T *>(q);
+    const int64_t nw = n / W;
+    const int64_t stride_ = static_cast<int64_t>(gridDim.x) * kRT;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x;
+    T rv[4], qv[4];
+    const bool first = i + 3 * stride_ < nw;
+    if (first) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rv[u] = rw[i + u * stride_];
+            qv[u] = qw[i + u * stride_];
+        }
+    }
     if (st->done) {
         if (lead) st->go[par] = 0;
         return;
@@ -208,28 +227,38 @@ __global__ __launch_bounds__(kRT) void k_cg_update(int64_t n, Real *__restrict__
     }
     const Real alpha = static_cast<Real>(st->rho[par] / sigma);
     double acc = 0.0;
-    using T = typename Pack<Real, W>::T;
-    T *__restrict__ rw = reinterpret_cast<T *>(r);
-    const T *__restrict__ qw = reinterpret_cast<const T *>(q);
-    const int64_t nw = n / W;
-    SPMVC_STREAM4N(nw,
-        T rv[4]; T qv[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) { rv[u] = rw[i + u * stride_]; qv[u] = qw[i + u * stride_]; }
-_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+    if (first) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
             const T ri = rv[u] - alpha * qv[u];
             rw[i + u * stride_] = ri;
             acc += sumsq(ri);
         }
-        ,
+        i += 4 * stride_;
+    }
+    for (; i + 3 * stride_ < nw; i += 4 * stride_) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rv[u] = rw[i + u * stride_];
+            qv[u] = qw[i + u * stride_];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T ri = rv[u] - alpha * qv[u];
+            rw[i + u * stride_] = ri;
+            acc += sumsq(ri);
+        }
+    }
+    for (; i < nw; i += stride_) {
         const T ri = rw[i] - alpha * qw[i];
         rw[i] = ri;
         acc += sumsq(ri);
-    )
+    }
     if (W > 1 && blockIdx.x == 0) {  // the last n mod W elements
-        const int64_t i = nw * W + threadIdx.x;
-        if (i < n) {
-            const Real ri = r[i] - alpha * q[i];
-            r[i] = ri;
+        const int64_t k = nw * W + threadIdx.x;
+        if (k < n) {
+            const Real ri = r[k] - alpha * q[k];
+            r[k] = ri;
             acc += sumsq(ri);
         }
     }
@@ -240,10 +269,29 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
 // rho' = sum of the r.r partials; convergence test; x += alpha p (with the
 // update step's alpha); unless the solve stops here, beta = rho'/rho and
 // p = r + beta p.  x is updated here, not in k_cg_update, so p is read once.
+// As in k_cg_update, each thread's first group of x, r and p is loaded before
+// the scalars and the partial sums are read.
 template <class Real, int W>
 __global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, Real *__restrict__ x, const Real *__restrict__ r,
                                                     Real *__restrict__ p, const double *rr_part, int n_rr,
                                                     CgScal *st, int par, int it) {
+    using T = typename Pack<Real, W>::T;
+    T *__restrict__ xw = reinterpret_cast<T *>(x);
+    const T *__restrict__ rw = reinterpret_cast<const T *>(r);
+    T *__restrict__ pw = reinterpret_cast<T *>(p);
+    const int64_t nw = n / W;
+    const int64_t stride_ = static_cast<int64_t>(gridDim.x) * kRT;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * kRT + threadIdx.x;
+    T xv[4], rv[4], pv[4];
+    const bool first = i + 3 * stride_ < nw;
+    if (first) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xv[u] = xw[i + u * stride_];
+            rv[u] = rw[i + u * stride_];
+            pv[u] = pw[i + u * stride_];
+        }
+    }
     if (!st->go[par]) return;
     const double rho_new = sum_partials<kRT>(rr_part, n_rr);
     const double rho = st->rho[par];
@@ -265,37 +313,52 @@ __global__ __launch_bounds__(kRT) void k_cg_pupdate(int64_t n, Real *__restrict_
         }
     }
     const Real alpha = static_cast<Real>(rho / st->sigma);
-    using T = typename Pack<Real, W>::T;
-    T *__restrict__ xw = reinterpret_cast<T *>(x);
-    const T *__restrict__ rw = reinterpret_cast<const T *>(r);
-    T *__restrict__ pw = reinterpret_cast<T *>(p);
-    const int64_t nw = n / W;
     const int64_t tail = (W > 1 && blockIdx.x == 0) ? nw * W + threadIdx.x : n;  // the last n mod W elements
     if (stop) {
-        SPMVC_STREAM4N(nw,
-            T xv[4]; T pv[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) { xv[u] = xw[i + u * stride_]; pv[u] = pw[i + u * stride_]; }
-_Pragma("unroll") for (int u = 0; u < 4; ++u) xw[i + u * stride_] = xv[u] + alpha * pv[u];
-            ,
-            xw[i] = xw[i] + alpha * pw[i];
-        )
+        if (first) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xw[i + u * stride_] = xv[u] + alpha * pv[u];
+            i += 4 * stride_;
+        }
+        for (; i + 3 * stride_ < nw; i += 4 * stride_) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xv[u] = xw[i + u * stride_];
+                pv[u] = pw[i + u * stride_];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xw[i + u * stride_] = xv[u] + alpha * pv[u];
+        }
+        for (; i < nw; i += stride_) xw[i] = xw[i] + alpha * pw[i];
         if (tail < n) x[tail] = x[tail] + alpha * p[tail];
         return;
     }
     const Real beta = static_cast<Real>(rho_new / rho);
-    SPMVC_STREAM4N(nw,
-        T xv[4]; T rv[4]; T pv[4];
-_Pragma("unroll") for (int u = 0; u < 4; ++u) {
-            xv[u] = xw[i + u * stride_]; rv[u] = rw[i + u * stride_]; pv[u] = pw[i + u * stride_];
-        }
-_Pragma("unroll") for (int u = 0; u < 4; ++u) {
+    if (first) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
             xw[i + u * stride_] = xv[u] + alpha * pv[u];
             pw[i + u * stride_] = rv[u] + beta * pv[u];
         }
-        ,
+        i += 4 * stride_;
+    }
+    for (; i + 3 * stride_ < nw; i += 4 * stride_) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xv[u] = xw[i + u * stride_];
+            rv[u] = rw[i + u * stride_];
+            pv[u] = pw[i + u * stride_];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xw[i + u * stride_] = xv[u] + alpha * pv[u];
+            pw[i + u * stride_] = rv[u] + beta * pv[u];
+        }
+    }
+    for (; i < nw; i += stride_) {
         xw[i] = xw[i] + alpha * pw[i];
         pw[i] = rw[i] + beta * pw[i];
-    )
+    }
     if (tail < n) {
         x[tail] = x[tail] + alpha * p[tail];
         p[tail] = r[tail] + beta * p[tail];
