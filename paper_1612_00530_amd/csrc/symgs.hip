@@ -29,6 +29,7 @@ namespace spmvc {
 namespace {
 
 constexpr int kGsThreads = 256;
+constexpr int kGsTblInts = 2048;  // pattern-offset words staged in LDS (8 KB)
 
 struct GsArgs {
     int64_t n_rows, n_pad;
@@ -46,6 +47,7 @@ struct GsArgs {
     const int32_t *esc_col;
     const double *esc_val;
     int64_t n_esc;
+    int32_t P;
     double V[kMaxK];
     // BMASK: displacement list, per-row masks (4 or 8 bytes)
     const int32_t *bm_d;
@@ -161,17 +163,53 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_color(GsArgs a, const int3
 // the row's length: every lane issues its MAXW gathers at once (entries past
 // the row's length read x_i and take weight 0), then the FMAs.  The generic
 // loop above waits for each pattern offset and each gather in turn.
-template <int MAXW>
+//
+// A color launch is short (one eighth of the rows), so its time is its chain
+// of dependent loads.  Everything that does not depend on the row's pattern
+// is issued first, together: the row's pattern word and index, b_i, (TBL) the
+// whole pattern table, which is then staged in LDS so that the offsets come
+// from LDS rather than from a second global round trip, and last the done
+// flag.  The chain is then: those loads, a barrier, the offsets, the gathers.
+template <int MAXW, bool TBL>
 __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_t *__restrict__ rows, int64_t r0,
                                                           const uint32_t *__restrict__ meta, int64_t n,
                                                           const double *__restrict__ b, double *x, const int *skip) {
-    if (skip && *skip) return;
+    constexpr int kQ = kGsTblInts / kGsThreads;  // table words per thread
+    __shared__ int32_t s_off[TBL ? kGsTblInts : 1];
+    __shared__ uint8_t s_len[TBL ? kGsTblInts : 1];
     const int64_t t = xcd_block() * kGsThreads + threadIdx.x;
-    if (t >= n) return;
-    const int64_t i = rows ? rows[t] : r0 + t;
-    // the row's pattern ID and T_i[0], stored in color order: read alongside
-    // the row index rather than after it
-    const uint32_t mw = meta[t];
+    const bool live = t < n;
+    int64_t i = 0;
+    uint32_t mw = 0;
+    double bi = 0.0;
+    if (live) {
+        mw = meta[t];
+        i = rows ? rows[t] : r0 + t;
+        bi = b[i];
+    }
+    const int tn = a.P * a.width;
+    int32_t tv[kQ];
+    uint8_t lv[kQ];
+    if constexpr (TBL) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int k = q * kGsThreads + static_cast<int>(threadIdx.x);
+            tv[q] = k < tn ? a.pat_off[k] : 0;
+            lv[q] = k < a.P ? a.pat_len[k] : 0;
+        }
+    }
+    // the flag last, so that waiting for it does not hold back the loads above
+    const int done = skip ? *skip : 0;
+    if constexpr (TBL) {
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int k = q * kGsThreads + static_cast<int>(threadIdx.x);
+            if (k < tn) s_off[k] = tv[q];
+            if (k < a.P) s_len[k] = lv[q];
+        }
+        __syncthreads();
+    }
+    if (done || !live) return;
     const uint32_t id = mw & 0xFFFFFFu;
     double s = 0.0, d = 0.0;
     if (id == 0xFFFFFFu) {  // escape row
@@ -182,12 +220,19 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
                 s = fma(v, x[in_bounds<int64_t>(j, a.n_rows)], s);
         });
     } else {
-        const int32_t *pr = a.pat_off + static_cast<int64_t>(id) * a.width;
-        const int len = a.pat_len[id];
+        const int64_t pb = static_cast<int64_t>(id) * a.width;
+        const int len = TBL ? s_len[in_bounds<int>(static_cast<int>(id), a.P)] : a.pat_len[id];
         const int t0 = a.K >= 2 ? static_cast<int>(mw >> 24) : len;
         int32_t off[MAXW];
 #pragma unroll
-        for (int k = 0; k < MAXW; ++k) off[k] = k < a.width ? pr[k] : 0;
+        for (int k = 0; k < MAXW; ++k) {
+            if (k >= a.width)
+                off[k] = 0;
+            else if constexpr (TBL)
+                off[k] = s_off[in_bounds<int64_t>(pb + k, static_cast<int64_t>(tn))];
+            else
+                off[k] = a.pat_off[pb + k];
+        }
         double xv[MAXW];
 #pragma unroll
         for (int k = 0; k < MAXW; ++k) xv[k] = x[in_bounds<int64_t>(i + (k < len ? off[k] : 0), a.n_rows)];
@@ -199,7 +244,7 @@ __global__ __launch_bounds__(kGsThreads) void k_symgs_dit(GsArgs a, const int32_
             s = diag ? s : fma(v, xv[k], s);
         }
     }
-    x[i] = (b[i] - s) / d;
+    x[i] = (bi - s) / d;
 }
 
 // meta[t] = (T_i[0] << 24) | ID of row rows[t] (ID 0xFFFFFF: escape row).
@@ -240,6 +285,7 @@ GsArgs gs_args(const spmvc_matrix_s *M) {
     a.esc_col = M->esc_col.as<int32_t>();
     a.esc_val = M->esc_val.as<double>();
     a.n_esc = M->n_esc;
+    a.P = static_cast<int32_t>(M->P);
     for (int c = 0; c < kMaxK; ++c) a.V[c] = M->V[c];
     a.bm_d = M->bm_d.as<int32_t>();
     a.bm_mask = M->bm_mask.p;
@@ -346,6 +392,8 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
     const int C = M->gs_n_colors;
     const int32_t *rows = M->gs_contig ? nullptr : M->gs_rows.as<int32_t>();
     const bool dit27 = gs_dit27(M);
+    // the pattern table fits the LDS staging area
+    const bool tbl = M->P * static_cast<int64_t>(M->width) <= kGsTblInts && M->P <= kGsTblInts;
     int last = -1;  // color of the previous launch
     for (int sw = 0; sw < sweeps; ++sw)
         for (int q = 0; q < 2 * C; ++q) {
@@ -360,8 +408,12 @@ void launch_symgs(const spmvc_matrix_s *M, const double *b, double *x, int sweep
             if (cnt == 0) continue;
             const unsigned g = grid_for(cnt, kGsThreads, 0x7fffffff);
             const int32_t *rc = rows ? rows + r0 : nullptr;
-            if (dit27)
-                k_symgs_dit<27><<<g, kGsThreads, 0, s>>>(a, rc, r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x, skip);
+            if (dit27 && tbl)
+                k_symgs_dit<27, true><<<g, kGsThreads, 0, s>>>(a, rc, r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x,
+                                                               skip);
+            else if (dit27)
+                k_symgs_dit<27, false><<<g, kGsThreads, 0, s>>>(a, rc, r0, M->gs_meta.as<uint32_t>() + r0, cnt, b, x,
+                                                                skip);
             else
                 k_symgs_color<<<g, kGsThreads, 0, s>>>(a, rc, r0, cnt, b, x, skip);
             SPMVC_CHECK_LAUNCH();
