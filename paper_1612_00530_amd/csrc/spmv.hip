@@ -946,8 +946,13 @@ __global__ __launch_bounds__(kBlock) void k_dit_reg_pairs(SpmvArgs a, const doub
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t pr = blockIdx.y;  // right-hand-side pair
     const double *xp = X + 2 * pr;
+    if (blockIdx.x >= a.n_main_blocks) {  // escape rows: one lane per row, this pair, from global memory
+        escape_row<double, 2>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, 2, xp, ldx,
+                              Y + 2 * pr, ldy);
+        return;
+    }
     D2 *xs = reinterpret_cast<D2 *>(smem);
-    const int64_t r0 = xcd_tile(blockIdx.x, gridDim.x, a.n_xcd) * (kBlock * RPT);
+    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * (kBlock * RPT);
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     uint32_t idv[RPT];
     int t0v[RPT];
@@ -1086,10 +1091,15 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NR = 2 * LPR;          // right-hand sides
     constexpr int PASSES = kWinRows / (kBlock / LPR);
+    if (blockIdx.x >= a.n_main_blocks) {  // escape rows: one lane per row, all right-hand sides, from global memory
+        escape_row<double, NR>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, NR, X, NR,
+                               Y, NR);
+        return;
+    }
     const int NW = a.n_win;
     double *xs = reinterpret_cast<double *>(smem);
     const uint4 *tab_s = reinterpret_cast<const uint4 *>(smem + a.lds_x_bytes);
-    const int64_t r0 = xcd_tile(blockIdx.x, gridDim.x, a.n_xcd) * kWinRows;
+    const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * kWinRows;
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     const int lr = threadIdx.x / LPR;           // row within a pass
     const int rp = (threadIdx.x % LPR) * 2;     // this lane's right-hand-side pair
@@ -1436,7 +1446,9 @@ bool launch_block_win(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     a.lds_x_bytes = static_cast<int32_t>(xb);
     a.reg_tab = reinterpret_cast<const uint16_t *>(p.bw_tab.p);
     const size_t shmem = static_cast<size_t>(xb + tb);
-    const unsigned grid = static_cast<unsigned>((M->n_rows + kWinRows - 1) / kWinRows);
+    // the row tiles, then the escape rows' blocks (same launch)
+    a.n_main_blocks = static_cast<unsigned>((M->n_rows + kWinRows - 1) / kWinRows);
+    const unsigned grid = a.n_main_blocks + escape_blocks(M);
     const double *xp = static_cast<const double *>(X);
     double *yp = static_cast<double *>(Y);
     if (nrhs == 2)
@@ -1446,12 +1458,6 @@ bool launch_block_win(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     else
         k_dit_block_win<4><<<grid, kBlock, shmem, s>>>(a, xp, yp);
     SPMVC_CHECK_LAUNCH();
-    const unsigned eb = escape_blocks(M);
-    if (eb) {
-        a.n_main_blocks = 0;
-        k_spmv_lanes<SPMVC_FMT_DIT, double, uint8_t, false, 1, 1><<<eb, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
-        SPMVC_CHECK_LAUNCH();
-    }
     return true;
 }
 
@@ -1479,8 +1485,9 @@ bool launch_pairs(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, 
     a.reg_tab = p.reg_tab128.as<uint16_t>();
     a.lds_x_bytes = 16 * (p.zero_base + p.rows);
     const size_t shmem = a.lds_x_bytes + static_cast<size_t>(M->P) * kRegTw * 2;
-    const unsigned tiles = static_cast<unsigned>((M->n_rows + p.rows - 1) / p.rows);
-    const dim3 grid(tiles, static_cast<unsigned>(nrhs / 2));
+    // the row tiles, then the escape rows' blocks (same launch), for each pair
+    a.n_main_blocks = static_cast<unsigned>((M->n_rows + p.rows - 1) / p.rows);
+    const dim3 grid(a.n_main_blocks + escape_blocks(M), static_cast<unsigned>(nrhs / 2));
     const double *xp = static_cast<const double *>(X);
     double *yp = static_cast<double *>(Y);
     const bool w27 = M->width <= 27;
@@ -1505,13 +1512,6 @@ bool launch_pairs(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void *X, 
 #undef SPMVC_PAIRS_R
 #undef SPMVC_PAIRS_W
     SPMVC_CHECK_LAUNCH();
-    // escape rows: one lane per row, all right-hand sides
-    const unsigned eb = escape_blocks(M);
-    if (eb) {
-        a.n_main_blocks = 0;
-        k_spmv_lanes<SPMVC_FMT_DIT, double, uint8_t, false, 1, 1><<<eb, kBlock, 0, s>>>(a, nrhs, xp, ldx, yp, ldy);
-        SPMVC_CHECK_LAUNCH();
-    }
     return true;
 }
 
