@@ -16,9 +16,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum over a block of NT threads: each wavefront's sum, then the NT / 64
 // wavefront sums in wavefront order; the result in every thread.  Every
-// thread of the block must call it.
-template <int NT> __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[NT / 64];
+// thread of the block must call it.  sh: NT / 64 doubles of LDS for the
+// wavefront sums -- the caller's (a buffer it is done with: the first barrier
+// below orders every earlier access to it before these writes), so that a
+// kernel with only dynamic LDS keeps its LDS base at 0.
+template <int NT> __device__ __forceinline__ double block_sum(double v, double *sh) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     __syncthreads();
@@ -28,6 +30,12 @@ template <int NT> __device__ __forceinline__ double block_sum(double v) {
 #pragma unroll
     for (int i = 0; i < NT / 64; ++i) s += sh[i];
     return s;
+}
+
+// The same with a static LDS array for the wavefront sums.
+template <int NT> __device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[NT / 64];
+    return block_sum<NT>(v, sh);
 }
 
 }  // namespace spmvc

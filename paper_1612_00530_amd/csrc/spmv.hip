@@ -23,9 +23,14 @@
 // entries, 64 bytes of LDS offsets) in registers, so its LDS reads are
 // independent and issue back to back.  Per entry it costs one add (offset +
 // row), one LDS read and one add (one FMA where the value must be selected per
-// lane).  Rows shorter than the table width read a zero window in LDS for the
-// missing entries (exact when every table value is finite); with every value
-// raw, a row's values are read up to its 64-row slice's width (zero padding).
+// lane).  Entries past a row's length (rows shorter than the table width) read
+// zeros (exact when every table value is finite): in FP64 they carry the
+// offset 0xFFFF and the kernel reads min(row + offset, Z), Z a single zero
+// element after the windows -- one more VALU operation per entry instead of a
+// zero window of one element per row, a fifth of the block's LDS, so that more
+// blocks are resident; FP32 (and the marching form) keep the zero window.  With
+// every value raw, a row's values are read up to its 64-row slice's width
+// (zero padding).
 // k_dit_march is its plane-marching form: a block walks one row tile through
 // consecutive planes and stages one new window per step.
 //
@@ -78,9 +83,10 @@ struct SpmvArgs {
     int32_t win_base[kMaxWindows];
     const uint16_t *tab; // [P][width+1]: len, then LDS element indices
     int32_t tab_elems;
-    int32_t zero_base, zero_len;   // register kernel: zero window
+    int32_t zero_base, zero_len;   // zeros after the windows: one element (FP64 register kernel) or
+                                   // one per row (the other register-table kernels)
     const uint16_t *reg_tab;       // [P][kRegTw]: len, then LDS byte offsets
-    int32_t lds_x_bytes;           // bytes of windows + zero window (16-byte multiple)
+    int32_t lds_x_bytes;           // bytes of the windows (+ zero window), 16-byte multiple
     int32_t n_xcd;                 // XCDs the blocks are spread over (tile mapping)
     int32_t async_lds;             // x is 16-byte aligned: stage windows with direct LDS loads
     int32_t bw_split;              // window-phased block SpMV: records split into value runs
@@ -120,6 +126,13 @@ template <class T> __device__ __forceinline__ T ldg_stream(const T *p) {
 __device__ __forceinline__ void emit_dot(const SpmvArgs &a, double part) {
     if (!a.dot) return;
     const double b = block_sum<kBlock>(part);
+    if (threadIdx.x == 0) a.dot[blockIdx.x] = b;
+}
+
+// The same with the wavefront sums in the caller's LDS (a buffer it is done with).
+__device__ __forceinline__ void emit_dot(const SpmvArgs &a, double part, double *sh) {
+    if (!a.dot) return;
+    const double b = block_sum<kBlock>(part, sh);
     if (threadIdx.x == 0) a.dot[blockIdx.x] = b;
 }
 
@@ -274,7 +287,7 @@ __device__ __forceinline__ double direct_row(const SpmvArgs &a, int64_t row, int
     return a.dot ? static_cast<double>(x[row * ldx]) * static_cast<double>(acc[0]) : 0.0;
 }
 
-// Load the block's x windows (and the zero window) into LDS.  Each window is a
+// Load the block's x windows (and a zero window, if any) into LDS.  Each window is a
 // contiguous range of x.  Interior windows are copied with direct
 // global-to-LDS loads (16 bytes per lane, no register round trip), so every
 // load of the block is in flight at once; windows that reach past either end
@@ -440,11 +453,11 @@ __device__ __forceinline__ void load_tile_meta(const SpmvArgs &a, const Real *__
 }
 
 // The rows of one tile, x windows already in LDS at `buf` (byte base of the
-// windows + zero window), pattern rows at `tab`.  Adds the tile's x.y to dotc:
+// windows), pattern rows at `tab`.  Adds the tile's x.y to dotc:
 // with EARLY_X the row's x comes from xrow (loaded with the metadata),
 // otherwise it is read when needed -- from the windows at self_off when one
 // holds it, else from x -- so that no register holds it through the tile.
-template <class Real, int KK, int RPT, int MAXW, bool EARLY_X = true>
+template <class Real, int KK, int RPT, int MAXW, bool EARLY_X = true, bool ZEL = false>
 __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char *buf, const uint4 *tab, int64_t r0,
                                          int rel_end, const uint32_t (&idv)[RPT], const int (&t0v)[RPT],
                                          const Real (&xrow)[RPT], Real v0, Real v1, Real *__restrict__ y,
@@ -481,17 +494,31 @@ __device__ __forceinline__ void reg_tile(const SpmvArgs &a, const unsigned char 
         }
         if (!active) continue;
         const uint32_t relb = static_cast<uint32_t>(rel) * sizeof(Real);
+        // ZEL: LDS addresses of the buffer, of this row's slot and of the zero element
+        typedef const __attribute__((address_space(3))) unsigned char lds_byte;
+        const uint32_t bufa = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_byte *)buf));
+        const uint32_t rowa = bufa + relb, zeroa = bufa + static_cast<uint32_t>(a.zero_base) * sizeof(Real);
         Real acc = Real(0);
         auto xat = [&](int k) -> Real {
             const uint32_t word = w[(k + 1) >> 1];
             const uint32_t off = ((k + 1) & 1) ? (word >> 16) : (word & 0xFFFFu);
-            return *reinterpret_cast<const Real *>(buf + in_bounds<uint32_t>(relb + off, a.lds_x_bytes));
+            if constexpr (ZEL) {
+                // entries past the row's length (offset 0xFFFF) read the zero element.
+                // The minimum is taken of LDS addresses (row start with the buffer's
+                // base already added), so an entry costs an add and a minimum.
+                const uint32_t ad = min(rowa + off, zeroa);
+                (void)in_bounds<uint32_t>(ad - bufa, a.lds_x_bytes);
+                return *(const __attribute__((address_space(3))) Real *)(static_cast<uintptr_t>(ad));
+            } else {
+                // entries past the length point at the row's slot in a zero window
+                return *reinterpret_cast<const Real *>(buf + in_bounds<uint32_t>(relb + off, a.lds_x_bytes));
+            }
         };
         if constexpr (KK == 0) {
             // Raw values up to the width of the row's 64-row slice (the same for
             // every lane of the wave; the slice's padding is zero): these loads
             // do not wait for the pattern row.  Entries past the row's length
-            // meet the zero window, so they add 0 * 0.
+            // read zeros, so they add 0 * 0.
             const Real *raw = static_cast<const Real *>(a.raw);
             const int64_t s0 = a.raw_slice[row / kSlice];
             const int sw = static_cast<int>((a.raw_slice[row / kSlice + 1] - s0) / kSlice);
@@ -544,23 +571,28 @@ template <class Real, int KK> __device__ __forceinline__ void value_pair(const S
     }
 }
 
-// With one or two rows per thread a block of the 27-point stencil takes about
-// 23 KB of LDS (three plane windows, the zero window, the table), so seven
-// blocks fit a CU; asking for seven waves per SIMD keeps registers from being
-// the tighter limit (at most 72 VGPRs instead of 80, no spills).  With raw
-// values (KK = 0) a row also holds its values in registers: six waves (80
-// VGPRs) keep those from spilling, and six blocks is what the LDS allows there.
+// With one or two rows per thread an FP64 block of the 27-point stencil takes
+// about 19 KB of LDS (three plane windows, the zero element, the table), so
+// eight blocks fit a CU by LDS; asking for seven waves per SIMD keeps registers
+// from spilling (at most 72 VGPRs instead of 80).  With three rows per thread
+// (768 rows, 25 KB) six blocks fit, six waves per SIMD: at 104^3 the whole
+// grid is then resident at once.  With raw values (KK = 0) a row also holds its values in registers:
+// six waves (80 VGPRs) keep those from spilling.
 template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
 __global__ __launch_bounds__(kBlock, (KK == 0 && RPT <= 3) ? 6 : (RPT <= 2 ? 7 : (RPT == 3 ? 6 : 1))) void k_dit_reg(SpmvArgs a,
                                                                                       const Real *__restrict__ x,
                                                                                       Real *__restrict__ y) {
+    // only dynamic LDS (the dot product's wavefront sums reuse the windows), so
+    // that LDS addresses are the buffer offsets themselves
+    extern __shared__ __align__(16) unsigned char smem[];
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
-        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
-                                        1, x, 1, y, 1));
+        emit_dot(a,
+                 escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, 1,
+                                     x, 1, y, 1),
+                 reinterpret_cast<double *>(smem));
         return;
     }
-    extern __shared__ __align__(16) unsigned char smem[];
     Real *xs = reinterpret_cast<Real *>(smem);
     const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * (kBlock * RPT);
     double dotc = 0.0;
@@ -579,8 +611,9 @@ __global__ __launch_bounds__(kBlock, (KK == 0 && RPT <= 3) ? 6 : (RPT <= 2 ? 7 :
     const uint4 *tab = TAB_LDS ? tab_s : reinterpret_cast<const uint4 *>(a.reg_tab);
     Real v0, v1;
     value_pair<Real, KK>(a, v0, v1);
-    reg_tile<Real, KK, RPT, MAXW, false>(a, smem, tab, r0, kBlock * RPT, idv, t0v, xrow, v0, v1, y, dotc, x);
-    emit_dot(a, dotc);
+    reg_tile<Real, KK, RPT, MAXW, false, sizeof(Real) == 8>(a, smem, tab, r0, kBlock * RPT, idv, t0v, xrow, v0, v1, y,
+                                                           dotc, x);
+    emit_dot(a, dotc, reinterpret_cast<double *>(smem));
 }
 
 // ---- DIT, plane-marching register kernel ------------------------------------------
@@ -597,13 +630,15 @@ __global__ __launch_bounds__(kBlock, (KK == 0 && RPT <= 3) ? 6 : (RPT <= 2 ? 7 :
 // that phase, so the inner loop is the register kernel's (reg_tile).
 template <class Real, int KK, bool TAB_LDS, int RPT, int MAXW>
 __global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__restrict__ x, Real *__restrict__ y) {
+    extern __shared__ __align__(16) unsigned char smem[];  // only dynamic LDS, as in k_dit_reg
     if (a.skip && *a.skip) return;
     if (blockIdx.x >= a.n_main_blocks) {
-        emit_dot(a, escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x,
-                                        1, x, 1, y, 1));
+        emit_dot(a,
+                 escape_row<Real, 1>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, 1,
+                                     x, 1, y, 1),
+                 reinterpret_cast<double *>(smem));
         return;
     }
-    extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kRows = kBlock * RPT;
     Real *xs = reinterpret_cast<Real *>(smem);
     const int64_t ord = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd);
@@ -613,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__
     const int64_t z_beg = zc * a.m_C;
     const int64_t z_end = z_beg + a.m_C < a.m_nz ? z_beg + a.m_C : a.m_nz;
     const int L = a.m_L, NB = a.m_NB;
-    // zero window and the per-phase pattern tables
+    // zero window (if any) and the per-phase pattern tables
     for (int e = threadIdx.x; e < a.zero_len; e += kBlock) xs[a.zero_base + e] = Real(0);
     const int tab_u4 = a.P * (kRegTw * 2 / 16);  // uint4 per phase
     const uint4 *tab_all = reinterpret_cast<const uint4 *>(a.reg_tab);
@@ -690,7 +725,8 @@ __global__ __launch_bounds__(kBlock) void k_dit_march(SpmvArgs a, const Real *__
         const uint4 *tab = tab_all + static_cast<int64_t>(z % NB) * tab_u4;
         reg_tile<Real, KK, RPT, MAXW>(a, smem, tab, r0, rel_end, idv, t0v, xrow, v0, v1, y, dotc);
     }
-    emit_dot(a, dotc);
+    // the last plane stages nothing further: no copy into LDS is in flight here
+    emit_dot(a, dotc, reinterpret_cast<double *>(smem));
 }
 
 // The value of the first active lane, as a wavefront-uniform (scalar) value.
@@ -1289,9 +1325,9 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
     if (rv > 0) {
         const bool f64 = sizeof(Real) == 8;
         a.zero_base = p.zero_base;
-        a.zero_len = p.rows;
+        a.zero_len = f64 ? 1 : p.rows;  // FP64: one zero element; FP32: a zero window
         a.reg_tab = f64 ? p.reg_tab64.as<uint16_t>() : p.reg_tab32.as<uint16_t>();
-        const int x_bytes = static_cast<int>(sizeof(Real)) * (p.zero_base + p.rows);
+        const int x_bytes = static_cast<int>(sizeof(Real)) * (p.zero_base + a.zero_len);
         a.lds_x_bytes = (x_bytes + 15) & ~15;
         const int rpt = p.rows / kBlock;
         const bool w27 = M->width <= 27;  // the 27-point stencil: no padded step
@@ -1716,13 +1752,13 @@ static void build_march_plan(spmvc_matrix_s *M, LdsPlan &p, const std::vector<st
                 r[0] = reg_row_head(M, q);
                 const bool rev = M->K >= 1;
                 for (int k = 0; k < kRegW; ++k) {
-                    int64_t e = NB * L;  // zero window
+                    uint16_t off = static_cast<uint16_t>(NB * L * es);  // past the length: the zero window
                     if (k < Lq) {
                         const int64_t d = M->h_pat_off[static_cast<size_t>(q) * W + (rev ? Lq - 1 - k : k)];
                         const int w = window_of(d);
-                        e = ((ph + w) % NB) * L + (d - lo[w]);
+                        off = static_cast<uint16_t>((((ph + w) % NB) * L + (d - lo[w])) * es);
                     }
-                    r[1 + k] = static_cast<uint16_t>(e * es);
+                    r[1 + k] = off;
                 }
             }
         DevBuf &dst = es == 8 ? p.m_tab64 : p.m_tab32;
@@ -2012,9 +2048,13 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
     p.total = static_cast<int32_t>(total);
     p.n_win = static_cast<int>(win.size());
 
-    // register-kernel table: [len, byte offset...] with a zero window after the x windows
-    // (per dtype: a value finite in FP64 can be infinite in FP32, and an
-    // infinite table value times the zero window's 0 would give NaN)
+    // register-kernel table: [len, byte offset...] of the x windows; entries past
+    // the length read zeros after the windows: FP64 one zero element (the
+    // kernel clamps their offset 0xFFFF to it: one more VALU operation per
+    // entry, a fifth less LDS per block), FP32 a zero window of one element per
+    // row (the FP32 kernel spends its time on VALU, not on LDS capacity).  The
+    // values must be finite (per dtype: a value finite in FP64 can be infinite
+    // in FP32, and an infinite table value times 0 would give NaN)
     p.v_finite = true;
     for (int c = 0; c < M->K; ++c)
         p.v_finite = p.v_finite && (dt == SPMVC_F32 ? std::isfinite(M->V32[c]) : std::isfinite(M->V[c]));
@@ -2025,10 +2065,11 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
         std::memcpy(&bc, &M->V[c], 8);
         p.v_same_lo = p.v_same_lo && (static_cast<uint32_t>(b0) == static_cast<uint32_t>(bc));
     }
-    const int64_t x_elems = total + rows;  // windows + zero window
+    const int64_t x_elems = total + 1;  // FP64: the windows and the zero element
     const int64_t x_bytes64 = ((x_elems * 8) + 15) & ~int64_t(15);
+    const int64_t x_bytes32 = (total + rows) * 4;  // FP32: the windows and the zero window
     const bool rows_ok = rows == 256 || rows == 512 || rows == 768 || rows == 1024 || rows == 2048;
-    if (rows_ok && W <= kRegW && x_bytes64 <= kLdsBudgetBytes && x_elems * 8 <= 65535) {
+    if (rows_ok && W <= kRegW && x_bytes64 <= kLdsBudgetBytes && x_elems * 8 <= 65535 && x_bytes32 <= 65535) {
         const int64_t reg_tab_bytes = static_cast<int64_t>(M->P) * kRegTw * 2;
         p.zero_base = static_cast<int32_t>(total);
         for (int es : {8, 4}) {
@@ -2040,9 +2081,12 @@ void build_lds_plan(spmvc_matrix_s *M, int dt, int rows) {
                 // dictionary kernels take the entries in reverse canonical order
                 const bool rev = M->K >= 1;
                 for (int k = 0; k < kRegW; ++k) {
+                    // entries past the length: FP64 0xFFFF, which the kernel clamps to
+                    // the zero element; FP32 the row's slot in the zero window
                     const int src = rev ? L - 1 - k : k;
-                    const int64_t e = k < L ? lds_index(M->h_pat_off[static_cast<size_t>(q) * W + src]) : total;
-                    r[1 + k] = static_cast<uint16_t>(e * es);
+                    r[1 + k] = k < L ? static_cast<uint16_t>(
+                                           lds_index(M->h_pat_off[static_cast<size_t>(q) * W + src]) * es)
+                                     : (es == 8 ? uint16_t(0xFFFF) : static_cast<uint16_t>(total * es));
                 }
             }
             DevBuf &dst = es == 8 ? p.reg_tab64 : p.reg_tab32;
