@@ -50,20 +50,21 @@ struct CgScal {
 };
 
 // Sum of partials[0..np) in a fixed order; identical in every block.  Each
-// thread loads eight of its partials at a time (independent loads in flight)
-// before adding them in order: an SpMV leaves thousands of partials, and one
+// thread adds its partials i, i + NT, i + 2 NT, ... in that order, loading
+// sixteen of them at a time (independent loads in flight, the last batch
+// predicated): an SpMV can leave over ten thousand partials, and one
 // dependent load per partial would make this sum a chain of cache round trips.
 template <int NT> __device__ __forceinline__ double sum_partials(const double *partials, int np) {
+    constexpr int B = 16;
     double s = 0.0;
-    int i = threadIdx.x;
-    for (; i + 7 * NT < np; i += 8 * NT) {
-        double v[8];
+    for (int i0 = threadIdx.x; i0 < np; i0 += B * NT) {
+        double v[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = partials[i + u * NT];
+        for (int u = 0; u < B; ++u) v[u] = i0 + u * NT < np ? partials[i0 + u * NT] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+        for (int u = 0; u < B; ++u)
+            if (i0 + u * NT < np) s += v[u];
     }
-    for (; i < np; i += NT) s += partials[i];
     return block_sum<NT>(s);
 }
 

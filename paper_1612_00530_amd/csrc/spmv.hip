@@ -1294,6 +1294,12 @@ void launch_direct_nr(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     SPMVC_CHECK_LAUNCH();
 }
 
+// Register tiles above which a launch with the dot product takes the marching
+// form (where the plan has one): measured at 192^3, FP64 CG 36.2 ms with
+// 13,824 register tiles of 512 rows, 35.2 ms with the marching form's 1,009
+// blocks; at 104^3 the 1,465 tiles of 768 rows are the faster choice.
+constexpr int64_t kDotMaxTiles = 8192;
+
 // Which register-kernel variant fits the matrix: 0 = none, else KK + 1.
 int reg_variant(const spmvc_matrix_s *M, int dt) {
     const LdsPlan &p = M->plan[dt];
@@ -1331,7 +1337,12 @@ unsigned launch_lds(const spmvc_matrix_s *M, SpmvArgs a, const void *x, void *y,
         a.lds_x_bytes = (x_bytes + 15) & ~15;
         const int rpt = p.rows / kBlock;
         const bool w27 = M->width <= 27;  // the 27-point stencil: no padded step
-        if (M->lds_mode[dt] == 2 && p.march) {
+        // With the dot product (CG), each block leaves a partial that every block
+        // of the next kernel sums: past kDotMaxTiles register tiles that sum
+        // costs more than the register form saves, and the marching form of the
+        // same plan (fewer, longer-lived blocks) is taken instead.
+        const bool many_partials = a.dot && M->lds_mode[dt] == 1 && a.n_main_blocks > kDotMaxTiles;
+        if ((M->lds_mode[dt] == 2 || many_partials) && p.march) {
             a.m_S = p.m_S;
             a.m_nz = p.m_nz;
             a.m_lo0 = p.m_lo0;
