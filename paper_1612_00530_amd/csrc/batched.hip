@@ -90,6 +90,7 @@ struct Batch {
     int32_t tab_ints;   // largest pattern table (P * width entries)
     int32_t win_x_bytes;  // window-phased SpMV: LDS bytes of the largest window (0: not used)
     int32_t win_tab_bytes; // ... and of the largest entry-list table
+    int32_t all_split;     // every system's records are split into value runs (four rhs per lane)
     int32_t n_xcd;      // XCDs the blocks are dispatched over (tile mapping of the SpMV)
     // SpMV configuration (tuned per batch shape): 0 = window-phased (where it
     // applies), 1 = lane groups with two right-hand sides per lane (16-byte
@@ -322,18 +323,21 @@ __device__ __forceinline__ void bwin_group(uint4 e, const unsigned char *xrow, u
     }
 }
 
-// Window-phased form of k_bspmv for nrhs = 2 * LPR (2, 4 or 8): the tile's
+// Window-phased form of k_bspmv for nrhs = Q * LPR (2, 4 or 8): the tile's
 // rows of one x window at a time -- whole rows of the row-interleaved block,
 // a contiguous range -- are copied into LDS, and every row adds the products
 // of its entries that fall in that window (per pattern and window a record of
 // the count and the entries, read four entries at a time, the last cnt mod 4
-// one by one).  One lane per right-hand-side pair, LPR lanes per row; each
-// product is weighted by its value-table entry as it is added.
-template <int LPR>
+// one by one).  LPR lanes per row, each taking Q consecutive right-hand sides:
+// Q = 2, or Q = 4 when every system's records are split into value runs (a
+// record then serves twice the right-hand sides per read and loop set-up).
+// Without split records each product is weighted by its value-table entry as
+// it is added.
+template <int LPR, int Q = 2>
 __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restrict__ Pin,
                                                   double *__restrict__ Qout, double *part, int with_dot) {
     extern __shared__ __align__(16) unsigned char wsm[];
-    constexpr int NR = 2 * LPR;
+    constexpr int NR = Q * LPR;
     constexpr int PASSES = kT / (kT / LPR);  // = LPR
     const int tile = chunk_tile(blockIdx.x, gridDim.x, b.n_xcd, b.chunk);
     const int s = b.tile_sys[tile];
@@ -345,7 +349,7 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
     const int64_t r0 = static_cast<int64_t>(tile - d.tile0) * kT;  // system-local first row
     const uint32_t esc = d.id_bytes == 1 ? 0xFFu : (d.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     const int lr = threadIdx.x / LPR;
-    const int rp = (threadIdx.x % LPR) * 2;
+    const int rp = (threadIdx.x % LPR) * Q;
     const bool lane_on = rp < b.nrhs;
     uint32_t idv[PASSES];
     int t0v[PASSES];
@@ -363,9 +367,11 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
         for (int e = threadIdx.x; e < n16; e += kT) dst[e] = src[e];
     }
     const double v0 = d.V[0], v1 = d.K >= 2 ? d.V[1] : d.V[0];
-    double acc[PASSES][2];
+    double acc[PASSES][Q];
 #pragma unroll
-    for (int ps = 0; ps < PASSES; ++ps) acc[ps][0] = acc[ps][1] = 0.0;
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[ps][q] = 0.0;
     const double *sysP = Pin + d.row0 * NR;  // the system's rows
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int w = 0; w < NW; ++w) {
@@ -396,11 +402,11 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
             const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
             const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
             const uint32_t lim = static_cast<uint32_t>(d.bw_len[w] - rel);  // window rows from this row on
-            if (d.bw_split) {
-                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps][0],
-                                      acc[ps][1]);
+            if (Q == 4 || d.bw_split) {  // Q = 4 is launched only with split records
+                win_row_split<NR * 8, Q>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps]);
                 continue;
             }
+            if constexpr (Q != 2) continue;
             const int cnt = static_cast<int>(rec[0].x);
             int k0 = 0;
             for (; k0 + 4 <= cnt; k0 += 4)
@@ -417,15 +423,17 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
             }
         }
     }
-    double dotc[2] = {0.0, 0.0};
+    double dotc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) dotc[q] = 0.0;
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
         const int64_t lrow = r0 + ps * (kT / LPR) + lr;
         if (lrow >= d.n) continue;
-        double q0, q1;
+        double qv[Q];
         if (idv[ps] != esc) {
-            q0 = acc[ps][0];
-            q1 = acc[ps][1];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) qv[q] = acc[ps][q];
         } else {
             // escape row: plain CSR gathers from global memory
             int64_t lo = 0, hi = d.n_esc;
@@ -433,30 +441,36 @@ __global__ __launch_bounds__(kT) void k_bspmv_win(Batch b, const double *__restr
                 const int64_t mid = (lo + hi) / 2;
                 if (d.esc_rows[mid] <= lrow) lo = mid; else hi = mid;
             }
-            q0 = 0.0;
-            q1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) qv[q] = 0.0;
             for (int64_t e = d.esc_ptr[lo]; e < d.esc_ptr[lo + 1]; ++e) {
-                const double2 xv =
-                    *reinterpret_cast<const double2 *>(sysP + in_bounds<int64_t>(d.esc_col[e], d.n) * NR + rp);
-                q0 = fma(d.esc_val[e], xv.x, q0);
-                q1 = fma(d.esc_val[e], xv.y, q1);
+                const double *xe = sysP + in_bounds<int64_t>(d.esc_col[e], d.n) * NR + rp;
+#pragma unroll
+                for (int h = 0; h < Q / 2; ++h) {
+                    const double2 xv = *reinterpret_cast<const double2 *>(xe + 2 * h);
+                    qv[2 * h] = fma(d.esc_val[e], xv.x, qv[2 * h]);
+                    qv[2 * h + 1] = fma(d.esc_val[e], xv.y, qv[2 * h + 1]);
+                }
             }
         }
         if (lane_on) {
             const int64_t gi = (d.row0 + lrow) * NR + rp;
-            *reinterpret_cast<double2 *>(Qout + gi) = double2{q0, q1};
-            if (with_dot) {
-                const double2 pv = *reinterpret_cast<const double2 *>(Pin + gi);
-                dotc[0] += pv.x * q0;
-                dotc[1] += pv.y * q1;
+#pragma unroll
+            for (int h = 0; h < Q / 2; ++h) {
+                *reinterpret_cast<double2 *>(Qout + gi + 2 * h) = double2{qv[2 * h], qv[2 * h + 1]};
+                if (with_dot) {
+                    const double2 pv = *reinterpret_cast<const double2 *>(Pin + gi + 2 * h);
+                    dotc[2 * h] += pv.x * qv[2 * h];
+                    dotc[2 * h + 1] += pv.y * qv[2 * h + 1];
+                }
             }
         }
     }
     if (!with_dot) return;
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < Q; ++v) {
         const double t = rhs_sum<LPR>(dotc[v]);
-        const int rr = static_cast<int>(threadIdx.x) * 2 + v;
+        const int rr = static_cast<int>(threadIdx.x) * Q + v;
         if (threadIdx.x < LPR && rr < b.nrhs) part[static_cast<int64_t>(tile) * b.nrhs + rr] = t;
     }
 }
@@ -792,10 +806,15 @@ void launch_bspmv(const Batch &b, const double *Pin, double *Qout, int with_dot,
     const unsigned g = static_cast<unsigned>(b.n_tiles);
     if (b.spmv_form == 0 && b.win_x_bytes > 0) {
         const size_t wsh = static_cast<size_t>(b.win_x_bytes) + static_cast<size_t>(b.win_tab_bytes);
+        // four right-hand sides per lane when every system's records are split
         if (b.nrhs == 2)
             k_bspmv_win<1><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
+        else if (b.nrhs == 4 && b.all_split)
+            k_bspmv_win<1, 4><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
         else if (b.nrhs == 4)
             k_bspmv_win<2><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
+        else if (b.all_split)
+            k_bspmv_win<2, 4><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
         else
             k_bspmv_win<4><<<g, kT, wsh, s>>>(b, Pin, Qout, b.part, with_dot);
         return;
@@ -1012,6 +1031,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
     // is 2, 4 or 8 and the largest window and table fit the LDS budget
     b.win_x_bytes = 0;
     b.win_tab_bytes = 0;
+    b.all_split = 1;
     bool win_ok = nrhs == 2 || nrhs == 4 || nrhs == 8;
     for (int q = 0; q < n_sys && win_ok; ++q) {
         const LdsPlan &pl = A[q]->plan[SPMVC_F64];
@@ -1020,6 +1040,7 @@ spmvc_status cg_solve_batched(const spmvc_matrix *A, int n_sys, int nrhs, const 
             win_ok = false;
             break;
         }
+        if (!pl.bw_split) b.all_split = 0;
         b.win_x_bytes = std::max<int32_t>(b.win_x_bytes, pl.bw_maxlen * nrhs * 8);
         b.win_tab_bytes = std::max<int32_t>(b.win_tab_bytes, A[q]->P * pl.bw_nw * kWinSt * 4);
     }

@@ -1114,18 +1114,20 @@ __device__ __forceinline__ void win_row(const uint4 *rec, const unsigned char *x
     }
 }
 
-// nrhs = 2 * LPR FP64 right-hand sides, row-interleaved and unpadded.  A block
+// nrhs = Q * LPR FP64 right-hand sides, row-interleaved and unpadded.  A block
 // owns kWinRows rows; for each x window in turn it copies the window's rows
-// of the block (all nrhs values of a row: 16 * LPR bytes, a contiguous range
+// of the block (all nrhs values of a row: 8 * nrhs bytes, a contiguous range
 // of memory) into LDS, then every row adds the products of its entries that
 // fall in that window (win_row).  Only one window is held at a time, so whole
-// rows fit.  A group of LPR lanes serves a row, each lane a pair of
-// right-hand sides (16-byte LDS reads).
-template <int LPR>
+// rows fit.  A group of LPR lanes serves a row, each lane Q consecutive
+// right-hand sides (16-byte LDS reads): Q = 2, or Q = 4 with split records,
+// where each record read and loop set-up then serves twice the right-hand
+// sides (the record handling, not the sums, is most of the kernel's VALU work).
+template <int LPR, int Q = 2>
 __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const double *__restrict__ X,
                                                            double *__restrict__ Y) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NR = 2 * LPR;          // right-hand sides
+    constexpr int NR = Q * LPR;          // right-hand sides
     constexpr int PASSES = kWinRows / (kBlock / LPR);
     if (blockIdx.x >= a.n_main_blocks) {  // escape rows: one lane per row, all right-hand sides, from global memory
         escape_row<double, NR>(a, static_cast<int64_t>(blockIdx.x - a.n_main_blocks) * kBlock + threadIdx.x, NR, X, NR,
@@ -1138,7 +1140,7 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
     const int64_t r0 = xcd_tile(blockIdx.x, a.n_main_blocks, a.n_xcd) * kWinRows;
     const uint32_t esc = a.id_bytes == 1 ? 0xFFu : (a.id_bytes == 2 ? 0xFFFFu : 0xFFFFFFFFu);
     const int lr = threadIdx.x / LPR;           // row within a pass
-    const int rp = (threadIdx.x % LPR) * 2;     // this lane's right-hand-side pair
+    const int rp = (threadIdx.x % LPR) * Q;     // this lane's first right-hand side
     uint32_t idv[PASSES];
     int t0v[PASSES];
 #pragma unroll
@@ -1155,9 +1157,11 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
         for (int e = threadIdx.x; e < n16; e += kBlock) dst[e] = src[e];
     }
     const double v0 = a.V[0], v1 = a.V[a.K >= 2 ? 1 : 0];
-    double acc[PASSES][2];
+    double acc[PASSES][Q];
 #pragma unroll
-    for (int ps = 0; ps < PASSES; ++ps) acc[ps][0] = acc[ps][1] = 0.0;
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[ps][q] = 0.0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int w = 0; w < NW; ++w) {
         if (w > 0) __syncthreads();  // every row is done with the previous window
@@ -1189,18 +1193,23 @@ __global__ __launch_bounds__(kBlock) void k_dit_block_win(SpmvArgs a, const doub
             const uint4 *rec = tab_s + (static_cast<int64_t>(idv[ps]) * NW + w) * (kWinSt / 4);
             const unsigned char *xrow = reinterpret_cast<const unsigned char *>(xs + rel * NR + rp);
             const uint32_t lim = static_cast<uint32_t>(a.win_len[w] - rel);  // window rows from this row on
-            if (a.bw_split)
-                win_row_split<NR * 8>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps][0],
-                                      acc[ps][1]);
-            else
-                win_row<NR * 8>(rec, xrow, lim, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
+            if constexpr (Q == 4) {  // launched only with split records
+                win_row_split<NR * 8, Q>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps]);
+            } else {
+                if (a.bw_split)
+                    win_row_split<NR * 8, Q>(reinterpret_cast<const uint32_t *>(rec), xrow, lim, v0, v1, acc[ps]);
+                else
+                    win_row<NR * 8>(rec, xrow, lim, t0v[ps], v0, v1, acc[ps][0], acc[ps][1]);
+            }
         }
     }
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
         const int64_t row = r0 + ps * (kBlock / LPR) + lr;
         if (row >= a.n_rows || idv[ps] == esc) continue;
-        *reinterpret_cast<double2 *>(Y + row * NR + rp) = double2{acc[ps][0], acc[ps][1]};
+#pragma unroll
+        for (int h = 0; h < Q / 2; ++h)
+            *reinterpret_cast<double2 *>(Y + row * NR + rp + 2 * h) = double2{acc[ps][2 * h], acc[ps][2 * h + 1]};
     }
 }
 
@@ -1498,10 +1507,15 @@ bool launch_block_win(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     const unsigned grid = a.n_main_blocks + escape_blocks(M);
     const double *xp = static_cast<const double *>(X);
     double *yp = static_cast<double *>(Y);
+    // with split records a lane takes four right-hand sides (nrhs 4 and 8)
     if (nrhs == 2)
         k_dit_block_win<1><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+    else if (nrhs == 4 && p.bw_split)
+        k_dit_block_win<1, 4><<<grid, kBlock, shmem, s>>>(a, xp, yp);
     else if (nrhs == 4)
         k_dit_block_win<2><<<grid, kBlock, shmem, s>>>(a, xp, yp);
+    else if (p.bw_split)
+        k_dit_block_win<2, 4><<<grid, kBlock, shmem, s>>>(a, xp, yp);
     else
         k_dit_block_win<4><<<grid, kBlock, shmem, s>>>(a, xp, yp);
     SPMVC_CHECK_LAUNCH();
