@@ -18,6 +18,13 @@ constexpr int kMaxPatternLen = 255; // T and positions are one byte
 constexpr int kSlice = 64;          // rows per raw-value slice (one wavefront)
 constexpr int kMaxWindows = 8;      // x windows staged in LDS per block
 constexpr int kLdsBudgetBytes = 64 * 1024;
+// Register tiles above which an SpMV with the dot product (CG) takes the
+// marching form of its plan, where it has one (each block leaves a partial that
+// every block of the next kernel sums): measured at 192^3, FP64 CG 36.2 ms with
+// 13,824 register tiles of 512 rows, 35.2 ms with the marching form's 1,009
+// blocks; at 104^3 the 1,465 tiles of 768 rows are the faster choice.  The
+// autotuner avoids configurations past it that have no marching form.
+constexpr int64_t kDotMaxTiles = 8192;
 constexpr int kBlock = 256;         // threads per block of the SpMV kernels
 constexpr int32_t kEscapeColumn = -2; // ELL/DT slot-0 marker of an escape row (padding is -1)
 

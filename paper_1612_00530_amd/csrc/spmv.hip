@@ -1303,12 +1303,6 @@ void launch_direct_nr(const spmvc_matrix_s *M, SpmvArgs a, int nrhs, const void 
     SPMVC_CHECK_LAUNCH();
 }
 
-// Register tiles above which a launch with the dot product takes the marching
-// form (where the plan has one): measured at 192^3, FP64 CG 36.2 ms with
-// 13,824 register tiles of 512 rows, 35.2 ms with the marching form's 1,009
-// blocks; at 104^3 the 1,465 tiles of 768 rows are the faster choice.
-constexpr int64_t kDotMaxTiles = 8192;
-
 // Which register-kernel variant fits the matrix: 0 = none, else KK + 1.
 int reg_variant(const spmvc_matrix_s *M, int dt) {
     const LdsPlan &p = M->plan[dt];

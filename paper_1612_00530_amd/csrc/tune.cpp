@@ -134,6 +134,12 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
         SPMVC_HIP(hipEventCreate(&e1));
         double best = 1e300;
         Cand win = cands.front();
+        struct Timed {
+            Cand c;
+            double us;
+            bool cg_ok;  // inside CG (with the dot product) it stays under kDotMaxTiles partials
+        };
+        std::vector<Timed> timed;
         for (const Cand &c : cands) {
             if (nrhs > 1) {
                 A->block_mode[dt] = c.lds;
@@ -166,11 +172,32 @@ extern "C" spmvc_status spmv_tune(spmvc_matrix A, int32_t dt, int32_t nrhs, void
             }
             std::sort(ts.begin(), ts.end());
             const double us = 1000.0 * ts[ts.size() / 2];
+            // blocks (dot partials) of the launch: register tiles (LDS windows) or
+            // one row per thread (direct gather); the marching form has few
+            const int64_t tiles = c.lds == 1 ? (A->n_rows + c.rows - 1) / c.rows
+                                             : (c.lds == 0 ? (A->n_pad + kBlock - 1) / kBlock : 0);
+            const bool many = nrhs == 1 && tiles > kDotMaxTiles;
+            timed.push_back({c, us, !many || (c.lds == 1 && A->plan[dt].march)});
             if (us < best) {
                 best = us;
                 win = c;
             }
         }
+        // The configuration also serves CG's SpMV with the dot product: a winner
+        // that would leave more than kDotMaxTiles partials there, with no
+        // marching form to fall back on, yields to the fastest candidate within
+        // 3 % that CG can use well.
+        for (const Timed &t : timed)
+            if (t.c.rows == win.rows && t.c.lds == win.lds && !t.cg_ok) {
+                double alt = 1e300;
+                for (const Timed &u : timed)
+                    if (u.cg_ok && u.us <= 1.03 * best && u.us < alt) {
+                        alt = u.us;
+                        win = u.c;
+                    }
+                if (alt < 1e300) best = alt;
+                break;
+            }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (nrhs > 1) {
