@@ -138,8 +138,7 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
 }
 
 // rho0 = rho[0] = sum of the partials; state reset (one block)
-__global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, int np, CgScal *st, double rtol,
-                                                      int max_iter) {
+__device__ __forceinline__ void cg_start_fin(const double *partials, int np, CgScal *st, double rtol, int max_iter) {
     const double tot = sum_partials<kRT>(partials, np);
     if (threadIdx.x != 0) return;
     st->rho[0] = tot;
@@ -156,6 +155,11 @@ __global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, in
         st->done = 1;
         st->status = SPMVC_EINVAL;
     }
+}
+
+__global__ __launch_bounds__(kRT) void k_cg_start_fin(const double *partials, int np, CgScal *st, double rtol,
+                                                      int max_iter) {
+    cg_start_fin(partials, np, st, rtol, max_iter);
 }
 
 // Restart of a finished solve whose recursive residual met the tolerance but
@@ -556,13 +560,70 @@ __global__ __launch_bounds__(kRT) void k_residual_fin(const double *rr_part, con
     }
 }
 
+// Scalars of the reliable-update solve that pass from one segment to the next
+// on the device, so that the host can queue the FP64 replacement and the next
+// segment without first reading the residual back.
+struct RelState {
+    double sn;       // the current segment's scale: ||b - A x|| at its start
+    double beta;     // factor taking p into the units of sn (0: p = r)
+    double seg_tol;  // the segment's tolerance, relative to its start
+    double bnorm;    // ||b||
+    int32_t fin;     // 0 while segments run; 1 converged, 2 out of iterations or replacements, 3 breakdown
+};
+constexpr int32_t kRelOk = 1, kRelNoConv = 2, kRelBreakdown = 3;
+
+// the first segment's scalars, computed by the host from the first residual
+__global__ void k_rel_first(RelState *rs, double sn, double seg_tol, double bnorm) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *rs = RelState{sn, 0.0, seg_tol, bnorm, 0};
+}
+
+// After a segment and the FP64 replacement r = b - A x (||r||^2 in aux[0]):
+// the stopping tests, then the next segment's scale sn' = ||r||, the factor
+// beta = sn' / (sn rho_k) that takes p into the new units (rho_k: the
+// segment's r.r before its last step, in units of sn) and its tolerance,
+// inner_rtol, raised so that the segment does not go past the final target
+// (0.9 rtol / rel) and capped at 0.5.  On a stop, fin records why and the
+// solve is marked done, so that the segment kernels queued behind do nothing.
+// aux[2] = fin and aux[3] = the finished segment's recursive residual over
+// ||b|| go back to the host with the scalars it reads next.
+__global__ void k_rel_next(CgScal *st, RelState *rs, double rtol, double inner_rtol, int segs, int total,
+                           int max_outer, int max_iter, double rho_k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double rr = st->aux[0];
+    const double rel = sqrt(rr) / rs->bnorm;
+    const double sn_old = rs->sn;
+    st->aux[3] = st->rel * sn_old / rs->bnorm;
+    int32_t fin = 0;
+    if (!isfinite(rel))
+        fin = kRelBreakdown;
+    else if (rel <= rtol)
+        fin = kRelOk;
+    else if (segs > max_outer || total >= max_iter)
+        fin = kRelNoConv;
+    rs->fin = fin;
+    st->aux[2] = static_cast<double>(fin);
+    if (fin) {
+        st->done = 1;
+        return;
+    }
+    const double sn = sqrt(rr);
+    rs->beta = rho_k > 0.0 ? sn / (sn_old * rho_k) : 0.0;
+    rs->sn = sn;
+    rs->seg_tol = fmin(fmax(inner_rtol, 0.9 * rtol / rel), 0.5);
+}
+
 // Start of a reliable-update segment: r = r64 / s (the FP64 true residual in
 // units of its norm s), p = r + beta p (beta = 0: p = r; otherwise p keeps the
-// previous segment's direction, rescaled into the new units by the caller's
-// beta), xl = 0; partials of r.r.
-__global__ __launch_bounds__(kRT) void k_rel_start(int64_t n, const double *__restrict__ r64, double s, float beta,
-                                                   float *__restrict__ xl, float *__restrict__ r,
-                                                   float *__restrict__ p, double *partials) {
+// previous segment's direction, rescaled into the new units by beta), xl = 0;
+// partials of r.r.  s and beta come from rs; nothing is done once the solve
+// has stopped.
+__global__ __launch_bounds__(kRT) void k_rel_start(int64_t n, const double *__restrict__ r64,
+                                                   const RelState *rs, float *__restrict__ xl,
+                                                   float *__restrict__ r, float *__restrict__ p,
+                                                   double *partials) {
+    if (rs->fin) return;
+    const double s = rs->sn;
+    const float beta = static_cast<float>(rs->beta);
     double acc = 0.0;
     const bool fresh = beta == 0.0f;
     SPMVC_STREAM4(
@@ -585,8 +646,23 @@ _Pragma("unroll") for (int u = 0; u < 4; ++u) {
     if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
+// the segment's reset of the CG scalars with its tolerance from rs (one block)
+__global__ __launch_bounds__(kRT) void k_rel_start_fin(const double *partials, int np, CgScal *st,
+                                                       const RelState *rs, int max_iter) {
+    if (rs->fin) return;
+    cg_start_fin(partials, np, st, rs->seg_tol, max_iter);
+}
+
 // x += scale * (double) d
 __global__ void k_add_f32(int64_t n, double *__restrict__ x, const float *__restrict__ d, double scale) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        x[i] += scale * static_cast<double>(d[i]);
+}
+
+// x += sn * (double) d with the segment's scale from rs
+__global__ void k_add_rel(int64_t n, double *__restrict__ x, const float *__restrict__ d, const RelState *rs) {
+    const double scale = rs->sn;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
         x[i] += scale * static_cast<double>(d[i]);
@@ -684,17 +760,26 @@ struct Solver {
     // geometrically, reach the tolerance within the chunk in flight, the next
     // chunk is queued only after that chunk's status has been read.  Without
     // events (the allocation-free solver) each read waits for the stream.
-    template <class F> void iterate_chunks(F &&launch_chunk) {
+    // Returns true with the scalars that showed the solve done in `out`;
+    // false when launch_chunk() ran out first (nothing read since).  A chunk
+    // queued past the end leaves these scalars as they were, so the caller
+    // can go on enqueuing without another read.
+    template <class F> bool iterate_chunks(F &&launch_chunk, CgScal &out) {
         if (!ev[0]) {
-            while (!read().done && launch_chunk()) {
+            while (true) {
+                const CgScal &h = read();
+                if (h.done) {
+                    out = h;
+                    return true;
+                }
+                if (!launch_chunk()) return false;
             }
-            return;
         }
         auto post = [&](int slot) {
             SPMVC_HIP(hipMemcpyAsync(pin->h + 1 + slot, dscal, sizeof(CgScal), hipMemcpyDeviceToHost, s));
             SPMVC_HIP(hipEventRecord(ev[slot], s));
         };
-        if (!launch_chunk()) return;
+        if (!launch_chunk()) return false;
         post(0);
         double rel_prev = -1.0, rel_last = -1.0;  // residuals read after the last two chunks
         for (int slot = 0;; slot ^= 1) {
@@ -707,12 +792,15 @@ struct Solver {
             }
             SPMVC_HIP(hipEventSynchronize(ev[slot]));
             const CgScal &h = pin->h[1 + slot];
-            if (h.done) return;
+            if (h.done) {
+                out = h;
+                return true;
+            }
             if (near_end) {
                 more = launch_chunk();
                 if (more) post(slot ^ 1);
             }
-            if (!more) return;
+            if (!more) return false;
             rel_prev = rel_last;
             rel_last = h.rel;
         }
@@ -732,7 +820,7 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
     const bool vec_u = aligned16(r, q), vec_p = aligned16(z, r, p);
     const int chunk = std::max(1, check_every);
     int it = it0;
-    sv.iterate_chunks([&]() -> bool {
+    auto chunk_fn = [&]() -> bool {
         if (it >= max_iter) return false;
         for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
             const int par = it & 1;
@@ -752,8 +840,9 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
         }
         SPMVC_CHECK_LAUNCH();
         return true;
-    });
-    CgScal out = sv.read();
+    };
+    CgScal out;
+    if (!sv.iterate_chunks(chunk_fn, out)) out = sv.read();
     if (!out.done) {
         out.done = 1;
         out.status = SPMVC_ENOCONV;
@@ -774,15 +863,22 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, RhsT rhs_nor
     return cg_iterate<Real>(M, sv, z, r, p, q, 0, max_iter, check_every);
 }
 
-// ||b - A x||^2 and ||b||^2 in FP64 (tmp: n doubles; r receives b - Ax when not null)
-void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp, double *r,
-              double &rr, double &bb) {
+// Queues ||b - A x||^2 -> aux[0] and ||b||^2 -> aux[1] in FP64 (tmp: n
+// doubles; r receives b - Ax when not null).
+void residual_enqueue(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp,
+                      double *r) {
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     launch_spmv(M, SPMVC_F64, x, tmp, sv.s);
     k_residual<<<g, kRT, 0, sv.s>>>(n, b, tmp, r, sv.pa, sv.pb);
     k_residual_fin<<<1, kRT, 0, sv.s>>>(sv.pa, sv.pb, static_cast<int>(g), sv.st());
     SPMVC_CHECK_LAUNCH();
+}
+
+// ||b - A x||^2 and ||b||^2 in FP64, read back
+void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp, double *r,
+              double &rr, double &bb) {
+    residual_enqueue(M, sv, b, x, tmp, r);
     const CgScal &h = sv.read();
     rr = h.aux[0];
     bb = h.aux[1];
@@ -922,7 +1018,7 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
         k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), it & 1);
         SPMVC_CHECK_LAUNCH();
         const int chunk = std::max(1, o.check_every);
-        sv.iterate_chunks([&]() -> bool {
+        auto chunk_fn = [&]() -> bool {
             if (it >= o.max_iter) return false;
             for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
                 const int par = it & 1;
@@ -936,8 +1032,9 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
             }
             SPMVC_CHECK_LAUNCH();
             return true;
-        });
-        CgScal h = sv.read();
+        };
+        CgScal h;
+        if (!sv.iterate_chunks(chunk_fn, h)) h = sv.read();
         if (!h.done) {
             h.done = 1;
             h.status = SPMVC_ENOCONV;
@@ -1097,25 +1194,31 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
 // that residual but keeps the search direction p (rescaled to the new units,
 // with beta = ||r_new||^2 / ||r_k||^2), so the Krylov space is not thrown away
 // as at a refinement restart.  Stops when the true FP64 residual meets rtol.
+// Between segments the scale, beta, the tolerance and the stopping tests are
+// computed on the device (k_rel_next): the host reads the scalars once per
+// segment, when the chunk reads show it done, and then queues the replacement
+// and the next segment at once; the replacement's residual is never read
+// back on its own.
 spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
                             spmvc_cg_stat &stat, hipStream_t s) {
     const int64_t n = M->n_rows;
     const int64_t nn = std::max<int64_t>(n, 1);
     const unsigned g = rgrid(n);
     Solver sv(s, spmv_dot_blocks(M));
-    DevBuf r64, q64, r32, p32, q32, xl32;
+    DevBuf r64, q64, r32, p32, q32, xl32, rsb;
     r64.alloc(sizeof(double) * nn);
     q64.alloc(sizeof(double) * nn);
     r32.alloc(sizeof(float) * nn);
     p32.alloc(sizeof(float) * nn);
     q32.alloc(sizeof(float) * nn);
     xl32.alloc(sizeof(float) * nn);
+    rsb.alloc(sizeof(RelState));
+    RelState *rs = rsb.as<RelState>();
     SPMVC_HIP(hipMemsetAsync(x, 0, sizeof(double) * nn, s));
     double rr, bb;
     residual(M, sv, b, x, q64.as<double>(), r64.as<double>(), rr, bb);
     const double bnorm = std::sqrt(bb);
     int total = 0, segs = 0;
-    spmvc_status st = SPMVC_ENOCONV;
     if (!std::isfinite(bb) || !std::isfinite(rr)) {  // NaN or Inf in b
         stat = spmvc_cg_stat{};
         stat.status = SPMVC_EINVAL;
@@ -1123,39 +1226,41 @@ spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x,
         return SPMVC_EINVAL;
     }
     double rel = bnorm > 0.0 ? std::sqrt(rr) / bnorm : 0.0, rel_rec = rel;
-    double s_prev = 0.0, rho_k = 0.0;  // the last segment's scale and r.r before its last step
-    while (true) {
-        if (rel <= o.rtol) {
-            st = SPMVC_OK;
-            break;
-        }
-        if (segs > o.max_outer || total >= o.max_iter) break;
-        const double sn = std::sqrt(rr);
-        // ||R_true||^2 / ||R_k||^2 with R_k = s_prev r_k, and p into units of sn
-        const double beta = (segs == 0 || !(rho_k > 0.0)) ? 0.0 : sn / (s_prev * rho_k);
-        const double seg_tol = std::min(std::max(o.inner_rtol, 0.9 * o.rtol / rel), 0.5);
-        k_rel_start<<<g, kRT, 0, s>>>(n, r64.as<double>(), sn, static_cast<float>(beta), xl32.as<float>(),
-                                      r32.as<float>(), p32.as<float>(), sv.pa);
-        k_cg_start_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), seg_tol, o.max_iter - total);
-        SPMVC_CHECK_LAUNCH();
-        const CgScal h = cg_iterate<float>(M, sv, xl32.as<float>(), r32.as<float>(), p32.as<float>(),
-                                           q32.as<float>(), 0, o.max_iter - total, o.check_every);
-        total += h.iters;
-        ++segs;
-        if (h.status == SPMVC_ENOTSPD || h.status == SPMVC_EINVAL) {
-            st = static_cast<spmvc_status>(h.status);
-            break;
-        }
-        rel_rec = h.rel * sn / bnorm;
-        rho_k = h.iters > 0 ? h.rho[(h.iters - 1) & 1] : 0.0;
-        s_prev = sn;
-        k_add_f32<<<rgrid(n), kRT, 0, s>>>(n, x, xl32.as<float>(), sn);
-        SPMVC_CHECK_LAUNCH();
-        residual(M, sv, b, x, q64.as<double>(), r64.as<double>(), rr, bb);
-        rel = std::sqrt(rr) / bnorm;
-        if (!std::isfinite(rel)) {
-            st = SPMVC_ENOTSPD;
-            break;
+    spmvc_status st = SPMVC_ENOCONV;
+    if (rel <= o.rtol) {
+        st = SPMVC_OK;
+    } else if (o.max_outer >= 0 && o.max_iter > 0) {
+        k_rel_first<<<1, 64, 0, s>>>(rs, std::sqrt(rr), std::min(std::max(o.inner_rtol, 0.9 * o.rtol / rel), 0.5),
+                                     bnorm);
+        while (true) {
+            k_rel_start<<<g, kRT, 0, s>>>(n, r64.as<double>(), rs, xl32.as<float>(), r32.as<float>(),
+                                          p32.as<float>(), sv.pa);
+            k_rel_start_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), rs, o.max_iter - total);
+            SPMVC_CHECK_LAUNCH();
+            const CgScal h = cg_iterate<float>(M, sv, xl32.as<float>(), r32.as<float>(), p32.as<float>(),
+                                               q32.as<float>(), 0, o.max_iter - total, o.check_every);
+            if (segs > 0) {  // the values k_rel_next left after the last replacement
+                rel = std::sqrt(h.aux[0]) / bnorm;
+                rel_rec = h.aux[3];
+            }
+            if (h.aux[2] != 0.0) {  // k_rel_next stopped the solve; h still holds the last segment's scalars
+                const int fin = static_cast<int>(h.aux[2]);
+                st = fin == kRelOk ? SPMVC_OK : fin == kRelBreakdown ? SPMVC_ENOTSPD : SPMVC_ENOCONV;
+                break;
+            }
+            total += h.iters;
+            ++segs;
+            if (h.status == SPMVC_ENOTSPD || h.status == SPMVC_EINVAL) {
+                st = static_cast<spmvc_status>(h.status);
+                break;
+            }
+            k_add_rel<<<rgrid(n), kRT, 0, s>>>(n, x, xl32.as<float>(), rs);
+            SPMVC_CHECK_LAUNCH();
+            residual_enqueue(M, sv, b, x, q64.as<double>(), r64.as<double>());
+            const double rho_k = h.iters > 0 ? h.rho[(h.iters - 1) & 1] : 0.0;
+            k_rel_next<<<1, 64, 0, s>>>(sv.st(), rs, o.rtol, o.inner_rtol, segs, total, o.max_outer, o.max_iter,
+                                        rho_k);
+            SPMVC_CHECK_LAUNCH();
         }
     }
     stat.iters = total;
