@@ -220,6 +220,30 @@ def test_reliable_updates_failures():
     assert st == -1
 
 
+def test_reliable_updates_replacement_cap():
+    """max_outer caps the replacements (decided on the device between
+    segments): with max_outer = k the solve stops with SPMVC_ENOCONV after
+    k + 1 segments; the reported true residual is the oracle's residual of
+    the returned x, the recursive one that of the last segment (close to it),
+    and both fall as k grows."""
+    say("case: reliable updates replacement cap")
+    A = stencil27(24, 20, 16)
+    b = oracle.spmv(A, np.ones(A.n_cols))
+    prev_rel, prev_iters = np.inf, 0
+    for k in (0, 1, 2):
+        st, x, stats = solve(A, b, mode=3, inner_rtol=1e-2, max_outer=k)
+        s = stats[0]
+        say("  ", k, s)
+        rel = oracle.relres(A, b, x)
+        assert st == -7 and s["status"] == -7 and s["outer_iters"] == k + 1
+        assert rel > 1e-10 and rel < prev_rel and s["iters"] > prev_iters
+        assert abs(s["relres_true"] - rel) <= 1e-12
+        assert 0.5 * rel <= s["relres_recursive"] <= 2.0 * rel
+        prev_rel, prev_iters = rel, s["iters"]
+    st, x, stats = solve(A, b, mode=3, inner_rtol=1e-2)
+    assert st == 0 and stats[0]["outer_iters"] >= 3 and oracle.relres(A, b, x) <= 1e-10
+
+
 @pytest.mark.parametrize("scale", [1e-36, 1e39])
 def test_mixed_precision_scaled_rhs(scale):
     """b = scale * A*1 with scale outside the FP32 range of the residual
