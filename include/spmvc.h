@@ -152,7 +152,8 @@ typedef struct {
     double inner_rtol;   /* MIXED: inner FP32 solve tolerance relative to ||r||, 1e-5;     */
                          /* RELIABLE: fall of the recursive residual between replacements */
     int32_t max_outer;   /* MIXED: refinement steps cap; RELIABLE: replacements cap; 20   */
-    int32_t check_every; /* iterations between host convergence checks, default 16         */
+    int32_t check_every; /* iterations between host convergence checks, default 16 (PCG  */
+                         /* and MG: check_every / 4, at least 1)                          */
     int32_t batched;     /* several systems or right-hand sides (FP64 mode): 0 = one solve  */
                          /* after another, 1 = all pairs advanced together by batched       */
                          /* kernels, 2 = the same with check_every iterations recorded once */

@@ -750,21 +750,25 @@ struct Solver {
         SPMVC_HIP(hipStreamSynchronize(s));
         return *h;
     }
-    // Enqueues chunks of iterations (launch_chunk() returns false when there
-    // is nothing left to enqueue) until the solve reports done.  The host reads
-    // the scalars after chunk k while chunk k + 1 is already queued, so the
-    // device does not idle during the read; a chunk queued after the solve
-    // finished runs as no-ops (every kernel of an iteration returns at once
-    // when `done` is set, but each launch still costs a few microseconds).
-    // So when the residuals read after the last two chunks, continued
-    // geometrically, reach the tolerance within the chunk in flight, the next
-    // chunk is queued only after that chunk's status has been read.  Without
+    // Enqueues chunks of at most `full` iterations (launch_chunk(n) queues up
+    // to n and returns how many it queued, 0 when there is nothing left) until
+    // the solve reports done.  The host reads the scalars after chunk k while
+    // chunk k + 1 is already queued, so the device does not idle during the
+    // read; iterations queued after the solve finished run as no-ops (every
+    // kernel of an iteration returns at once when `done` is set, but each
+    // launch still costs a few microseconds, and a preconditioned iteration is
+    // dozens of launches).  So the residuals of the last two reads, continued
+    // geometrically, predict how many iterations are still needed: when they
+    // are fewer than the chunk in flight, the next chunk is queued only after
+    // that chunk's status has been read, and when they end within the next
+    // chunk, that chunk is cut to the prediction plus a margin.  Without
     // events (the allocation-free solver) each read waits for the stream.
     // Returns true with the scalars that showed the solve done in `out`;
     // false when launch_chunk() ran out first (nothing read since).  A chunk
     // queued past the end leaves these scalars as they were, so the caller
     // can go on enqueuing without another read.
-    template <class F> bool iterate_chunks(F &&launch_chunk, CgScal &out) {
+    template <class F> bool iterate_chunks(int full, F &&launch_chunk, CgScal &out) {
+        full = std::max(1, full);
         if (!ev[0]) {
             while (true) {
                 const CgScal &h = read();
@@ -772,23 +776,40 @@ struct Solver {
                     out = h;
                     return true;
                 }
-                if (!launch_chunk()) return false;
+                if (!launch_chunk(full)) return false;
             }
         }
         auto post = [&](int slot) {
             SPMVC_HIP(hipMemcpyAsync(pin->h + 1 + slot, dscal, sizeof(CgScal), hipMemcpyDeviceToHost, s));
             SPMVC_HIP(hipEventRecord(ev[slot], s));
         };
-        if (!launch_chunk()) return false;
+        int len[2] = {0, 0};  // iterations of the chunk posted to each slot
+        len[0] = launch_chunk(full);
+        if (!len[0]) return false;
         post(0);
-        double rel_prev = -1.0, rel_last = -1.0;  // residuals read after the last two chunks
+        double rel_prev = -1.0, rel_last = -1.0, tol = 0.0;  // the last two reads
+        int it_prev = 0, it_last = 0;
+        // iterations still needed after the last read (infinite when unknown)
+        auto need = [&]() -> double {
+            if (!(rel_prev > 0.0 && rel_last > 0.0 && rel_last < rel_prev && it_last > it_prev && tol > 0.0))
+                return HUGE_VAL;
+            return std::log(tol / rel_last) / std::log(rel_last / rel_prev) * (it_last - it_prev);
+        };
+        // length of the next chunk when `ahead` iterations are queued past the last read
+        auto next_len = [&](int ahead) -> int {
+            const double left = need() - ahead;
+            if (!(left < full)) return full;
+            return std::min(full, std::max(1, static_cast<int>(std::ceil(1.25 * left)) + 1));
+        };
         for (int slot = 0;; slot ^= 1) {
-            const bool near_end = rel_prev > 0.0 && rel_last > 0.0 && rel_last < rel_prev &&
-                                  rel_last * (rel_last / rel_prev) <= pin->h[1 + (slot ^ 1)].rtol;
-            bool more = false;
+            const bool near_end = need() <= len[slot];
+            int n = 0;
             if (!near_end) {
-                more = launch_chunk();
-                if (more) post(slot ^ 1);
+                n = launch_chunk(next_len(len[slot]));
+                if (n) {
+                    len[slot ^ 1] = n;
+                    post(slot ^ 1);
+                }
             }
             SPMVC_HIP(hipEventSynchronize(ev[slot]));
             const CgScal &h = pin->h[1 + slot];
@@ -796,13 +817,19 @@ struct Solver {
                 out = h;
                 return true;
             }
-            if (near_end) {
-                more = launch_chunk();
-                if (more) post(slot ^ 1);
-            }
-            if (!more) return false;
             rel_prev = rel_last;
+            it_prev = it_last;
             rel_last = h.rel;
+            it_last = h.iters;
+            tol = h.rtol;
+            if (near_end) {
+                n = launch_chunk(next_len(0));
+                if (n) {
+                    len[slot ^ 1] = n;
+                    post(slot ^ 1);
+                }
+            }
+            if (!n) return false;
         }
     }
 };
@@ -820,9 +847,9 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
     const bool vec_u = aligned16(r, q), vec_p = aligned16(z, r, p);
     const int chunk = std::max(1, check_every);
     int it = it0;
-    auto chunk_fn = [&]() -> bool {
-        if (it >= max_iter) return false;
-        for (int j = 0; j < chunk && it < max_iter; ++j, ++it) {
+    auto chunk_fn = [&](int want) -> int {
+        int j = 0;
+        for (; j < want && it < max_iter; ++j, ++it) {
             const int par = it & 1;
             const unsigned ns = launch_spmv_dot(M, dt, p, q, sv.s, &sv.st()->done, sv.psig);
             if (vec_u)
@@ -839,10 +866,10 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
                                                            sv.st(), par, it);
         }
         SPMVC_CHECK_LAUNCH();
-        return true;
+        return j;
     };
     CgScal out;
-    if (!sv.iterate_chunks(chunk_fn, out)) out = sv.read();
+    if (!sv.iterate_chunks(chunk, chunk_fn, out)) out = sv.read();
     if (!out.done) {
         out.done = 1;
         out.status = SPMVC_ENOCONV;
@@ -1017,10 +1044,14 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
         k_pcg_init<<<g, kRT, 0, s>>>(n, pr, pz, pp, sv.pa);
         k_pcg_init_fin<<<1, kRT, 0, s>>>(sv.pa, static_cast<int>(g), sv.st(), it & 1);
         SPMVC_CHECK_LAUNCH();
-        const int chunk = std::max(1, o.check_every);
-        auto chunk_fn = [&]() -> bool {
-            if (it >= o.max_iter) return false;
-            for (int j = 0; j < chunk && it < o.max_iter; ++j, ++it) {
+        // a preconditioned iteration is a sweep or a V-cycle, dozens of launches
+        // and several plain iterations' time: the status is read four times as
+        // often, which bounds the no-op iterations queued past convergence at
+        // little cost (a read is one small copy)
+        const int chunk = std::max(1, o.check_every / 4);
+        auto chunk_fn = [&](int want) -> int {
+            int j = 0;
+            for (; j < want && it < o.max_iter; ++j, ++it) {
                 const int par = it & 1;
                 const unsigned ns = launch_spmv_dot(M, SPMVC_F64, pp, pq, s, done, sv.psig);
                 k_pcg_update<<<g, kRT, 0, s>>>(n, x, pr, pp, pq, sv.psig, static_cast<int>(ns),
@@ -1031,10 +1062,10 @@ spmvc_status solve_pcg(spmvc_matrix_s *M, const double *b, double *x, const spmv
                 k_pcg_p<<<g, kRT, 0, s>>>(n, pz, pp, sv.pa, static_cast<int>(g), sv.st(), par);
             }
             SPMVC_CHECK_LAUNCH();
-            return true;
+            return j;
         };
         CgScal h;
-        if (!sv.iterate_chunks(chunk_fn, h)) h = sv.read();
+        if (!sv.iterate_chunks(chunk, chunk_fn, h)) h = sv.read();
         if (!h.done) {
             h.done = 1;
             h.status = SPMVC_ENOCONV;
