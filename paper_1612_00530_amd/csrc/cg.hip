@@ -1258,6 +1258,10 @@ spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x,
     }
     double rel = bnorm > 0.0 ? std::sqrt(rr) / bnorm : 0.0, rel_rec = rel;
     spmvc_status st = SPMVC_ENOCONV;
+    auto rel_status = [](double fin) {
+        const int f = static_cast<int>(fin);
+        return f == kRelOk ? SPMVC_OK : f == kRelBreakdown ? SPMVC_ENOTSPD : SPMVC_ENOCONV;
+    };
     if (rel <= o.rtol) {
         st = SPMVC_OK;
     } else if (o.max_outer >= 0 && o.max_iter > 0) {
@@ -1275,8 +1279,7 @@ spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x,
                 rel_rec = h.aux[3];
             }
             if (h.aux[2] != 0.0) {  // k_rel_next stopped the solve; h still holds the last segment's scalars
-                const int fin = static_cast<int>(h.aux[2]);
-                st = fin == kRelOk ? SPMVC_OK : fin == kRelBreakdown ? SPMVC_ENOTSPD : SPMVC_ENOCONV;
+                st = rel_status(h.aux[2]);
                 break;
             }
             total += h.iters;
@@ -1292,6 +1295,19 @@ spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x,
             k_rel_next<<<1, 64, 0, s>>>(sv.st(), rs, o.rtol, o.inner_rtol, segs, total, o.max_outer, o.max_iter,
                                         rho_k);
             SPMVC_CHECK_LAUNCH();
+            // when the segment's recursive residual, times the true one at its
+            // start (rel), comes within twice rtol, this is most likely the last
+            // segment: read k_rel_next's decision now rather than queue
+            // iterations that would run as no-ops
+            if (rel * h.rel <= 2.0 * o.rtol) {
+                const CgScal &c = sv.read();
+                if (c.aux[2] != 0.0) {
+                    rel = std::sqrt(c.aux[0]) / bnorm;
+                    rel_rec = c.aux[3];
+                    st = rel_status(c.aux[2]);
+                    break;
+                }
+            }
         }
     }
     stat.iters = total;
