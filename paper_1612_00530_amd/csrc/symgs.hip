@@ -301,38 +301,48 @@ bool gs_dit27(const spmvc_matrix_s *M) {
            M->P < 0xFFFFFF;
 }
 
-}  // namespace
+// Every row holds a non-zero diagonal entry (the last entry in column i
+// decides, as in the decompressed CSR); otherwise *bad = 1.
+__global__ void k_diag_check(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const double *__restrict__ val, int64_t n, int *bad) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ok = false;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (col[k] == i) ok = val[k] != 0.0;
+    if (!ok) *bad = 1;
+}
 
-// Greedy row-order coloring of the pattern of A + A^T, built once per handle;
-// also checks that every row holds a non-zero diagonal entry.
-void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
-    if (M->gs_ready) return;
-    if (M->n_rows != M->n_cols) throw Error{SPMVC_EINVAL, "Gauss-Seidel needs a square matrix"};
-    const int64_t n = M->n_rows, nnz = M->nnz;
-    std::vector<int64_t> rp(n + 1, 0);
-    std::vector<int32_t> col(nnz);
-    std::vector<double> val(nnz);
-    if (n > 0) {
-        DevBuf drp, dcol, dval;
-        drp.alloc(sizeof(int64_t) * (n + 1));
-        dcol.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
-        dval.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
-        decompress(M, drp.as<int64_t>(), dcol.as<int32_t>(), dval.as<double>(), s);
-        SPMVC_HIP(hipMemcpyAsync(rp.data(), drp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
-        if (nnz > 0) {
-            SPMVC_HIP(hipMemcpyAsync(col.data(), dcol.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
-            SPMVC_HIP(hipMemcpyAsync(val.data(), dval.p, sizeof(double) * nnz, hipMemcpyDeviceToHost, s));
-        }
-        SPMVC_HIP(hipStreamSynchronize(s));
-    }
+// Greedy colors in row order over the pattern of A + A^T: each row takes the
+// smallest color that no lower-numbered neighbour holds.  The neighbours
+// j < i through A^T are the rows j < i that hold column i; instead of building
+// A^T, each row, once colored, marks its color in a 64-bit mask of every
+// higher-numbered column it holds, so that row i finds the colors of both
+// kinds of neighbours in its own row and its mask.  Returns false (colors
+// unset) when some row would need a 65th color.
+bool greedy_colors_masks(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
+                         std::vector<int32_t> &color, int32_t &n_colors) {
+    std::vector<uint64_t> taken(n, 0);
+    n_colors = 0;
     for (int64_t i = 0; i < n; ++i) {
-        bool ok = false;
+        uint64_t m = taken[i];
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-            if (col[k] == i) ok = val[k] != 0.0;
-        if (!ok) throw Error{SPMVC_EINVAL, "Gauss-Seidel needs a non-zero diagonal entry in every row"};
+            if (col[k] < i) m |= 1ull << color[col[k]];
+        if (m == ~0ull) return false;
+        const int32_t c = __builtin_ctzll(~m);
+        color[i] = c;
+        n_colors = std::max(n_colors, c + 1);
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (col[k] > i) taken[col[k]] |= 1ull << c;
     }
-    // A^T's pattern: for each row, the rows that hold it as a column
-    std::vector<int64_t> tp(n + 1, 0);
+    return true;
+}
+
+// The same for any number of colors, through A^T's pattern.
+void greedy_colors_any(int64_t n, const std::vector<int64_t> &rp, const std::vector<int32_t> &col,
+                       std::vector<int32_t> &color, int32_t &n_colors) {
+    const int64_t nnz = rp[n];
+    std::vector<int64_t> tp(n + 1, 0);  // for each row, the rows that hold it as a column
     for (int64_t k = 0; k < nnz; ++k) ++tp[col[k] + 1];
     for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
     std::vector<int32_t> tr(nnz);
@@ -341,9 +351,8 @@ void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
         for (int64_t i = 0; i < n; ++i)
             for (int64_t k = rp[i]; k < rp[i + 1]; ++k) tr[fill[col[k]]++] = static_cast<int32_t>(i);
     }
-    std::vector<int32_t> color(n, -1);
     std::vector<int64_t> mark(32, -1);
-    int32_t n_colors = 0;
+    n_colors = 0;
     for (int64_t i = 0; i < n; ++i) {
         auto take = [&](int64_t j) {
             if (j < i) {
@@ -359,6 +368,43 @@ void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
         color[i] = c;
         n_colors = std::max(n_colors, c + 1);
     }
+}
+
+}  // namespace
+
+// Greedy row-order coloring of the pattern of A + A^T, built once per handle;
+// also checks (on the device) that every row holds a non-zero diagonal entry.
+// The greedy pass is a sequential recurrence over the rows (each row's color
+// depends on its lower-numbered neighbours' colors), so it runs on the host
+// over the decompressed pattern; only row pointers and columns come back.
+void build_coloring(spmvc_matrix_s *M, hipStream_t s) {
+    if (M->gs_ready) return;
+    if (M->n_rows != M->n_cols) throw Error{SPMVC_EINVAL, "Gauss-Seidel needs a square matrix"};
+    const int64_t n = M->n_rows, nnz = M->nnz;
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> col(nnz);
+    if (n > 0) {
+        DevBuf drp, dcol, dval, dbad;
+        drp.alloc(sizeof(int64_t) * (n + 1));
+        dcol.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+        dval.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+        dbad.alloc(sizeof(int));
+        decompress(M, drp.as<int64_t>(), dcol.as<int32_t>(), dval.as<double>(), s);
+        SPMVC_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), s));
+        k_diag_check<<<grid_for(n, 256, 0x7fffffff), 256, 0, s>>>(drp.as<int64_t>(), dcol.as<int32_t>(),
+                                                                  dval.as<double>(), n, dbad.as<int>());
+        SPMVC_CHECK_LAUNCH();
+        int bad = 0;
+        SPMVC_HIP(hipMemcpyAsync(&bad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPMVC_HIP(hipMemcpyAsync(rp.data(), drp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        if (nnz > 0)
+            SPMVC_HIP(hipMemcpyAsync(col.data(), dcol.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+        SPMVC_HIP(hipStreamSynchronize(s));
+        if (bad) throw Error{SPMVC_EINVAL, "Gauss-Seidel needs a non-zero diagonal entry in every row"};
+    }
+    std::vector<int32_t> color(n, 0);
+    int32_t n_colors = 0;
+    if (!greedy_colors_masks(n, rp, col, color, n_colors)) greedy_colors_any(n, rp, col, color, n_colors);
     // rows of each color, ascending
     M->gs_off.assign(n_colors + 1, 0);
     for (int64_t i = 0; i < n; ++i) ++M->gs_off[color[i] + 1];
