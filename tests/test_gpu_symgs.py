@@ -8,6 +8,8 @@
   a sweep chains 16 color steps of a diagonally dominant (contracting)
   iteration, so 1e-12 of the vectors' size leaves a wide margin;
 * DITV gives DIT's result bit for bit (same entries in the same order);
+* one-sided patterns (neighbours only through A^T) and more than 64 colors
+  (the coloring's general path) give the oracle's colors and sweeps;
 * bad inputs are rejected (non-square, zero diagonal, negative sweeps).
 """
 import sys
@@ -58,6 +60,56 @@ def test_coloring_equals_oracle(make):
     ref = gs.greedy_coloring(A)
     assert nc == int(ref.max()) + 1
     assert np.array_equal(col.cpu().numpy().astype(np.int64), ref)
+
+
+def _csr(n, rows):
+    """CSR from per-row {column: value} dicts (columns sorted)."""
+    rp, cols, vals = [0], [], []
+    for r in rows:
+        for j in sorted(r):
+            cols.append(j)
+            vals.append(r[j])
+        rp.append(len(cols))
+    return CSR(n, n, np.array(rp, dtype=np.int64), np.array(cols, dtype=np.int32), np.array(vals))
+
+
+def _asymmetric(n=400, block=0):
+    """Tridiagonal rows plus one-sided long-range entries (row i holds column
+    i + 5 + i % 11 for i % 3 == 0, not the reverse), so that some rows' only
+    lower-numbered neighbours come through A^T; with block = k, rows 100 ..
+    100 + k - 1 also form a fully coupled block, which needs k colors."""
+    rows = [dict() for _ in range(n)]
+    for i in range(n):
+        rows[i][i] = 4.0
+        for j in (i - 1, i + 1):
+            if 0 <= j < n:
+                rows[i][j] = -1.0
+        if i % 3 == 0 and i + 5 + i % 11 < n:
+            rows[i][i + 5 + i % 11] = -0.5
+    for i in range(100, 100 + block):
+        for j in range(100, 100 + block):
+            if j != i:
+                rows[i][j] = -1.0
+        rows[i][i] = 2.0 * block
+    return _csr(n, rows)
+
+
+@pytest.mark.parametrize("block,fmt", [(0, "DIT"), (0, "ELL"), (70, "ELL")])
+def test_coloring_asymmetric_and_over_64_colors(block, fmt):
+    """One-sided entries (neighbours only through A^T) and, with a fully
+    coupled block of 70 rows, more than 64 colors (the coloring then takes its
+    general path): the colors equal the oracle's greedy coloring and a sweep
+    equals the oracle's."""
+    say("case: symgs coloring asymmetric", block, fmt)
+    A = _asymmetric(block=block)
+    M = compress(A, fmt=fmt)
+    nc, col = M.colors()
+    ref = gs.greedy_coloring(A)
+    assert nc == int(ref.max()) + 1 and (nc >= 70 if block else nc < 64)
+    assert np.array_equal(col.cpu().numpy().astype(np.int64), ref)
+    b = uniform_vector(A.n_rows, seed=6)
+    x0 = uniform_vector(A.n_rows, seed=7)
+    assert close(run(M, b, x0, 1), gs.symgs(A, b, x0, ref, 1), b, x0)
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
