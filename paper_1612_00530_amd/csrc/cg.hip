@@ -1228,8 +1228,9 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
 // Between segments the scale, beta, the tolerance and the stopping tests are
 // computed on the device (k_rel_next): the host reads the scalars once per
 // segment, when the chunk reads show it done, and then queues the replacement
-// and the next segment at once; the replacement's residual is never read
-// back on its own.
+// and the next segment at once; the replacement's outcome is read on its own
+// only after a segment that most likely reached the target, so that no
+// iterations are queued past the stop.
 spmvc_status solve_reliable(const spmvc_matrix_s *M, const double *b, double *x, const spmvc_cg_opts &o,
                             spmvc_cg_stat &stat, hipStream_t s) {
     const int64_t n = M->n_rows;
