@@ -913,12 +913,6 @@ void residual(const spmvc_matrix_s *M, Solver &sv, const double *b, const double
 
 double ratio(double rr, double bb) { return bb > 0.0 ? std::sqrt(rr) / std::sqrt(bb) : std::sqrt(rr); }
 
-double true_relres(const spmvc_matrix_s *M, Solver &sv, const double *b, const double *x, double *tmp) {
-    double rr, bb;
-    residual(M, sv, b, x, tmp, nullptr, rr, bb);
-    return ratio(rr, bb);
-}
-
 // A solve that stopped on its recursive residual is accepted only when its
 // true FP64 residual ||b - A x|| / ||b|| meets the tolerance too; otherwise it
 // restarts from the true residual (at most this many times) and, if still
@@ -1208,11 +1202,13 @@ spmvc_status solve_mixed(const spmvc_matrix_s *M, const double *b, double *x, co
         k_add_f32<<<rgrid(n), kRT, 0, s>>>(n, x, d32.as<float>(), rnorm);
         SPMVC_CHECK_LAUNCH();
     }
+    // every exit follows the residual of the current x (or leaves x as it
+    // was then), so rel is already its true FP64 residual
     stat.iters = inner_total;
     stat.outer_iters = outer;
     stat.status = st;
     stat.relres_recursive = rel;
-    stat.relres_true = true_relres(M, sv, b, x, q64.as<double>());
+    stat.relres_true = rel;
     return st;
 }
 
