@@ -767,8 +767,11 @@ struct Solver {
     // false when launch_chunk() ran out first (nothing read since).  A chunk
     // queued past the end leaves these scalars as they were, so the caller
     // can go on enqueuing without another read.
-    template <class F> bool iterate_chunks(int full, F &&launch_chunk, CgScal &out) {
+    // A solve expected to take few iterations passes first > 0: the chunks
+    // queued before any read is back then hold `first` iterations each.
+    template <class F> bool iterate_chunks(int full, F &&launch_chunk, CgScal &out, int first = 0) {
         full = std::max(1, full);
+        const int blind = first > 0 ? std::min(first, full) : full;
         if (!ev[0]) {
             while (true) {
                 const CgScal &h = read();
@@ -784,7 +787,7 @@ struct Solver {
             SPMVC_HIP(hipEventRecord(ev[slot], s));
         };
         int len[2] = {0, 0};  // iterations of the chunk posted to each slot
-        len[0] = launch_chunk(full);
+        len[0] = launch_chunk(blind);
         if (!len[0]) return false;
         post(0);
         double rel_prev = -1.0, rel_last = -1.0, tol = 0.0;  // the last two reads
@@ -797,6 +800,7 @@ struct Solver {
         };
         // length of the next chunk when `ahead` iterations are queued past the last read
         auto next_len = [&](int ahead) -> int {
+            if (rel_last < 0.0) return blind;  // nothing read yet
             const double left = need() - ahead;
             if (!(left < full)) return full;
             return std::min(full, std::max(1, static_cast<int>(std::ceil(1.25 * left)) + 1));
@@ -839,7 +843,7 @@ static_assert(sizeof(CgScal) <= Solver::kSolverScalBytes, "scalar block of the s
 // stops or max_iter; returns the final scalars.
 template <class Real>
 CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p, Real *q, int it0, int max_iter,
-                  int check_every) {
+                  int check_every, int first = 0) {
     const int64_t n = M->n_rows;
     const unsigned g = rgrid(n);
     const int dt = std::is_same<Real, double>::value ? SPMVC_F64 : SPMVC_F32;
@@ -869,7 +873,7 @@ CgScal cg_iterate(const spmvc_matrix_s *M, Solver &sv, Real *z, Real *r, Real *p
         return j;
     };
     CgScal out;
-    if (!sv.iterate_chunks(chunk, chunk_fn, out)) out = sv.read();
+    if (!sv.iterate_chunks(chunk, chunk_fn, out, first)) out = sv.read();
     if (!out.done) {
         out.done = 1;
         out.status = SPMVC_ENOCONV;
@@ -887,7 +891,9 @@ CgScal run_cg(const spmvc_matrix_s *M, Solver &sv, const RhsT *rhs, RhsT rhs_nor
     k_cg_start<Real, RhsT><<<g, kRT, 0, sv.s>>>(n, rhs, rhs_norm, z, r, p, sv.pa);
     k_cg_start_fin<<<1, kRT, 0, sv.s>>>(sv.pa, static_cast<int>(g), sv.st(), rtol, max_iter);
     SPMVC_CHECK_LAUNCH();
-    return cg_iterate<Real>(M, sv, z, r, p, q, 0, max_iter, check_every);
+    // a loose tolerance (the last refinement steps) is met in a few
+    // iterations: start with short chunks rather than queue two full ones
+    return cg_iterate<Real>(M, sv, z, r, p, q, 0, max_iter, check_every, rtol >= 0.1 ? 2 : 0);
 }
 
 // Queues ||b - A x||^2 -> aux[0] and ||b||^2 -> aux[1] in FP64 (tmp: n
